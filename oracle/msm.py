@@ -1,0 +1,80 @@
+"""Multi-scalar multiplication and Pippenger's decomposition (test oracle).
+
+Test infrastructure: imported only by tests, the smoke check and the CPU
+baseline of the benchmark.
+
+MSM is the sum of scalar-point products sum_i s_i P_i over G1 (Abstract;
+Sec. II-C).  Pippenger's algorithm (Sec. II-C) cuts k-bit scalars into w-bit
+windows, giving k/w groups; inside each group the points go to buckets by
+their sliced scalar value and are summed (bucket accumulation); the buckets
+are then combined (bucket aggregation); and the groups are combined into the
+result (group aggregation).  Reading of the slicing: unsigned c-bit digits,
+digit 0 contributes nothing, the top window holds the remaining
+253 mod c bits.
+
+Everything here is the plain definition, on Weierstrass affine points, so the
+functions below are independent of the twisted-Edwards machinery in ``te``.
+"""
+
+from .curve import INF, G, add, smul
+from .field import R_ORDER
+
+SCALAR_BITS = 253
+
+
+def msm_naive(scalars, points):
+    """sum_i s_i P_i by independent double-and-add products."""
+    acc = INF
+    for s, pt in zip(scalars, points):
+        acc = add(acc, smul(s, pt))
+    return acc
+
+
+def num_windows(c, bits=SCALAR_BITS):
+    return -(-bits // c)
+
+
+def digit(s, w, c):
+    """The w-th c-bit slice of scalar s (window w covers bits [w c, w c + c))."""
+    return (s >> (w * c)) & ((1 << c) - 1)
+
+
+def buckets(scalars, points, c):
+    """B[w][b] = sum of P_i whose w-th digit equals b (bucket accumulation)."""
+    W = num_windows(c)
+    B = [[INF] * (1 << c) for _ in range(W)]
+    for s, pt in zip(scalars, points):
+        for w in range(W):
+            d = digit(s, w, c)
+            if d:
+                B[w][d] = add(B[w][d], pt)
+    return B
+
+
+def window_sum(bucket_row):
+    """S = sum_b b * B[b] (bucket aggregation, written as the definition)."""
+    acc = INF
+    for b, pt in enumerate(bucket_row):
+        if b and pt is not INF:
+            acc = add(acc, smul(b, pt))
+    return acc
+
+
+def group_aggregate(window_sums, c):
+    """Q = sum_w 2^(w c) S_w (group aggregation, written as the definition)."""
+    acc = INF
+    for w, s in enumerate(window_sums):
+        acc = add(acc, smul(1 << (w * c), s))
+    return acc
+
+
+def msm_pippenger(scalars, points, c):
+    """The three Pippenger steps composed; equals msm_naive for any c >= 1."""
+    B = buckets(scalars, points, c)
+    return group_aggregate([window_sum(row) for row in B], c)
+
+
+def closed_form(scalars, ks):
+    """For P_i = k_i G:  sum_i s_i P_i = ((sum_i s_i k_i) mod r) G."""
+    tot = sum(s * k for s, k in zip(scalars, ks)) % R_ORDER
+    return smul(tot, G)
