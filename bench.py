@@ -1,0 +1,297 @@
+#!/usr/bin/env python3
+"""Benchmark: BLS12-377 G1 multi-scalar multiplication on one MI355X (gfx950).
+
+One step = one full MSM (msm_run: digit sort, bucket accumulation, bucket
+aggregation, group aggregation, affine result) over n = 2^20 seeded synthetic
+points P_i = k_i G with uniform scalars mod r -- the n = 2^20 workload the
+headline metric is quoted on.  Points are generated and prepared on the GPU
+before the timed region (preparation is reported separately).
+
+value = PADDs/s, counted by the algorithm's formula
+        n W + 2 (2^c - 1) W + W c + W - 1   per MSM,  W = ceil(253 / c),
+ms_per_step = MSM latency.
+
+Prints one JSON line.  Extra keys: the window sweep, per-phase times, the
+standalone PADD kernel (2^22 independent pairs), the roofline of the dominant
+kernel and the CPU oracle baseline.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N_POINTS = 1 << 20
+C_SWEEP = list(range(10, 17))
+MAD_PER_MUL = 276          # 144 a*b + 132 m*p word products per Montgomery multiply
+MULS_MIXED = 7             # mixed PADD (Z2 = 1, U2 = k T2)
+MULS_COMPLETE = 9          # complete PADD with k T2 formed on the fly
+# gfx950 VALU: 256 CUs x 4 SIMDs x 16 lanes, v_mad_u64_u32 at full rate, 2.4 GHz
+PEAK_MAD_PER_S = 256 * 64 * 2.4e9
+
+
+def padd_count(n, c):
+    W = -(-253 // c)
+    return n * W + 2 * ((1 << c) - 1) * W + W * c + W - 1
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle, timed on the host cores (runs before the GPU is
+# touched, so the worker processes are forked from a GPU-free process)
+# ---------------------------------------------------------------------------
+
+def _oracle_worker(args):
+    seed, seconds, c = args
+    import random
+    from oracle import msm, points
+    from oracle.field import R_ORDER
+    rng = random.Random(seed)
+    pts = [points.fixed_base_mul(rng.randrange(1, R_ORDER)) for _ in range(64)]
+    adds = 0
+    t0 = time.perf_counter()
+    elapsed = 0.0
+    while elapsed < seconds:
+        sc = [rng.randrange(R_ORDER) for _ in range(256)]
+        pp = [pts[i % len(pts)] for i in range(256)]
+        msm.buckets(sc, pp, c)          # bucket accumulation: affine PADDs
+        W = msm.num_windows(c)
+        adds += sum(1 for s in sc for w in range(W) if msm.digit(s, w, c))
+        elapsed = time.perf_counter() - t0
+    return adds, elapsed
+
+
+def cpu_baseline(c, seconds=8.0):
+    import multiprocessing as mp
+    cores = max(1, min(os.cpu_count() or 1, 16))
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_worker, [(1000 + i, seconds, c) for i in range(cores)])
+    wall = time.perf_counter() - t0
+    adds = sum(r[0] for r in res)
+    rate = adds / max(r[1] for r in res)
+    return {
+        "value": rate,
+        "unit": "PADD/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": ("CPU oracle bucket accumulation (affine Weierstrass PADDs, Fermat inverse "
+                   "per add) at c=%d: %d adds in %.1f s on %d processes; MSM at n=2^20 "
+                   "extrapolated from this rate" % (c, adds, wall, cores)),
+        "msm_ms_extrapolated": padd_count(N_POINTS, c) / rate * 1e3,
+    }
+
+
+# ---------------------------------------------------------------------------
+# GPU side
+# ---------------------------------------------------------------------------
+
+def timed(fn, reps, torch):
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def nonzero_digit_entries(sw_np, c):
+    """Number of (point, window) pairs with a non-zero digit: the mixed PADDs
+    bucket accumulation performs."""
+    import numpy as np
+    W = -(-253 // c)
+    words = sw_np.reshape(-1, 8).astype(np.uint64)
+    total = 0
+    for w in range(W):
+        pos = w * c
+        wi, sh = pos // 32, pos % 32
+        lo = words[:, wi]
+        hi = words[:, wi + 1] if wi + 1 < 8 else np.zeros_like(lo)
+        d = ((lo | (hi << np.uint64(32))) >> np.uint64(sh)) & np.uint64((1 << c) - 1)
+        total += int(np.count_nonzero(d))
+    return total
+
+
+def padd_kernel_bench(torch, api, xyu_pool, pool_n, pairs, reps):
+    """Standalone batched PADD (2^22 independent pairs, SoA) -- the paper's
+    'task' measured as a stream of independent additions."""
+    import numpy as np
+    dev = xyu_pool.device
+    aos = xyu_pool.view(pool_n, 3, 12)
+    soa_b = aos.permute(1, 2, 0).contiguous()             # (3, 12, pool) prepared
+    ident = torch.zeros(4, 12, pool_n, dtype=torch.int32, device=dev)
+    one = api.to_device(np.array([0xffffff68, 0x02cdffff, 0x7fffffb1, 0x51409f83, 0x8a7d3ff2,
+                                  0x9f7db3a9, 0x6e7c6305, 0x7b4e97b7, 0x803c84e8, 0x4cf495bf,
+                                  0xe2fdf49a, 0x008d6661], dtype=np.uint32), dev)
+    ident[1] = one.view(12, 1)
+    ident[3] = one.view(12, 1)
+    # projective points with Z != 1: identity + P, then + another pool point
+    a_pool = api.padd_batch(ident.reshape(-1), soa_b.reshape(-1), pool_n, api.MSM_FORM_XYU)
+    rot = torch.roll(soa_b, 1, dims=2).contiguous()
+    a_pool = api.padd_batch(a_pool, rot.reshape(-1), pool_n, api.MSM_FORM_XYU)
+    g = torch.Generator(device="cpu").manual_seed(20250219)
+    ja = torch.randint(0, pool_n, (pairs,), generator=g).to(dev)
+    jb = torch.randint(0, pool_n, (pairs,), generator=g).to(dev)
+    A = a_pool.view(4, 12, pool_n).index_select(2, ja).contiguous().view(-1)
+    Bm = soa_b.index_select(2, jb).contiguous().view(-1)
+    Bc = a_pool.view(4, 12, pool_n).index_select(2, jb).contiguous().view(-1)
+    out = torch.empty_like(A)
+    res = {}
+    for name, B, form, muls, nbytes in (("mixed", Bm, api.MSM_FORM_XYU, MULS_MIXED, 48 * 4 * 2 + 36 * 4),
+                                        ("complete", Bc, api.MSM_FORM_XYTZ, MULS_COMPLETE, 48 * 4 * 3)):
+        fn = lambda: api.padd_batch(A, B, pairs, form, out=out)
+        fn()
+        ms = timed(fn, reps, torch)
+        rate = pairs / (ms * 1e-3)
+        res[name] = {
+            "pairs": pairs,
+            "ms": ms,
+            "padd_per_s": rate,
+            "mad_per_s": rate * muls * MAD_PER_MUL,
+            "frac_of_valu_mad_peak": rate * muls * MAD_PER_MUL / PEAK_MAD_PER_S,
+            "hbm_GBps": rate * nbytes / 1e9,
+        }
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--c", type=int, default=0, help="window width (0: sweep 10..16, take the best)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-padd-kernel", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X and has no "
+              "multi-GPU path (requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(16)
+
+    import numpy as np
+    import torch
+
+    from paper_2502_11660_amd import api, inputs
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    n = N_POINTS
+    seed = inputs.config_seed(3)
+    kw = inputs.nonzero_scalars_mod_r(seed, n, stream=1)
+    sw = inputs.scalars_mod_r(seed, n, stream=2)
+    k_dev = api.to_device(kw, dev)
+    s_dev = api.to_device(sw, dev)
+
+    print("[bench] generating %d points on the GPU ..." % n, file=sys.stderr, flush=True)
+    xy, inf = api.gen_points(k_dev, n)
+    torch.cuda.synchronize()
+    xyu = None
+
+    def prep():
+        nonlocal xyu
+        xyu, _ = api.points_prepare(xy, n, inf=inf, out=xyu)
+
+    prep()
+    prepare_ms = timed(prep, 3, torch)
+
+    # window sweep
+    sweep = {}
+    cs = [args.c] if args.c else C_SWEEP
+    for c in cs:
+        ws = api.workspace(n, c, dev)
+        res = api.words(api.MSM_RESULT_WORDS, dev)
+        fn = lambda: api.msm_run(xyu, s_dev, n, c, result=res, ws=ws)
+        fn()
+        sweep[c] = timed(fn, 2, torch)
+        del ws
+        print("[bench] c=%d: %.3f ms" % (c, sweep[c]), file=sys.stderr, flush=True)
+    best_c = min(sweep, key=sweep.get)
+
+    ws = api.workspace(n, best_c, dev)
+    res = api.words(api.MSM_RESULT_WORDS, dev)
+    step = lambda: api.msm_run(xyu, s_dev, n, best_c, result=res, ws=ws)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    for ph in ("sort", "accum", "merge", "agg", "horner"):
+        api.profile_read(ph)
+    api.profile_enable(True)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(args.steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    api.profile_enable(False)
+    ms_per_step = t0.elapsed_time(t1) / args.steps
+    phases = {}
+    for ph in ("sort", "accum", "merge", "agg", "horner"):
+        tot, cnt = api.profile_read(ph)
+        phases[ph] = tot / max(cnt, 1)
+    accum_tot_ms = phases["accum"]
+
+    padds = padd_count(n, best_c)
+    value = padds / (ms_per_step * 1e-3)
+    entries = nonzero_digit_entries(sw, best_c)
+    accum_mads = entries * MULS_MIXED * MAD_PER_MUL
+    achieved = accum_mads / (accum_tot_ms * 1e-3)
+
+    padd_k = None
+    if not args.no_padd_kernel:
+        pool_n = 8192
+        padd_k = padd_kernel_bench(torch, api, xyu[:pool_n * 36], pool_n, 1 << 22, 5)
+
+    out = {
+        "metric": "PADDs/s and MSM latency (ms) at n=2^20; batched/served MSMs/s + p99 vs plain",
+        "value": value,
+        "unit": "PADD/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "BLS12-377 G1 MSM, n=2^20 points k_i*G, uniform scalars mod r",
+                   "n": n, "c": best_c, "windows": -(-253 // best_c), "seed": seed,
+                   "padds_per_msm": padds},
+        "msm_ms": ms_per_step,
+        "prepare_ms": prepare_ms,
+        "c_sweep_ms": {str(k): v for k, v in sweep.items()},
+        "phase_ms": phases,
+        "roofline": {
+            "kernel": "k_accum (bucket accumulation, mixed PADD)",
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_MAD_PER_S / 1e12,
+            "unit": "Tmad/s (32x32->64 multiply-adds)",
+            "frac": achieved / PEAK_MAD_PER_S,
+            "traffic": None,
+            "work_per_launch": {"mixed_padds": entries, "mad_per_padd": MULS_MIXED * MAD_PER_MUL},
+            "launch_ms": accum_tot_ms,
+        },
+        "padd_kernel": padd_k,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,161 @@
+/*
+ * msm.h -- C ABI of the gfx950 BLS12-377 G1 multi-scalar multiplication library.
+ *
+ * The library computes MSM = sum_i s_i P_i over G1 of BLS12-377 (Abstract,
+ * Sec. II-C) by Pippenger's method: scalars are cut into c-bit windows, points
+ * are accumulated into buckets by their window digits (bucket accumulation),
+ * buckets are combined per window (bucket aggregation), and windows are
+ * combined into the result (group aggregation) (Sec. II-C).  Points are kept
+ * in twisted-Edwards extended coordinates (X, Y, T, Z); inputs to bucket
+ * accumulation are prepared as (X, Y, U = k T) with Z = 1 and added with the
+ * mixed addition, while aggregation uses the complete addition (Sec. II-D).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - A field element (FE) is 12 little-endian uint32 words.  Device-side FEs
+ *    crossing this boundary are canonical (< p).  Twisted-Edwards data is in
+ *    Montgomery form (value * 2^384 mod p); Weierstrass affine input/output
+ *    ("std") is in ordinary form.
+ *  - Scalars are 8 little-endian uint32 words each, one scalar after another,
+ *    and must be < 2^253 (values >= 2^253 are flagged, see MSM_FLAG_RANGE).
+ *  - Every pointer argument is a DEVICE pointer owned by the caller unless
+ *    stated otherwise; the library never frees or keeps caller memory.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Calls validate their
+ *    arguments on the host, enqueue work on `stream` and return without
+ *    synchronising; results are valid once the stream has reached them.
+ *    Calls on distinct workspaces may run concurrently.
+ *  - Return value: MSM_OK (0) or a negative MSM_E* code.  Nothing is enqueued
+ *    when a call returns an error from argument validation.
+ *
+ * Layouts
+ *  - SoA ("structure of arrays", limb-major): coordinate c, word l of element
+ *    i is at word index (c*12 + l)*count + i.
+ *  - AoS records: element i occupies a contiguous record; an XYU record is
+ *    36 words (X, Y, U), an XYTZ record 48 words (X, Y, T, Z).
+ */
+#ifndef MSM_H_
+#define MSM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MSM_OK 0
+#define MSM_EINVAL (-1) /* null pointer, zero/oversized count, c out of [1, 20] */
+#define MSM_ENOSPC (-2) /* workspace smaller than msm_workspace_bytes() */
+#define MSM_EHIP (-3)   /* HIP launch/runtime error; see msm_last_hip_error() */
+
+/* device-written status flags (bit set = condition detected) */
+#define MSM_FLAG_RANGE 1u    /* a scalar >= 2^253 (its bits >= 253 were ignored) */
+#define MSM_FLAG_OFFCURVE 2u /* an input point is not on y^2 = x^3 + 1 */
+#define MSM_FLAG_EXCEPT 4u   /* an input point is exceptional for the Edwards map
+                                (it cannot lie in the prime-order subgroup) */
+
+#define MSM_FORM_XYTZ 0 /* second PADD operand in extended coordinates */
+#define MSM_FORM_XYU 1  /* second PADD operand prepared: (X, Y, U = kT), Z = 1 */
+
+#define MSM_RESULT_WORDS 32 /* x[12], y[12], inf, flags, 6 reserved */
+
+/* Batched point addition out_i = a_i + b_i (Sec. II-D; the paper's "task").
+ * a_xytz: SoA, 4 coordinates x 12 words x count.  b: SoA, 4 coordinates
+ * (MSM_FORM_XYTZ, complete addition) or 3 coordinates (MSM_FORM_XYU, mixed
+ * addition with Z2 = 1).  out_xytz: SoA like a_xytz, canonical; may alias a.
+ * Errors: MSM_EINVAL for null pointers, count = 0 or count >= 2^31, or an
+ * unknown b_form. */
+int msm_padd_batch(const uint32_t* a_xytz, const uint32_t* b, uint32_t* out_xytz, size_t count,
+                   int b_form, void* stream);
+
+/* Batched Montgomery product out_i = a_i * b_i * 2^-384 mod p (the field core
+ * of every PADD, Sec. III-B/III-C with Montgomery reduction as proposed in
+ * Sec. V-C).  a, b, out: SoA with one coordinate (12 x count words).  Inputs
+ * may be any values with a_i * b_i < 2^384 p.  canonical != 0 reduces the
+ * output to [0, p); otherwise it is the lazily reduced value in [0, 2p).
+ * Errors: MSM_EINVAL as for msm_padd_batch. */
+int msm_fe_mul_batch(const uint32_t* a, const uint32_t* b, uint32_t* out, size_t count,
+                     int canonical, void* stream);
+
+/* Convert Weierstrass affine points (x, y), y^2 = x^3 + 1, to prepared
+ * twisted-Edwards form (Sec. II-D: inputs as (X, Y, U = k T), Z = 1).
+ * xy_std: SoA, 2 coordinates x 12 words x n, ordinary form, canonical.
+ * inf: n uint32 flags (non-zero = point at infinity) or NULL.
+ * xyu: AoS, 36 words per point, Montgomery form, canonical.
+ * status: one device uint32 that receives MSM_FLAG_OFFCURVE / MSM_FLAG_EXCEPT
+ * bits (OR-ed in; the caller clears it).  Points in the prime-order subgroup
+ * are never exceptional.  Errors: MSM_EINVAL for null pointers or n = 0. */
+int msm_points_prepare(const uint32_t* xy_std, const uint32_t* inf, uint32_t* xyu, size_t n,
+                       uint32_t* status, void* stream);
+
+/* Synthetic-workload generator: P_i = k_i G for the conventional generator G
+ * of BLS12-377 G1, written as Weierstrass affine points.  k: 8 words per
+ * scalar (any value < 2^256).  xy_std: SoA, 2 x 12 x n words, ordinary form,
+ * canonical.  inf: n uint32 flags (1 where k_i G is the point at infinity).
+ * Errors: MSM_EINVAL for null pointers or n = 0. */
+int msm_gen_points(const uint32_t* k, size_t n, uint32_t* xy_std, uint32_t* inf, void* stream);
+
+/* Number of window digits W = ceil(253 / c) for window width c. */
+int msm_num_windows(int c);
+
+/* Workspace (device bytes) needed by msm_bucket_accumulate / msm_run for n
+ * points and window width c (c = 0: the width msm_run would pick).  Returns 0
+ * for invalid arguments. */
+size_t msm_workspace_bytes(size_t n, int c);
+
+/* Window width msm_run picks for n points when called with c = 0. */
+int msm_default_window(size_t n);
+
+/* Bucket accumulation (Sec. II-C): B[w][b] = sum of P_i whose w-th c-bit
+ * digit of s_i equals b, for w < W = ceil(253/c), 0 <= b < 2^c (bucket 0
+ * holds the identity).  xyu: AoS prepared points (msm_points_prepare).
+ * scalars: 8 words per scalar.  buckets: AoS XYTZ records, record index
+ * w*2^c + b, Montgomery form, lazily reduced (< 2p; compare after
+ * normalisation -- any projective multiple is the same point).
+ * ws: device workspace of ws_bytes >= msm_workspace_bytes(n, c); word 0 of ws
+ * receives the status flags (MSM_FLAG_RANGE).
+ * Errors: MSM_EINVAL (null, n = 0, n >= 2^26, c not in [1, 20]),
+ * MSM_ENOSPC, MSM_EHIP. */
+int msm_bucket_accumulate(const uint32_t* xyu, const uint32_t* scalars, size_t n, int c,
+                          uint32_t* buckets, void* ws, size_t ws_bytes, void* stream);
+
+/* Full MSM: result = sum_i s_i P_i (Sec. II-C), Pippenger with window width
+ * c (c = 0 picks msm_default_window(n)).  result: MSM_RESULT_WORDS device
+ * words: x[12], y[12] (Weierstrass affine, ordinary form, canonical), inf
+ * (1 if the sum is the point at infinity, then x = y = 0), flags
+ * (MSM_FLAG_RANGE).  Other arguments as for msm_bucket_accumulate.
+ * Errors as for msm_bucket_accumulate. */
+int msm_run(const uint32_t* xyu, const uint32_t* scalars, size_t n, int c, uint32_t* result,
+            void* ws, size_t ws_bytes, void* stream);
+
+/* Per-phase timing for measurement.  While enabled, each call records HIP
+ * events on its own stream around its phases: "sort" (histogram, scan,
+ * scatter), "accum" (the bucket accumulation kernel), "merge" (split-bucket
+ * merge), "agg" (bucket aggregation), "horner" (group aggregation and the
+ * affine result).  msm_profile_read synchronises on the recorded events,
+ * returns the summed milliseconds and the number of recorded launches of one
+ * phase since the last read, and forgets them.  Recording adds event records
+ * to the stream, so leave it disabled under graph capture.
+ * Errors: MSM_EINVAL (unknown phase, null outputs), MSM_EHIP. */
+int msm_profile_enable(int on);
+int msm_profile_read(const char* phase, double* total_ms, int* launches);
+
+/* HIP error code (hipError_t value) behind the last MSM_EHIP on this thread. */
+int msm_last_hip_error(void);
+
+/* Human-readable name of a status code. */
+const char* msm_status_string(int status);
+
+/* Host copy of the built-in constants the kernels use, for independent
+ * checking: words [0,12) p, [12,24) 2^384 mod p, [24,36) 2^768 mod p, then in
+ * Montgomery form (value * 2^384 mod p): [36,48) the Edwards constant k,
+ * [48,60) alpha, [60,72) beta (the Weierstrass/Edwards map x = alpha u - 1,
+ * y = beta v), [72,84) G.x, [84,96) G.y.  out: HOST pointer to at least 96
+ * words.  Returns MSM_OK or MSM_EINVAL (null out, words < 96). */
+int msm_constants(uint32_t* out, size_t words);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSM_H_ */

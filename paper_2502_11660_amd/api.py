@@ -1,0 +1,187 @@
+"""Python binding of the C ABI (include/msm.h), one function per entry point.
+
+Argument marshalling only: torch provides device memory (int32 tensors used as
+raw 32-bit words) and the current HIP stream; every step of the computation
+runs in the library's kernels.  Calls are asynchronous on the current stream,
+like the C functions they wrap.
+"""
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (MSM_FLAG_EXCEPT, MSM_FLAG_OFFCURVE, MSM_FLAG_RANGE, MSM_FORM_XYTZ,  # noqa: F401
+                   MSM_FORM_XYU, MSM_RESULT_WORDS, MSMError)
+
+WORDS = 12
+XYU_WORDS = 36
+XYTZ_WORDS = 48
+SCALAR_WORDS = 8
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a CUDA/HIP tensor" % name)
+    if t.dtype != torch.int32 or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous int32 tensor (raw 32-bit words)" % name)
+    return t
+
+
+def words(n, device="cuda"):
+    return torch.empty(int(n), dtype=torch.int32, device=device)
+
+
+def to_device(arr_u32, device="cuda"):
+    """numpy uint32 array -> contiguous int32 device tensor with the same bits."""
+    a = np.ascontiguousarray(arr_u32, dtype=np.uint32).reshape(-1)
+    return torch.from_numpy(a.view(np.int32).copy()).to(device)
+
+
+def to_host(t):
+    """device tensor of 32-bit words -> numpy uint32 array (synchronises)."""
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+def padd_batch(a_xytz, b, count, b_form, out=None):
+    """out_i = a_i + b_i (SoA layouts, see msm_padd_batch)."""
+    _dev(a_xytz, "a_xytz")
+    _dev(b, "b")
+    nb = 4 if b_form == MSM_FORM_XYTZ else 3
+    if a_xytz.numel() != 4 * WORDS * count or b.numel() != nb * WORDS * count:
+        raise ValueError("operand sizes do not match count")
+    if out is None:
+        out = words(4 * WORDS * count, a_xytz.device)
+    _dev(out, "out")
+    _lib.check("msm_padd_batch", _lib.lib().msm_padd_batch(
+        _ptr(a_xytz), _ptr(b), _ptr(out), count, b_form, _stream()))
+    return out
+
+
+def fe_mul_batch(a, b, count, canonical=True, out=None):
+    _dev(a, "a")
+    _dev(b, "b")
+    if a.numel() != WORDS * count or b.numel() != WORDS * count:
+        raise ValueError("operand sizes do not match count")
+    if out is None:
+        out = words(WORDS * count, a.device)
+    _lib.check("msm_fe_mul_batch", _lib.lib().msm_fe_mul_batch(
+        _ptr(a), _ptr(b), _ptr(out), count, 1 if canonical else 0, _stream()))
+    return out
+
+
+def points_prepare(xy_std, n, inf=None, out=None, status=None):
+    """Weierstrass affine (SoA) -> prepared Edwards XYU records (AoS)."""
+    _dev(xy_std, "xy_std")
+    if xy_std.numel() != 2 * WORDS * n:
+        raise ValueError("xy_std size does not match n")
+    if inf is not None:
+        _dev(inf, "inf")
+    if out is None:
+        out = words(XYU_WORDS * n, xy_std.device)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=xy_std.device)
+    _lib.check("msm_points_prepare", _lib.lib().msm_points_prepare(
+        _ptr(xy_std), _ptr(inf), _ptr(out), n, _ptr(status), _stream()))
+    return out, status
+
+
+def gen_points(k, n, xy_out=None, inf_out=None):
+    """P_i = k_i G as Weierstrass affine points (SoA) plus infinity flags."""
+    _dev(k, "k")
+    if k.numel() != SCALAR_WORDS * n:
+        raise ValueError("k size does not match n")
+    if xy_out is None:
+        xy_out = words(2 * WORDS * n, k.device)
+    if inf_out is None:
+        inf_out = words(n, k.device)
+    _lib.check("msm_gen_points", _lib.lib().msm_gen_points(
+        _ptr(k), n, _ptr(xy_out), _ptr(inf_out), _stream()))
+    return xy_out, inf_out
+
+
+def num_windows(c):
+    return _lib.lib().msm_num_windows(c)
+
+
+def default_window(n):
+    return _lib.lib().msm_default_window(n)
+
+
+def workspace_bytes(n, c):
+    return _lib.lib().msm_workspace_bytes(n, c)
+
+
+def workspace(n, c, device="cuda"):
+    nbytes = workspace_bytes(n, c)
+    if nbytes == 0:
+        raise ValueError("invalid (n, c) = (%d, %d)" % (n, c))
+    return torch.empty((nbytes + 3) // 4, dtype=torch.int32, device=device)
+
+
+def bucket_accumulate(xyu, scalars, n, c, buckets=None, ws=None):
+    _dev(xyu, "xyu")
+    _dev(scalars, "scalars")
+    if xyu.numel() != XYU_WORDS * n or scalars.numel() != SCALAR_WORDS * n:
+        raise ValueError("input sizes do not match n")
+    W = num_windows(c)
+    if buckets is None:
+        buckets = words(XYTZ_WORDS * (W << c), xyu.device)
+    if ws is None:
+        ws = workspace(n, c, xyu.device)
+    _lib.check("msm_bucket_accumulate", _lib.lib().msm_bucket_accumulate(
+        _ptr(xyu), _ptr(scalars), n, c, _ptr(buckets), _ptr(ws), ws.numel() * 4, _stream()))
+    return buckets, ws
+
+
+def msm_run(xyu, scalars, n, c=0, result=None, ws=None):
+    _dev(xyu, "xyu")
+    _dev(scalars, "scalars")
+    if xyu.numel() != XYU_WORDS * n or scalars.numel() != SCALAR_WORDS * n:
+        raise ValueError("input sizes do not match n")
+    if result is None:
+        result = words(MSM_RESULT_WORDS, xyu.device)
+    if ws is None:
+        ws = workspace(n, c, xyu.device)
+    _lib.check("msm_run", _lib.lib().msm_run(
+        _ptr(xyu), _ptr(scalars), n, c, _ptr(result), _ptr(ws), ws.numel() * 4, _stream()))
+    return result
+
+
+def constants():
+    buf = (ctypes.c_uint32 * 96)()
+    _lib.check("msm_constants", _lib.lib().msm_constants(ctypes.cast(buf, ctypes.c_void_p), 96))
+    return np.frombuffer(bytes(buf), dtype=np.uint32).copy()
+
+
+def decode_result(res_u32):
+    """Host view of a result buffer: (x, y) ints or None for infinity, flags."""
+    r = np.asarray(res_u32, dtype=np.uint32)
+    flags = int(r[2 * WORDS + 1])
+    if r[2 * WORDS]:
+        return None, flags
+    x = sum(int(w) << (32 * i) for i, w in enumerate(r[:WORDS]))
+    y = sum(int(w) << (32 * i) for i, w in enumerate(r[WORDS:2 * WORDS]))
+    return (x, y), flags
+
+
+def profile_enable(on=True):
+    _lib.check("msm_profile_enable", _lib.lib().msm_profile_enable(1 if on else 0))
+
+
+def profile_read(phase):
+    """(total_ms, launches) of one phase since the last read (synchronises)."""
+    tot = ctypes.c_double(0.0)
+    cnt = ctypes.c_int(0)
+    _lib.check("msm_profile_read", _lib.lib().msm_profile_read(
+        phase.encode(), ctypes.byref(tot), ctypes.byref(cnt)))
+    return tot.value, cnt.value

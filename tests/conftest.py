@@ -35,3 +35,16 @@ def pytest_collection_modifyitems(config, items):
 @pytest.fixture(scope="session")
 def nproc():
     return min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="session")
+def oracle_pool(nproc):
+    """2048 oracle points P_i = k_i G (k_i from the shared seeded generator)."""
+    from oracle import points
+    from paper_2502_11660_amd import inputs
+    kw = inputs.nonzero_scalars_mod_r(inputs.config_seed(1), 2048, stream=7)
+    ks = [inputs.words_to_int(r) for r in kw]
+    # serial on purpose: no worker processes forked from a process that may
+    # already hold a GPU context
+    pts = points.gen_points(ks)
+    return ks, pts

@@ -1,0 +1,89 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+declared in include/msm.h, validates arguments, and its built-in constants
+equal the oracle's independently derived values.  No GPU work is launched."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import field, te
+from paper_2502_11660_amd import _lib
+from tests.helpers import words_int
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(msm_\w+)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("library not built: " + _lib.LIB_PATH)
+    return _lib.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in _lib.SIGNATURES, "binding does not declare " + n
+
+
+def test_constants_match_oracle(lib):
+    buf = (ctypes.c_uint32 * 96)()
+    assert lib.msm_constants(ctypes.cast(buf, ctypes.c_void_p), 96) == 0
+    w = np.frombuffer(bytes(buf), dtype=np.uint32)
+    g = lambda i: words_int(w[12 * i:12 * i + 12])
+    P = field.P
+    assert g(0) == P
+    assert g(1) == field.R_MONT % P
+    assert g(2) == field.R2_MONT
+    assert field.from_mont(g(3)) == te.K_TE
+    assert field.from_mont(g(4)) == te.ALPHA
+    assert field.from_mont(g(5)) == te.BETA
+    assert field.from_mont(g(6)) == field.G_X
+    assert field.from_mont(g(7)) == field.G_Y
+    assert lib.msm_constants(None, 96) == _lib.MSM_EINVAL
+    assert lib.msm_constants(ctypes.cast(buf, ctypes.c_void_p), 10) == _lib.MSM_EINVAL
+
+
+def test_argument_validation_without_gpu(lib):
+    # invalid arguments are rejected on the host before anything is enqueued
+    p = ctypes.c_void_p(16)
+    assert lib.msm_padd_batch(None, p, p, 4, 0, None) == _lib.MSM_EINVAL
+    assert lib.msm_padd_batch(p, p, p, 0, 0, None) == _lib.MSM_EINVAL
+    assert lib.msm_padd_batch(p, p, p, 4, 7, None) == _lib.MSM_EINVAL
+    assert lib.msm_fe_mul_batch(p, None, p, 4, 1, None) == _lib.MSM_EINVAL
+    assert lib.msm_points_prepare(p, None, p, 0, p, None) == _lib.MSM_EINVAL
+    assert lib.msm_gen_points(p, 0, p, p, None) == _lib.MSM_EINVAL
+    assert lib.msm_run(p, p, 0, 8, p, p, 1 << 30, None) == _lib.MSM_EINVAL
+    assert lib.msm_run(p, p, 16, 21, p, p, 1 << 30, None) == _lib.MSM_EINVAL
+    assert lib.msm_run(p, p, 16, 8, p, p, 100, None) == _lib.MSM_ENOSPC
+    assert lib.msm_bucket_accumulate(p, p, 16, 8, None, p, 1 << 30, None) == _lib.MSM_EINVAL
+    assert lib.msm_bucket_accumulate(p, p, 1 << 26, 8, p, p, 1 << 40, None) == _lib.MSM_EINVAL
+    assert lib.msm_workspace_bytes(0, 8) == 0
+    assert lib.msm_workspace_bytes(1024, 21) == 0
+    assert lib.msm_workspace_bytes(1024, 8) > 0
+    assert lib.msm_status_string(_lib.MSM_ENOSPC).startswith(b"MSM_ENOSPC")
+
+
+def test_window_helpers(lib):
+    for c in range(1, 21):
+        assert lib.msm_num_windows(c) == -(-253 // c)
+    assert lib.msm_num_windows(0) == 0
+    for n in (1, 1024, 1 << 16, 1 << 20):
+        c = lib.msm_default_window(n)
+        assert 1 <= c <= 20
+        assert lib.msm_workspace_bytes(n, 0) == lib.msm_workspace_bytes(n, c)

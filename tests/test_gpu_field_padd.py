@@ -1,0 +1,166 @@
+"""GPU parity: field multiply, batched PADD, point preparation and the
+synthetic point generator, each against the CPU oracle on seeded inputs.
+
+Every expected value is computed by the oracle from the same seeded integers;
+comparisons are exact (integers), after normalising projective outputs.
+"""
+
+import random
+
+import numpy as np
+import pytest
+
+from oracle import curve, field, te
+from oracle.field import P
+from paper_2502_11660_amd import api, inputs
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+R = field.R_MONT
+
+
+def _dev(a):
+    return api.to_device(a)
+
+
+# --------------------------------------------------------------------------
+# field multiply
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("count", [1, 63, 1000, 4099])
+def test_fe_mul_lazy_and_canonical(count):
+    rng = random.Random(count)
+    edge = [0, 1, 2, P - 1, P, P + 1, 2 * P - 1, 2 * P, 6 * P - 1, 11 * P + 5, 12 * P - 1,
+            R % P, (1 << 377) - 1]
+    a_vals, b_vals = [], []
+    for i in range(count):
+        if i < len(edge) ** 2 and i < count // 2:
+            a, b = edge[i % len(edge)], edge[(i // len(edge)) % len(edge)]
+        else:
+            a, b = rng.randrange(12 * P), rng.randrange(12 * P)
+        assert a * b < R * P
+        a_vals.append(a)
+        b_vals.append(b)
+    A = _dev(H.soa([(v,) for v in a_vals], 1))
+    B = _dev(H.soa([(v,) for v in b_vals], 1))
+    lazy = H.unsoa(api.to_host(api.fe_mul_batch(A, B, count, canonical=False)), 1, count)
+    canon = H.unsoa(api.to_host(api.fe_mul_batch(A, B, count, canonical=True)), 1, count)
+    rinv = field.R_MONT_INV
+    for a, b, (lz,), (cn,) in zip(a_vals, b_vals, lazy, canon):
+        want = a * b * rinv % P
+        assert lz < 2 * P
+        assert lz % P == want
+        assert cn == want
+
+
+# --------------------------------------------------------------------------
+# batched PADD (complete and mixed)
+# --------------------------------------------------------------------------
+
+def _pairs(pool_pts, count, seed):
+    rng = random.Random(seed)
+    te_pts = [te.w_to_te(p) for p in pool_pts[:256]]
+    pairs = []
+    for i in range(count):
+        a = rng.choice(te_pts)
+        kind = i % 16
+        if kind == 0:
+            b = a                                  # doubling through the unified law
+        elif kind == 1:
+            b = te.te_neg(a)                       # P + (-P) = identity
+        elif kind == 2:
+            a, b = te.IDENTITY, rng.choice(te_pts)
+        elif kind == 3:
+            b = te.IDENTITY
+        else:
+            b = rng.choice(te_pts)
+        pairs.append((a, b))
+    return pairs
+
+
+@pytest.mark.parametrize("form", [api.MSM_FORM_XYTZ, api.MSM_FORM_XYU])
+@pytest.mark.parametrize("count", [1, 100, 1024, 1537])
+def test_padd_batch_parity(oracle_pool, form, count):
+    _, pts = oracle_pool
+    pairs = _pairs(pts, count, seed=count * 7 + form)
+    lam = inputs.base_field_elements(inputs.config_seed(1) + form, 2 * count, stream=count)
+    lam = [inputs.words_to_int(r) for r in lam]
+    a_rows = [H.te_extended_mont(a, lam[2 * i]) for i, (a, _) in enumerate(pairs)]
+    if form == api.MSM_FORM_XYTZ:
+        b_rows = [H.te_extended_mont(b, lam[2 * i + 1]) for i, (_, b) in enumerate(pairs)]
+        nb = 4
+    else:
+        b_rows = [H.te_prepared_mont(b) for _, b in pairs]
+        nb = 3
+    out = api.padd_batch(_dev(H.soa(a_rows, 4)), _dev(H.soa(b_rows, nb)), count, form)
+    rows = H.unsoa(api.to_host(out), 4, count)
+    for (a, b), rec in zip(pairs, rows):
+        assert all(v < P for v in rec)                       # canonical at the boundary
+        assert H.normalize_extended_mont(rec) == te.te_add(a, b)
+
+
+def test_padd_batch_in_place(oracle_pool):
+    _, pts = oracle_pool
+    count = 300
+    pairs = _pairs(pts, count, seed=99)
+    a_rows = [H.te_extended_mont(a, 3 + i) for i, (a, _) in enumerate(pairs)]
+    b_rows = [H.te_extended_mont(b, 5 + i) for i, (_, b) in enumerate(pairs)]
+    A = _dev(H.soa(a_rows, 4))
+    api.padd_batch(A, _dev(H.soa(b_rows, 4)), count, api.MSM_FORM_XYTZ, out=A)
+    rows = H.unsoa(api.to_host(A), 4, count)
+    for (a, b), rec in zip(pairs, rows):
+        assert H.normalize_extended_mont(rec) == te.te_add(a, b)
+
+
+# --------------------------------------------------------------------------
+# point preparation and generation
+# --------------------------------------------------------------------------
+
+def test_points_prepare_parity(oracle_pool):
+    _, pts = oracle_pool
+    n = 777
+    sel = list(pts[:n - 2]) + [curve.INF, pts[5]]
+    xy = H.soa([(0, 0) if p is None else p for p in sel], 2)
+    inf = np.array([1 if p is None else 0 for p in sel], dtype=np.uint32)
+    out, status = api.points_prepare(_dev(xy), n, inf=_dev(inf))
+    rows = H.unaos(api.to_host(out), 3, n)
+    assert int(api.to_host(status)[0]) == 0
+    for p, rec in zip(sel, rows):
+        want = H.te_prepared_mont(te.w_to_te(p))
+        assert rec == want
+
+
+def test_points_prepare_flags_off_curve(oracle_pool):
+    _, pts = oracle_pool
+    x, y = pts[0]
+    bad = [(x, (y + 1) % P), pts[1]]
+    out, status = api.points_prepare(_dev(H.soa(bad, 2)), 2)
+    assert int(api.to_host(status)[0]) & api.MSM_FLAG_OFFCURVE
+    rows = H.unaos(api.to_host(out), 3, 2)
+    assert rows[1] == H.te_prepared_mont(te.w_to_te(pts[1]))
+
+
+def test_gen_points_parity(oracle_pool):
+    ks, pts = oracle_pool
+    n = 300
+    kw = H.scalar_words(ks[:n])
+    xy, inf = api.gen_points(_dev(kw), n)
+    rows = H.unsoa(api.to_host(xy), 2, n)
+    flags = api.to_host(inf)
+    for p, rec, f in zip(pts[:n], rows, flags):
+        assert f == 0
+        assert rec == p
+
+
+def test_gen_points_edge_scalars():
+    from oracle import points
+    ks = [1, 2, field.R_ORDER - 1, field.R_ORDER, 0, (1 << 256) - 1]
+    xy, inf = api.gen_points(_dev(H.scalar_words(ks)), len(ks))
+    rows = H.unsoa(api.to_host(xy), 2, len(ks))
+    flags = api.to_host(inf)
+    for k, rec, f in zip(ks, rows, flags):
+        want = points.fixed_base_mul(k % field.R_ORDER)
+        if want is None:
+            assert f == 1 and rec == (0, 0)
+        else:
+            assert f == 0 and rec == want

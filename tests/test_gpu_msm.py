@@ -1,0 +1,162 @@
+"""GPU parity of bucket accumulation and the full MSM against the oracle.
+
+Inputs are seeded; points P_i = k_i G.  Expected values come from the oracle:
+bucket sums by their definition, and the MSM either by the naive sum or by
+the closed form ((sum s_i k_i) mod r) G (both pinned in test_oracle.py).
+"""
+
+import random
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import curve, msm, te
+from oracle.field import R_ORDER
+from paper_2502_11660_amd import api, inputs
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    return api.to_device(a)
+
+
+def _prepared(pts):
+    xy = H.soa([(0, 0) if p is None else p for p in pts], 2)
+    inf = np.array([1 if p is None else 0 for p in pts], dtype=np.uint32)
+    xyu, status = api.points_prepare(_dev(xy), len(pts), inf=_dev(inf))
+    assert int(api.to_host(status)[0]) == 0
+    return xyu
+
+
+def _run(xyu, scalars, c):
+    n = len(scalars)
+    res = api.msm_run(xyu, _dev(H.scalar_words(scalars)), n, c)
+    pt, flags = api.decode_result(api.to_host(res))
+    return pt, flags
+
+
+def test_bucket_accumulate_config1(oracle_pool):
+    """n = 1024, c = 8: every bucket B[w][b] equals its definition."""
+    ks, pts = oracle_pool
+    n, c = 1024, 8
+    sc = [inputs.words_to_int(r) for r in inputs.scalars_mod_r(inputs.config_seed(1), n)]
+    xyu = _prepared(pts[:n])
+    buckets, ws = api.bucket_accumulate(xyu, _dev(H.scalar_words(sc)), n, c)
+    W = msm.num_windows(c)
+    got = H.unaos(api.to_host(buckets), 4, W << c)
+    want = msm.buckets(sc, pts[:n], c)
+    for w in range(W):
+        for b in range(1 << c):
+            assert H.normalize_extended_mont(got[(w << c) + b]) == te.w_to_te(want[w][b]), (w, b)
+    assert int(api.to_host(ws[:1])[0]) == 0
+
+
+def test_msm_config1_closed_form_and_naive(oracle_pool):
+    ks, pts = oracle_pool
+    n, c = 1024, 8
+    sc = [inputs.words_to_int(r) for r in inputs.scalars_mod_r(inputs.config_seed(1), n)]
+    xyu = _prepared(pts[:n])
+    got, flags = _run(xyu, sc, c)
+    assert flags == 0
+    assert got == msm.closed_form(sc, ks[:n])
+    # direct definition on a prefix
+    m = 48
+    got_m, _ = _run(_prepared(pts[:m]), sc[:m], c)
+    assert got_m == msm.msm_naive(sc[:m], pts[:m])
+
+
+@pytest.mark.parametrize("c", [1, 2, 3, 5, 7, 10, 12, 13, 16])
+def test_msm_window_widths(oracle_pool, c):
+    ks, pts = oracle_pool
+    n = 200 + 37 * c
+    sc = [inputs.words_to_int(r) for r in inputs.scalars_mod_r(1000 + c, n)]
+    got, flags = _run(_prepared(pts[:n]), sc, c)
+    assert flags == 0
+    assert got == msm.closed_form(sc, ks[:n])
+
+
+@pytest.mark.parametrize("n", [1, 2, 31, 32, 33, 65, 1000])
+def test_msm_ragged_sizes(oracle_pool, n):
+    ks, pts = oracle_pool
+    sc = [inputs.words_to_int(r) for r in inputs.scalars_mod_r(77 + n, n)]
+    got, _ = _run(_prepared(pts[:n]), sc, 8)
+    assert got == msm.closed_form(sc, ks[:n])
+
+
+def test_msm_degenerate_scalars(oracle_pool):
+    ks, pts = oracle_pool
+    n = 300
+    xyu = _prepared(pts[:n])
+    # all zero -> point at infinity
+    got, _ = _run(xyu, [0] * n, 8)
+    assert got is None
+    # all equal: every point in the same bucket of every window (skew)
+    s = 0x1234567890ABCDEF1234567890ABCDEF1234567890ABCDEF1234567890ABCDE % R_ORDER
+    got, _ = _run(xyu, [s] * n, 8)
+    assert got == msm.closed_form([s] * n, ks[:n])
+    # extremes: r - 1, 2^253 - 1 (>= r, still valid input), 1
+    sc = [R_ORDER - 1, (1 << 253) - 1, 1] * (n // 3)
+    got, flags = _run(xyu, sc, 8)
+    assert flags == 0
+    assert got == msm.closed_form(sc, ks[:n])
+    # cancellation: s and r - s on the same point -> infinity
+    sc2 = [5, R_ORDER - 5]
+    got, _ = _run(_prepared([pts[0], pts[0]]), sc2, 4)
+    assert got is None
+
+
+def test_msm_scalar_out_of_range_flagged(oracle_pool):
+    ks, pts = oracle_pool
+    n = 16
+    sc = [random.Random(i).randrange(R_ORDER) for i in range(n)]
+    sc[3] |= 1 << 254
+    got, flags = _run(_prepared(pts[:n]), sc, 8)
+    assert flags & api.MSM_FLAG_RANGE
+    trunc = [s & ((1 << 253) - 1) for s in sc]
+    assert got == msm.closed_form(trunc, ks[:n])
+
+
+def test_msm_with_identity_points(oracle_pool):
+    ks, pts = oracle_pool
+    sel = [pts[0], curve.INF, pts[1], curve.INF]
+    sc = [3, 5, 7, 11]
+    got, _ = _run(_prepared(sel), sc, 3)
+    assert got == msm.msm_naive(sc, sel)
+
+
+def test_msm_point_order_and_repeat_invariance(oracle_pool):
+    ks, pts = oracle_pool
+    n = 513
+    sc = [inputs.words_to_int(r) for r in inputs.scalars_mod_r(4242, n)]
+    perm = list(range(n))
+    random.Random(1).shuffle(perm)
+    a, _ = _run(_prepared(pts[:n]), sc, 9)
+    b, _ = _run(_prepared([pts[i] for i in perm]), [sc[i] for i in perm], 9)
+    c2, _ = _run(_prepared(pts[:n]), sc, 9)
+    assert a == b == c2 == msm.closed_form(sc, ks[:n])
+
+
+@pytest.mark.parametrize("c", [16])
+def test_msm_full_size_closed_form(c):
+    """n = 2^20 GPU-generated points (checked on a sample), closed form."""
+    n = 1 << 20
+    seed = inputs.config_seed(3)
+    kw = inputs.nonzero_scalars_mod_r(seed, n, stream=1)
+    sw = inputs.scalars_mod_r(seed, n, stream=2)
+    xy, inf = api.gen_points(_dev(kw), n)
+    xyu, status = api.points_prepare(xy, n, inf=inf)
+    res = api.msm_run(xyu, _dev(sw), n, c)
+    torch.cuda.synchronize()
+    got, flags = api.decode_result(api.to_host(res))
+    assert flags == 0 and int(api.to_host(status)[0]) == 0
+    ks = [inputs.words_to_int(r) for r in kw]
+    ss = [inputs.words_to_int(r) for r in sw]
+    assert got == msm.closed_form(ss, ks)
+    # sample of the generated points against the oracle
+    from oracle import points
+    rows = H.unsoa(api.to_host(xy).reshape(24, n)[:, :64].reshape(-1), 2, 64)
+    for i in range(0, 64, 8):
+        assert rows[i] == points.fixed_base_mul(ks[i])
