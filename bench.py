@@ -47,21 +47,20 @@ def padd_count(n, c):
 # ---------------------------------------------------------------------------
 
 def _oracle_worker(args):
-    seed, seconds, c = args
+    seed, seconds = args
     import random
-    from oracle import msm, points
+    from oracle import curve, points
     from oracle.field import R_ORDER
     rng = random.Random(seed)
-    pts = [points.fixed_base_mul(rng.randrange(1, R_ORDER)) for _ in range(64)]
+    pts = [points.fixed_base_mul(rng.randrange(1, R_ORDER)) for _ in range(32)]
+    acc = pts[0]
     adds = 0
     t0 = time.perf_counter()
     elapsed = 0.0
     while elapsed < seconds:
-        sc = [rng.randrange(R_ORDER) for _ in range(256)]
-        pp = [pts[i % len(pts)] for i in range(256)]
-        msm.buckets(sc, pp, c)          # bucket accumulation: affine PADDs
-        W = msm.num_windows(c)
-        adds += sum(1 for s in sc for w in range(W) if msm.digit(s, w, c))
+        for j in range(256):
+            acc = curve.add(acc, pts[j & 31])   # one affine PADD (chord law)
+        adds += 256
         elapsed = time.perf_counter() - t0
     return adds, elapsed
 
@@ -72,7 +71,7 @@ def cpu_baseline(c, seconds=8.0):
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
-        res = pool.map(_oracle_worker, [(1000 + i, seconds, c) for i in range(cores)])
+        res = pool.map(_oracle_worker, [(1000 + i, seconds) for i in range(cores)])
     wall = time.perf_counter() - t0
     adds = sum(r[0] for r in res)
     rate = adds / max(r[1] for r in res)
@@ -81,9 +80,10 @@ def cpu_baseline(c, seconds=8.0):
         "unit": "PADD/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": ("CPU oracle bucket accumulation (affine Weierstrass PADDs, Fermat inverse "
-                   "per add) at c=%d: %d adds in %.1f s on %d processes; MSM at n=2^20 "
-                   "extrapolated from this rate" % (c, adds, wall, cores)),
+        "sample": ("CPU oracle point additions (affine Weierstrass chord law, one Fermat "
+                   "inverse per add), %d dependent adds in %.1f s on %d processes; the MSM time "
+                   "at n=2^20, c=%d is extrapolated from this rate by the PADD count"
+                   % (adds, wall, cores, c)),
         "msm_ms_extrapolated": padd_count(N_POINTS, c) / rate * 1e3,
     }
 
@@ -162,6 +162,31 @@ def padd_kernel_bench(torch, api, xyu_pool, pool_n, pairs, reps):
     return res
 
 
+def microbench():
+    """Issue rates of v_mad_u64_u32 / v_addc_co_u32 and HBM copy bandwidth."""
+    import torch
+    from paper_2502_11660_amd import api
+    torch.cuda.set_device(0)
+    out = {}
+    buf = torch.empty(2048 * 256 * 2, dtype=torch.int32, device="cuda")
+    threads = 2048 * 256
+    for name, kind in (("v_mad_u64_u32", api._lib.MSM_MB_MAD64), ("v_addc_co_u32", api._lib.MSM_MB_ADDC)):
+        iters = 4000
+        api.microbench(kind, 10, buf)
+        ms = timed(lambda: api.microbench(kind, iters, buf), 3, torch)
+        rate = 16.0 * iters * threads / (ms * 1e-3)
+        out[name] = {"ops_per_s": rate, "frac_of_peak": rate / PEAK_MAD_PER_S,
+                     "lane_ops_per_cu_per_clk_at_2.4GHz": rate / (256 * 2.4e9)}
+    nbytes = 1 << 31
+    big = torch.empty(2 * nbytes // 4, dtype=torch.int32, device="cuda")
+    api.microbench(api._lib.MSM_MB_COPY, nbytes, big)
+    ms = timed(lambda: api.microbench(api._lib.MSM_MB_COPY, nbytes, big), 5, torch)
+    out["hbm_copy"] = {"bytes_read": nbytes, "bytes_written": nbytes, "ms": ms,
+                       "GBps_read_plus_write": 2 * nbytes / (ms * 1e-3) / 1e9}
+    out["peak_mad_per_s_derived"] = PEAK_MAD_PER_S
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,12 +195,18 @@ def main():
     ap.add_argument("--c", type=int, default=0, help="window width (0: sweep 10..16, take the best)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-padd-kernel", action="store_true")
+    ap.add_argument("--microbench", action="store_true",
+                    help="only measure the VALU mad / carry-add issue rates and HBM copy bandwidth")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X and has no "
               "multi-GPU path (requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    if args.microbench:
+        print(json.dumps(microbench()))
+        return
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -255,6 +286,10 @@ def main():
     if not args.no_padd_kernel:
         pool_n = 8192
         padd_k = padd_kernel_bench(torch, api, xyu[:pool_n * 36], pool_n, 1 << 22, 5)
+
+    if cpu is not None:
+        cpu["msm_ms_extrapolated"] = padd_count(n, best_c) / cpu["value"] * 1e3
+        cpu["sample"] = cpu["sample"].replace("c=16", "c=%d" % best_c)
 
     out = {
         "metric": "PADDs/s and MSM latency (ms) at n=2^20; batched/served MSMs/s + p99 vs plain",

@@ -140,6 +140,19 @@ int msm_run(const uint32_t* xyu, const uint32_t* scalars, size_t n, int c, uint3
 int msm_profile_enable(int on);
 int msm_profile_read(const char* phase, double* total_ms, int* launches);
 
+/* Microbenchmarks for the roofline denominators (not part of the MSM path).
+ * kind MSM_MB_MAD64: 2048 x 256 threads, each issuing 16 * param independent
+ *   v_mad_u64_u32 (the field core's 32x32->64 multiply-add);
+ * kind MSM_MB_ADDC: the same with v_addc_co_u32 (the carry add);
+ *   for both, buf is a device buffer of at least 2048 * 256 * 8 bytes.
+ * kind MSM_MB_COPY: copies param bytes (a multiple of 16) from the first half
+ *   of buf to the second; buf_bytes >= 2 * param, buf 16-byte aligned.
+ * The caller times the launch on `stream`.  Errors: MSM_EINVAL, MSM_EHIP. */
+#define MSM_MB_MAD64 0
+#define MSM_MB_ADDC 1
+#define MSM_MB_COPY 2
+int msm_microbench(int kind, size_t param, void* buf, size_t buf_bytes, void* stream);
+
 /* HIP error code (hipError_t value) behind the last MSM_EHIP on this thread. */
 int msm_last_hip_error(void);
 

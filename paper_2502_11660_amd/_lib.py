@@ -20,6 +20,9 @@ MSM_FLAG_EXCEPT = 4
 MSM_FORM_XYTZ = 0
 MSM_FORM_XYU = 1
 MSM_RESULT_WORDS = 32
+MSM_MB_MAD64 = 0
+MSM_MB_ADDC = 1
+MSM_MB_COPY = 2
 
 # every exported symbol and its (restype, argtypes)
 _P = ctypes.c_void_p
@@ -39,6 +42,7 @@ SIGNATURES = {
     "msm_status_string": (ctypes.c_char_p, [_I]),
     "msm_constants": (_I, [_P, _SZ]),
     "msm_profile_enable": (_I, [_I]),
+    "msm_microbench": (_I, [_I, _SZ, _P, _SZ, _P]),
     "msm_profile_read": (_I, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(ctypes.c_int)]),
 }

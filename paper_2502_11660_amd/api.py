@@ -185,3 +185,10 @@ def profile_read(phase):
     _lib.check("msm_profile_read", _lib.lib().msm_profile_read(
         phase.encode(), ctypes.byref(tot), ctypes.byref(cnt)))
     return tot.value, cnt.value
+
+
+def microbench(kind, param, buf):
+    """Launch one microbenchmark kernel (see msm_microbench) on the current stream."""
+    _dev(buf, "buf")
+    _lib.check("msm_microbench", _lib.lib().msm_microbench(
+        kind, param, _ptr(buf), buf.numel() * 4, _stream()))

@@ -1,20 +1,26 @@
-"""Build the gfx950 HIP library in-tree: paper_2502_11660_amd/libmsm_gfx950.so."""
+"""Build the gfx950 HIP library in-tree: paper_2502_11660_amd/libmsm_gfx950.so.
 
+Each translation unit under csrc/ is compiled to an object file in parallel,
+then the objects are linked into one shared library.
+"""
+
+import concurrent.futures as cf
+import glob
 import os
 import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "msm.hip")
+CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmsm_gfx950.so")
+OBJ_DIR = os.path.join(ROOT, "_build")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # no packed-fp32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
@@ -28,12 +34,35 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose=True):
+def sources():
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+
+
+def build(verbose=True, jobs=None):
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    cc = hipcc()
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    cmds = []
+    objs = []
+    for src in sources():
+        obj = os.path.join(OBJ_DIR, os.path.basename(src)[:-4] + ".o")
+        objs.append(obj)
+        cmds.append([cc, *HIPCC_FLAGS, *inc, "-c", "-o", obj, src])
+    jobs = jobs or min(len(cmds), max(1, min(os.cpu_count() or 1, 16)))
+
+    def run(cmd):
+        if verbose:
+            print("[build]", " ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        for f in [ex.submit(run, c) for c in cmds]:
+            f.result()
     tmp = OUT + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-o", tmp, SRC]
+    link = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
-        print("[build]", " ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+        print("[build]", " ".join(link), flush=True)
+    subprocess.run(link, check=True)
     os.replace(tmp, OUT)
     return OUT
 

@@ -1,0 +1,125 @@
+// Declarations shared by the translation units of libmsm_gfx950.so.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/msm.h"
+#include "curve.hpp"
+#include "field.hpp"
+
+namespace msm {
+
+// Constants of the Weierstrass <-> twisted-Edwards map, Montgomery form:
+//   x_w = alpha u - 1,  y_w = beta v,  u = (1 + y_e)/(1 - y_e),  v = u / x_e
+constexpr uint32_t kAlpha[NL] = {0x8894e1e4u, 0x3fabdfd0u, 0xcc1f55aau, 0xcbf921ddu,
+                                 0x460edc0cu, 0xd17deff1u, 0x7897028du, 0xd394e81eu,
+                                 0x0912681au, 0xc29c995du, 0xaff9d568u, 0x01515e6cu};
+constexpr uint32_t kBeta[NL] = {0xa38cfd11u, 0xface0c97u, 0x0adb8383u, 0x8cc7c229u,
+                                0xd44ae9cbu, 0x4765cd5fu, 0x22354029u, 0x9ae986d8u,
+                                0x252ab9bdu, 0xc3dc7860u, 0xc8942395u, 0x00486011u};
+constexpr uint32_t kBetaOverAlpha[NL] = {0xead605e4u, 0xfb7c0ab8u, 0xe2752c7au, 0x363b93d1u,
+                                         0x144be536u, 0xd2246835u, 0x429f2077u, 0xeb8bf6ddu,
+                                         0x0234d423u, 0x3a9efda2u, 0xba0c72a4u, 0x013c7943u};
+// R^3 mod p: turns a plain inverse of a Montgomery value into Montgomery form
+constexpr uint32_t kR3[NL] = {0x8815de20u, 0x581f532fu, 0xbe329585u, 0xe50f4148u,
+                              0x0449f513u, 0x2be8b118u, 0xc804a20eu, 0x6a2a9516u,
+                              0x13590cb9u, 0x3f725407u, 0xc0e7dda5u, 0x01065ab4u};
+// conventional generator G of BLS12-377 G1, Weierstrass affine (Montgomery form)
+constexpr uint32_t kGx[NL] = {0x772451f4u, 0x260f33b9u, 0x169d5658u, 0xc54dd773u,
+                              0x69a510ddu, 0x5c1551c4u, 0x425e1698u, 0x761662e4u,
+                              0x6f065272u, 0xc97d78ccu, 0xb361fd4du, 0x00a41206u};
+constexpr uint32_t kGy[NL] = {0xb8cb81f3u, 0x8193961fu, 0x5f44adb8u, 0x00638d4cu,
+                              0xd4daf54au, 0xfafaf3dau, 0xd655cd18u, 0xc27849e2u,
+                              0x01d52814u, 0x2ec3ddb4u, 0x26303c71u, 0x007da933u};
+// G in prepared twisted-Edwards form (x_e, y_e, k x_e y_e), Montgomery form
+constexpr uint32_t kGteX[NL] = {0x654b417fu, 0x5bab21b3u, 0x1d3e1fe0u, 0x042fff8au,
+                                0xdf39dc37u, 0xb702072eu, 0x39426b02u, 0xa5625e78u,
+                                0xb51c7d03u, 0xbf2dc368u, 0x28ac3263u, 0x00b3ad90u};
+constexpr uint32_t kGteY[NL] = {0xef15101du, 0x3904973cu, 0xb1f14456u, 0xb45ed211u,
+                                0x5dfac94eu, 0x90a86b86u, 0xfe3945cdu, 0xcdb19c57u,
+                                0xef4f7097u, 0x972a8d46u, 0xa3d9cf77u, 0x00281a91u};
+constexpr uint32_t kGteU[NL] = {0x4f3f8d58u, 0x719243efu, 0x4a7b9d48u, 0xf744d1fcu,
+                                0xa77008dcu, 0x0ab712e3u, 0x1e09b26fu, 0x53f80798u,
+                                0xef3f9f1bu, 0x24125ab8u, 0xfb63f6d1u, 0x01959f77u};
+
+constexpr int SCALAR_BITS = 253;
+constexpr int SCALAR_WORDS = 8;
+
+inline unsigned grid_for(size_t n, unsigned block) { return (unsigned)((n + block - 1) / block); }
+
+// ---------------------------------------------------------------------------
+// error reporting and optional per-phase timing (msm_api.hip)
+// ---------------------------------------------------------------------------
+void set_last_hip_error(int e);
+
+#define HIPCHK(x)                         \
+  do {                                    \
+    hipError_t e_ = (x);                  \
+    if (e_ != hipSuccess) {               \
+      ::msm::set_last_hip_error((int)e_); \
+      return MSM_EHIP;                    \
+    }                                     \
+  } while (0)
+
+enum ProfTag { PT_SORT = 0, PT_ACCUM, PT_MERGE, PT_AGG, PT_HORNER, PT_COUNT };
+
+// Records HIP events around its lifetime on `st` while profiling is enabled.
+struct ProfScope {
+  bool active = false;
+  int tag = 0;
+  hipStream_t st = nullptr;
+  hipEvent_t a = nullptr;
+  ProfScope(int t, hipStream_t s);
+  ~ProfScope();
+};
+
+// ---------------------------------------------------------------------------
+// workspace plan of one MSM (msm_api.hip)
+// ---------------------------------------------------------------------------
+struct Plan {
+  int c = 0, W = 0;
+  size_t n = 0, M = 0, NW = 0, chunks = 0, nb = 0;
+  uint32_t K = 32;  // entries per accumulation chunk
+  // byte offsets into the workspace
+  size_t o_flags = 0, o_total = 0, o_maxspan = 0, o_hist = 0, o_cursor = 0, o_blocksums = 0,
+         o_key = 0, o_idx = 0, o_head = 0, o_tail = 0, o_buckets = 0, o_lvl0 = 0, o_lvl1 = 0,
+         o_wsum = 0, lvl_records = 0, bytes = 0;
+};
+
+int num_windows(int c);
+int default_window(size_t n);
+bool make_plan(size_t n, int c, Plan& pl);
+
+template <typename T>
+inline T* ws_at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+// ---------------------------------------------------------------------------
+// kernel launchers (each returns MSM_OK or MSM_EHIP)
+// ---------------------------------------------------------------------------
+// k_sort.hip: digits -> CSR offsets, sorted (key, idx); empty buckets set to
+// the identity; largest bucket span (in chunks) to ws maxspan
+int launch_sort(const Plan& pl, const uint32_t* scalars, uint32_t* buckets, void* ws,
+                hipStream_t st);
+// k_accum.hip: bucket accumulation and split-bucket merge
+int launch_accumulate(const Plan& pl, const uint32_t* xyu, uint32_t* buckets, void* ws,
+                      hipStream_t st);
+// k_agg.hip: bucket aggregation, group aggregation, affine result
+int launch_aggregate(const Plan& pl, const uint32_t* buckets, uint32_t* result, void* ws,
+                     hipStream_t st);
+// k_elementwise.hip
+int launch_fe_mul(const uint32_t* a, const uint32_t* b, uint32_t* out, uint32_t count,
+                  int canonical, hipStream_t st);
+int launch_padd(const uint32_t* a, const uint32_t* b, uint32_t* out, uint32_t count, int form,
+                hipStream_t st);
+int launch_prepare(const uint32_t* xy, const uint32_t* inf, uint32_t* xyu, uint32_t n,
+                   uint32_t* status, hipStream_t st);
+int launch_gen_points(const uint32_t* k, uint32_t* xy, uint32_t* inf, uint32_t n, hipStream_t st);
+int launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
+
+}  // namespace msm
