@@ -85,9 +85,10 @@ struct Plan {
   size_t n = 0, M = 0, NW = 0, chunks = 0, nb = 0;
   uint32_t K = 32;  // entries per accumulation chunk
   // byte offsets into the workspace
-  size_t o_flags = 0, o_total = 0, o_maxspan = 0, o_hist = 0, o_cursor = 0, o_blocksums = 0,
-         o_key = 0, o_idx = 0, o_head = 0, o_tail = 0, o_buckets = 0, o_lvl0 = 0, o_lvl1 = 0,
-         o_wsum = 0, lvl_records = 0, bytes = 0;
+  size_t ncounts = 0;  // digit-sort (partition, tile) count matrix size
+  size_t o_flags = 0, o_total = 0, o_maxspan = 0, o_hist = 0, o_counts = 0, o_blocksums = 0,
+         o_digits = 0, o_tmp = 0, o_key = 0, o_idx = 0, o_head = 0, o_tail = 0, o_buckets = 0,
+         o_lvl0 = 0, o_lvl1 = 0, o_wsum = 0, lvl_records = 0, bytes = 0;
 };
 
 int num_windows(int c);
@@ -104,6 +105,7 @@ inline T* ws_at(void* ws, size_t off) {
 // ---------------------------------------------------------------------------
 // k_sort.hip: digits -> CSR offsets, sorted (key, idx); empty buckets set to
 // the identity; largest bucket span (in chunks) to ws maxspan
+size_t sort_counts_size(int c, int W, size_t n);
 int launch_sort(const Plan& pl, const uint32_t* scalars, uint32_t* buckets, void* ws,
                 hipStream_t st);
 // k_accum.hip: bucket accumulation and split-bucket merge

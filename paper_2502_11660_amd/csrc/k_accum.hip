@@ -182,7 +182,8 @@ int launch_accumulate(const Plan& pl, const uint32_t* xyu, uint32_t* buckets, vo
   // a bucket holds at most n entries, so its span is at most ceil(n/K) chunks
   const size_t max_span = (pl.n + K - 1) / K + 1;
   if (max_span > SMALL_SPAN) {
-    const unsigned g = std::min<unsigned>(grid_for(pl.chunks, 256), 1024u);
+    // these launches return at once unless some bucket spans > SMALL_SPAN chunks
+    const unsigned g = std::min<unsigned>(grid_for(pl.chunks, 256), 64u);
     uint32_t steps = 0;
     while (((size_t)1 << steps) < max_span) ++steps;
     for (uint32_t t = 0; t < steps; ++t)

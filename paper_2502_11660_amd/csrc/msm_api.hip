@@ -83,9 +83,14 @@ bool make_plan(size_t n, int c, Plan& pl) {
   pl.n = n;
   pl.M = (size_t)pl.W << c;
   pl.NW = n * (size_t)pl.W;
-  pl.K = 32;
+  // accumulation chunk: about two resident waves' worth of lanes per SIMD
+  // (256 CUs x 4 SIMDs x 2 waves x 64 lanes = 131072), K in [16, 64]
+  pl.K = 16;
+  while (pl.K < 64 && pl.NW / (2 * pl.K) >= 2 * 131072) pl.K *= 2;
   pl.chunks = (pl.NW + pl.K - 1) / pl.K;
-  pl.nb = (pl.M + 4095) / 4096;
+  pl.ncounts = sort_counts_size(c, pl.W, n);
+  if (pl.ncounts == (size_t)-1) return false;
+  pl.nb = (pl.ncounts + 4095) / 4096;
   if (pl.nb > 4096) return false;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -97,8 +102,10 @@ bool make_plan(size_t n, int c, Plan& pl) {
   pl.o_total = take(4);
   pl.o_maxspan = take(4);
   pl.o_hist = take((pl.M + 1) * 4);
-  pl.o_cursor = take(pl.M * 4);
+  pl.o_counts = take(pl.ncounts * 4);
   pl.o_blocksums = take(4096 * 4);
+  pl.o_digits = take(pl.NW * 4);
+  pl.o_tmp = take(pl.NW * 8);
   pl.o_key = take(pl.NW * 4);
   pl.o_idx = take(pl.NW * 4);
   pl.o_head = take(pl.chunks * XYTZ_WORDS * 4);

@@ -160,3 +160,40 @@ def test_msm_full_size_closed_form(c):
     rows = H.unsoa(api.to_host(xy).reshape(24, n)[:, :64].reshape(-1), 2, 64)
     for i in range(0, 64, 8):
         assert rows[i] == points.fixed_base_mul(ks[i])
+
+
+def test_msm_skewed_partition_larger_than_lds_stage(oracle_pool):
+    """All scalars equal at n = 20000: one bucket per window holds every entry,
+    so the sort's partition exceeds its LDS stage and the accumulation's
+    split-bucket tree runs (spans of hundreds of chunks)."""
+    ks, pts = oracle_pool
+    n = 20000
+    sel_k = [ks[i % len(ks)] for i in range(n)]
+    sel_p = [pts[i % len(pts)] for i in range(n)]
+    s = 0x0123456789ABCDEF0123456789ABCDEF0123456789ABCDEF0123456789ABCDE % R_ORDER
+    xyu = _prepared(sel_p)
+    for c in (8, 13):
+        got, _ = _run(xyu, [s] * n, c)
+        assert got == msm.closed_form([s] * n, sel_k), c
+    # half the scalars equal, half random: mixed bucket sizes
+    sc = [s if i % 2 else inputs.words_to_int(r)
+          for i, r in enumerate(inputs.scalars_mod_r(99, n))]
+    got, _ = _run(xyu, sc, 11)
+    assert got == msm.closed_form(sc, sel_k)
+
+
+@pytest.mark.parametrize("c", [10, 13])
+def test_msm_quarter_million_closed_form(c):
+    """n = 2^18 GPU-generated points; c = 10 / 13 split digits into 6+4 / 6+7 bits."""
+    n = 1 << 18
+    seed = inputs.config_seed(3) + c
+    kw = inputs.nonzero_scalars_mod_r(seed, n, stream=3)
+    sw = inputs.scalars_mod_r(seed, n, stream=4)
+    xy, inf = api.gen_points(_dev(kw), n)
+    xyu, status = api.points_prepare(xy, n, inf=inf)
+    res = api.msm_run(xyu, _dev(sw), n, c)
+    got, flags = api.decode_result(api.to_host(res))
+    assert flags == 0 and int(api.to_host(status)[0]) == 0
+    ks = [inputs.words_to_int(r) for r in kw]
+    ss = [inputs.words_to_int(r) for r in sw]
+    assert got == msm.closed_form(ss, ks)
