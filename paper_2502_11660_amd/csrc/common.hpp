@@ -84,11 +84,18 @@ struct Plan {
   int c = 0, W = 0;
   size_t n = 0, M = 0, NW = 0, chunks = 0, nb = 0;
   uint32_t K = 32;  // entries per accumulation chunk
+  // Windows are processed in G groups of gw windows, top windows first, so
+  // that group aggregation of finished groups overlaps the accumulation of
+  // the next ones.  group_chunks bounds the accumulation chunks of a group.
+  int G = 1, gw = 1;
+  size_t group_chunks = 0;
+  int group_hi(int g) const { return W - 1 - g * gw; }
+  int group_lo(int g) const { int lo = W - (g + 1) * gw; return lo < 0 ? 0 : lo; }
   // byte offsets into the workspace
   size_t ncounts = 0;  // digit-sort (partition, tile) count matrix size
   size_t o_flags = 0, o_total = 0, o_maxspan = 0, o_hist = 0, o_counts = 0, o_blocksums = 0,
          o_digits = 0, o_tmp = 0, o_key = 0, o_idx = 0, o_head = 0, o_tail = 0, o_buckets = 0,
-         o_lvl0 = 0, o_lvl1 = 0, o_wsum = 0, lvl_records = 0, bytes = 0;
+         o_lvl0 = 0, o_lvl1 = 0, o_wsum = 0, o_qstate = 0, o_longlist = 0, lvl_records = 0, bytes = 0;
 };
 
 int num_windows(int c);
@@ -108,12 +115,15 @@ inline T* ws_at(void* ws, size_t off) {
 size_t sort_counts_size(int c, int W, size_t n);
 int launch_sort(const Plan& pl, const uint32_t* scalars, uint32_t* buckets, void* ws,
                 hipStream_t st);
-// k_accum.hip: bucket accumulation and split-bucket merge
-int launch_accumulate(const Plan& pl, const uint32_t* xyu, uint32_t* buckets, void* ws,
-                      hipStream_t st);
-// k_agg.hip: bucket aggregation, group aggregation, affine result
-int launch_aggregate(const Plan& pl, const uint32_t* buckets, uint32_t* result, void* ws,
-                     hipStream_t st);
+// k_accum.hip: bucket accumulation and split-bucket merge of window group g
+int launch_accumulate_group(const Plan& pl, int g, const uint32_t* xyu, uint32_t* buckets,
+                            void* ws, hipStream_t st);
+// k_agg.hip: bucket aggregation (window sums) of group g; group aggregation
+// steps over group g's windows; the affine result
+int launch_aggregate_group(const Plan& pl, int g, const uint32_t* buckets, void* ws,
+                           hipStream_t st);
+int launch_horner_group(const Plan& pl, int g, void* ws, hipStream_t st);
+int launch_finalize(const Plan& pl, uint32_t* result, void* ws, hipStream_t st);
 // k_elementwise.hip
 int launch_fe_mul(const uint32_t* a, const uint32_t* b, uint32_t* out, uint32_t count,
                   int canonical, hipStream_t st);

@@ -22,23 +22,28 @@ namespace {
 
 constexpr uint32_t SMALL_SPAN = 8;
 
+// The entries of one window group are [offsets[b0], offsets[b1]); chunk ch of
+// the group covers [E0 + ch K, min(E0 + (ch+1) K, E1)).  head/tail are the
+// group's own partial slots (indexed by ch).
+
 __global__ void __launch_bounds__(256) k_accum(const uint32_t* __restrict__ pts,
                                                const uint32_t* __restrict__ key,
                                                const uint32_t* __restrict__ idx,
-                                               const uint32_t* __restrict__ total, uint32_t K,
+                                               const uint32_t* __restrict__ offsets, uint32_t b0,
+                                               uint32_t b1, uint32_t K,
                                                uint32_t* __restrict__ buckets,
                                                uint32_t* __restrict__ head,
                                                uint32_t* __restrict__ tail) {
-  const uint32_t N = *total;
+  const uint32_t E0 = offsets[b0], E1 = offsets[b1];
   const uint32_t ch = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t s64 = (uint64_t)ch * K;
-  if (s64 >= N) return;
+  const uint64_t s64 = (uint64_t)E0 + (uint64_t)ch * K;
+  if (s64 >= E1) return;
   const uint32_t s = (uint32_t)s64;
-  const uint32_t e = (uint32_t)(s64 + K < N ? s64 + K : N);
+  const uint32_t e = (uint32_t)(s64 + K < E1 ? s64 + K : E1);
   const fe p2 = fe_const(kP2);
 
   uint32_t cur = key[s];
-  const bool open_left = (s > 0) && (key[s - 1] == cur);
+  const bool open_left = (s > E0) && (key[s - 1] == cur);
   bool first_seg = true;
   xytz acc = pt_identity();
   xyu P = ld_xyu(pts + (size_t)idx[s] * XYU_WORDS);
@@ -57,7 +62,7 @@ __global__ void __launch_bounds__(256) k_accum(const uint32_t* __restrict__ pts,
     acc = padd_mixed(acc, P, p2);
     P = Pn;
   }
-  const bool open_right = (e < N) && (key[e] == cur);
+  const bool open_right = (e < E1) && (key[e] == cur);
   uint32_t* dst;
   if (first_seg && open_left)
     dst = head + (size_t)ch * XYTZ_WORDS;
@@ -68,36 +73,44 @@ __global__ void __launch_bounds__(256) k_accum(const uint32_t* __restrict__ pts,
   st_xytz(dst, acc);
 }
 
-// chunk ch holds a tail partial: returns true and the bucket / end chunk
+// chunk ch holds a tail partial: returns true, the bucket and its last chunk
 __device__ __forceinline__ bool tail_of(const uint32_t* __restrict__ key,
-                                        const uint32_t* __restrict__ offsets, uint32_t N,
-                                        uint32_t K, uint32_t ch, uint32_t& b, uint32_t& c1) {
-  const uint64_t s64 = (uint64_t)ch * K;
-  if (s64 >= N) return false;
+                                        const uint32_t* __restrict__ offsets, uint32_t E0,
+                                        uint32_t E1, uint32_t K, uint32_t ch, uint32_t& b,
+                                        uint32_t& c1) {
+  const uint64_t s64 = (uint64_t)E0 + (uint64_t)ch * K;
+  if (s64 >= E1) return false;
   const uint32_t s = (uint32_t)s64;
-  const uint32_t e = (uint32_t)(s64 + K < N ? s64 + K : N);
+  const uint32_t e = (uint32_t)(s64 + K < E1 ? s64 + K : E1);
   const uint32_t last = key[e - 1];
-  if (!(e < N && key[e] == last)) return false;        // last piece ends here
-  if (s > 0 && key[s - 1] == key[s] && key[s] == last)  // whole chunk is a middle piece
+  if (!(e < E1 && key[e] == last)) return false;          // last piece ends here
+  if (s > E0 && key[s - 1] == key[s] && key[s] == last)    // whole chunk is a middle piece
     return false;
   b = last;
-  c1 = (offsets[b + 1] - 1) / K;
+  c1 = (offsets[b + 1] - 1 - E0) / K;
   return true;
 }
 
-// Split buckets with span <= SMALL_SPAN: one lane sums tail + heads.
+// Split buckets: one lane sums tail + heads when the span is at most
+// SMALL_SPAN chunks; longer spans (skewed inputs) are appended to a work list
+// for k_merge_long.
 __global__ void __launch_bounds__(256) k_merge_small(const uint32_t* __restrict__ key,
                                                      const uint32_t* __restrict__ offsets,
-                                                     const uint32_t* __restrict__ total,
-                                                     uint32_t K, const uint32_t* __restrict__ head,
+                                                     uint32_t b0, uint32_t b1, uint32_t K,
+                                                     const uint32_t* __restrict__ head,
                                                      const uint32_t* __restrict__ tail,
-                                                     uint32_t* __restrict__ buckets) {
-  const uint32_t N = *total;
+                                                     uint32_t* __restrict__ buckets,
+                                                     uint32_t* __restrict__ longlist) {
+  const uint32_t E0 = offsets[b0], E1 = offsets[b1];
   const uint32_t ch = blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t b, c1;
-  if (!tail_of(key, offsets, N, K, ch, b, c1)) return;
+  if (!tail_of(key, offsets, E0, E1, K, ch, b, c1)) return;
   const uint32_t span = c1 - ch;
-  if (span > SMALL_SPAN) return;
+  if (span > SMALL_SPAN) {
+    const uint32_t slot = atomicAdd(&longlist[0], 1u);
+    longlist[1 + slot] = ch;
+    return;
+  }
   const fe p2 = fe_const(kP2);
   xytz acc = ld_xytz(tail + (size_t)ch * XYTZ_WORDS);
   for (uint32_t j = 1; j <= span; ++j)
@@ -105,91 +118,71 @@ __global__ void __launch_bounds__(256) k_merge_small(const uint32_t* __restrict_
   st_xytz(buckets + (size_t)b * XYTZ_WORDS, acc);
 }
 
-// Tree step t for buckets spanning more than SMALL_SPAN chunks: chunk c of
-// such a bucket (c0 < c <= c1, its first piece continues the bucket) with
-// (c - c0 - 1) % 2^(t+1) == 0 adds head[c + 2^t] if that chunk still belongs
-// to the bucket.  Grid-stride over the chunks; exits at once when no bucket
-// is long.
-__global__ void __launch_bounds__(256) k_merge_step(const uint32_t* __restrict__ key,
-                                                    const uint32_t* __restrict__ offsets,
-                                                    const uint32_t* __restrict__ total,
-                                                    const uint32_t* __restrict__ maxspan,
-                                                    uint32_t K, uint32_t t,
-                                                    uint32_t* __restrict__ head) {
-  const uint32_t ms = *maxspan;
-  if (ms <= SMALL_SPAN || (1u << t) >= ms) return;
-  const uint32_t N = *total;
-  const uint32_t nchunks = (N + K - 1) / K;
+// Long split buckets, one block each: the block's threads sum strided heads
+// of the span, then fold their partial sums pairwise through LDS, and thread
+// 0 adds the tail.  Blocks take list entries in turn; an empty list costs one
+// read.
+constexpr int LONG_THREADS = 128;
+__global__ void __launch_bounds__(LONG_THREADS) k_merge_long(const uint32_t* __restrict__ key,
+                                                             const uint32_t* __restrict__ offsets,
+                                                             uint32_t b0, uint32_t K,
+                                                             const uint32_t* __restrict__ head,
+                                                             const uint32_t* __restrict__ tail,
+                                                             uint32_t* __restrict__ buckets,
+                                                             const uint32_t* __restrict__ longlist) {
+  __shared__ uint32_t part[LONG_THREADS][XYTZ_WORDS];
+  const uint32_t count = longlist[0];
+  const uint32_t E0 = offsets[b0];
   const fe p2 = fe_const(kP2);
-  for (uint32_t ch = blockIdx.x * blockDim.x + threadIdx.x; ch < nchunks;
-       ch += gridDim.x * blockDim.x) {
-    if (ch == 0) continue;
-    const uint32_t s = ch * K;
-    const uint32_t b = key[s];
-    if (key[s - 1] != b) continue;
-    const uint32_t c0 = offsets[b] / K;
-    const uint32_t c1 = (offsets[b + 1] - 1) / K;
-    if (c1 - c0 <= SMALL_SPAN) continue;
-    const uint32_t rel = ch - c0 - 1;
-    const uint32_t stride = 1u << t;
-    if ((rel & ((stride << 1) - 1)) != 0 || ch + stride > c1) continue;
-    uint32_t* mine = head + (size_t)ch * XYTZ_WORDS;
-    st_xytz(mine, padd_full(ld_xytz(mine), ld_xytz(head + (size_t)(ch + stride) * XYTZ_WORDS), p2));
-  }
-}
-
-// Long split buckets after the tree: bucket = tail[c0] + head[c0 + 1].
-__global__ void __launch_bounds__(256) k_merge_long(const uint32_t* __restrict__ key,
-                                                    const uint32_t* __restrict__ offsets,
-                                                    const uint32_t* __restrict__ total,
-                                                    const uint32_t* __restrict__ maxspan,
-                                                    uint32_t K, const uint32_t* __restrict__ head,
-                                                    const uint32_t* __restrict__ tail,
-                                                    uint32_t* __restrict__ buckets) {
-  if (*maxspan <= SMALL_SPAN) return;
-  const uint32_t N = *total;
-  const uint32_t nchunks = (N + K - 1) / K;
-  const fe p2 = fe_const(kP2);
-  for (uint32_t ch = blockIdx.x * blockDim.x + threadIdx.x; ch < nchunks;
-       ch += gridDim.x * blockDim.x) {
-    uint32_t b, c1;
-    if (!tail_of(key, offsets, N, K, ch, b, c1) || c1 - ch <= SMALL_SPAN) continue;
-    xytz a = ld_xytz(tail + (size_t)ch * XYTZ_WORDS);
-    xytz o = ld_xytz(head + (size_t)(ch + 1) * XYTZ_WORDS);
-    st_xytz(buckets + (size_t)b * XYTZ_WORDS, padd_full(a, o, p2));
+  for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
+    const uint32_t ch = longlist[1 + item];
+    const uint32_t e_last = E0 + (ch + 1) * K - 1;  // the tail's bucket ends after this chunk
+    const uint32_t b = key[e_last];
+    const uint32_t c1 = (offsets[b + 1] - 1 - E0) / K;
+    xytz acc = pt_identity();
+    for (uint32_t j = ch + 1 + threadIdx.x; j <= c1; j += LONG_THREADS)
+      acc = padd_full(acc, ld_xytz(head + (size_t)j * XYTZ_WORDS), p2);
+    st_xytz(part[threadIdx.x], acc);
+    __syncthreads();
+    for (uint32_t half = LONG_THREADS / 2; half >= 1; half >>= 1) {
+      if (threadIdx.x < half) {
+        xytz a = ld_xytz(part[threadIdx.x]);
+        xytz o = ld_xytz(part[threadIdx.x + half]);
+        st_xytz(part[threadIdx.x], padd_full(a, o, p2));
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      xytz t = ld_xytz(tail + (size_t)ch * XYTZ_WORDS);
+      st_xytz(buckets + (size_t)b * XYTZ_WORDS, padd_full(t, ld_xytz(part[0]), p2));
+    }
+    __syncthreads();
   }
 }
 
 }  // namespace
 
-int launch_accumulate(const Plan& pl, const uint32_t* xyu, uint32_t* buckets, void* ws,
-                      hipStream_t st) {
-  const uint32_t* total = ws_at<uint32_t>(ws, pl.o_total);
-  const uint32_t* maxspan = ws_at<uint32_t>(ws, pl.o_maxspan);
+int launch_accumulate_group(const Plan& pl, int g, const uint32_t* xyu, uint32_t* buckets,
+                            void* ws, hipStream_t st) {
   const uint32_t* offsets = ws_at<uint32_t>(ws, pl.o_hist);
   const uint32_t* key = ws_at<uint32_t>(ws, pl.o_key);
   const uint32_t* idx = ws_at<uint32_t>(ws, pl.o_idx);
-  uint32_t* head = ws_at<uint32_t>(ws, pl.o_head);
-  uint32_t* tail = ws_at<uint32_t>(ws, pl.o_tail);
+  uint32_t* head = ws_at<uint32_t>(ws, pl.o_head) + (size_t)g * pl.group_chunks * XYTZ_WORDS;
+  uint32_t* tail = ws_at<uint32_t>(ws, pl.o_tail) + (size_t)g * pl.group_chunks * XYTZ_WORDS;
+  uint32_t* longlist = ws_at<uint32_t>(ws, pl.o_longlist) + (size_t)g * (pl.group_chunks + 1);
   const uint32_t K = pl.K;
+  const uint32_t w_lo = (uint32_t)pl.group_lo(g), w_hi = (uint32_t)pl.group_hi(g);
+  const uint32_t b0 = w_lo << pl.c, b1 = (w_hi + 1) << pl.c;
+  const unsigned grid = grid_for(pl.group_chunks, 256);
+  int rc;
+  if ((rc = launch_fill_u32(longlist, 1, 0u, st)) != MSM_OK) return rc;
   {
     ProfScope prof(PT_ACCUM, st);
-    k_accum<<<grid_for(pl.chunks, 256), 256, 0, st>>>(xyu, key, idx, total, K, buckets, head, tail);
+    k_accum<<<grid, 256, 0, st>>>(xyu, key, idx, offsets, b0, b1, K, buckets, head, tail);
   }
   ProfScope prof(PT_MERGE, st);
-  k_merge_small<<<grid_for(pl.chunks, 256), 256, 0, st>>>(key, offsets, total, K, head, tail,
-                                                          buckets);
-  // a bucket holds at most n entries, so its span is at most ceil(n/K) chunks
-  const size_t max_span = (pl.n + K - 1) / K + 1;
-  if (max_span > SMALL_SPAN) {
-    // these launches return at once unless some bucket spans > SMALL_SPAN chunks
-    const unsigned g = std::min<unsigned>(grid_for(pl.chunks, 256), 64u);
-    uint32_t steps = 0;
-    while (((size_t)1 << steps) < max_span) ++steps;
-    for (uint32_t t = 0; t < steps; ++t)
-      k_merge_step<<<g, 256, 0, st>>>(key, offsets, total, maxspan, K, t, head);
-    k_merge_long<<<g, 256, 0, st>>>(key, offsets, total, maxspan, K, head, tail, buckets);
-  }
+  k_merge_small<<<grid, 256, 0, st>>>(key, offsets, b0, b1, K, head, tail, buckets, longlist);
+  k_merge_long<<<64, LONG_THREADS, 0, st>>>(key, offsets, b0, K, head, tail, buckets, longlist);
   HIPCHK(hipGetLastError());
   return MSM_OK;
 }

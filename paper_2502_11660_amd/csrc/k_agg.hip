@@ -30,14 +30,15 @@ __device__ __forceinline__ size_t rec_index(uint32_t w, uint32_t nodes, uint32_t
 
 // One level h -> h+1, one output record per lane.
 __global__ void __launch_bounds__(256) k_tree_level(const uint32_t* __restrict__ in, uint32_t h,
-                                                    uint32_t nodes_in, uint32_t W,
-                                                    uint32_t* __restrict__ out, int to_u) {
+                                                    uint32_t nodes_in, uint32_t w_lo,
+                                                    uint32_t w_cnt, uint32_t* __restrict__ out,
+                                                    int to_u) {
   const uint32_t nodes_out = nodes_in >> 1, slots_in = h + 1, slots_out = h + 2;
   const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= (uint64_t)W * nodes_out * slots_out) return;
+  if (g >= (uint64_t)w_cnt * nodes_out * slots_out) return;
   const uint32_t s = (uint32_t)(g % slots_out);
   const uint32_t t = (uint32_t)(g / slots_out);
-  const uint32_t n = t % nodes_out, w = t / nodes_out;
+  const uint32_t n = t % nodes_out, w = w_lo + t / nodes_out;
   const uint32_t* L = in + rec_index(w, nodes_in, 2 * n, slots_in, 0) * XYTZ_WORDS;
   const uint32_t* R = L + (size_t)slots_in * XYTZ_WORDS;
   const fe p2 = fe_const(kP2);
@@ -54,15 +55,16 @@ __global__ void __launch_bounds__(256) k_tree_level(const uint32_t* __restrict__
 
 // Same level, four lanes per output record.
 __global__ void __launch_bounds__(256) k_tree_level_quad(const uint32_t* __restrict__ in, uint32_t h,
-                                                         uint32_t nodes_in, uint32_t W,
+                                                         uint32_t nodes_in, uint32_t w_lo,
+                                                         uint32_t w_cnt,
                                                          uint32_t* __restrict__ out, int to_u) {
   const uint32_t nodes_out = nodes_in >> 1, slots_in = h + 1, slots_out = h + 2;
   const uint64_t g = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
   // whole quads only: the task count test is uniform across a quad
-  if (g >= (uint64_t)W * nodes_out * slots_out) return;
+  if (g >= (uint64_t)w_cnt * nodes_out * slots_out) return;
   const uint32_t s = (uint32_t)(g % slots_out);
   const uint32_t t = (uint32_t)(g / slots_out);
-  const uint32_t n = t % nodes_out, w = t / nodes_out;
+  const uint32_t n = t % nodes_out, w = w_lo + t / nodes_out;
   const uint32_t* L = in + rec_index(w, nodes_in, 2 * n, slots_in, 0) * XYTZ_WORDS;
   const uint32_t* R = L + (size_t)slots_in * XYTZ_WORDS;
   const fe p2 = fe_const(kP2);
@@ -81,10 +83,11 @@ __global__ void __launch_bounds__(256) k_tree_level_quad(const uint32_t* __restr
 // root), by Horner's rule on one quad.  Writes S_w as XYTZ (record 2w) and
 // XYUZ (record 2w + 1).
 __global__ void __launch_bounds__(64) k_window_combine(const uint32_t* __restrict__ root,
-                                                       uint32_t c, uint32_t W,
+                                                       uint32_t c, uint32_t w_lo, uint32_t w_cnt,
                                                        uint32_t* __restrict__ wsum) {
-  const uint32_t w = (blockIdx.x * blockDim.x + threadIdx.x) >> 2;
-  if (w >= W) return;
+  const uint32_t wq = (blockIdx.x * blockDim.x + threadIdx.x) >> 2;
+  if (wq >= w_cnt) return;
+  const uint32_t w = w_lo + wq;
   const fe p2 = fe_const(kP2);
   const uint32_t* V = root + (size_t)w * (c + 1) * XYTZ_WORDS;
   fe acc = quad_add_u(quad_identity(), quad_ld(V + (size_t)(c - 1) * XYTZ_WORDS), p2);
@@ -96,24 +99,35 @@ __global__ void __launch_bounds__(64) k_window_combine(const uint32_t* __restric
   quad_st(wsum + (size_t)(2 * w + 1) * XYTZ_WORDS, quad_to_u(acc));
 }
 
-// Group aggregation Q = sum_w 2^(w c) S_w by Horner's rule on one quad, then
-// the affine Weierstrass result (one lane).
-__global__ void __launch_bounds__(64) k_horner(const uint32_t* __restrict__ wsum, uint32_t W,
-                                               uint32_t c, const uint32_t* __restrict__ flags,
-                                               uint32_t* __restrict__ result) {
+// Group aggregation Q = sum_w 2^(w c) S_w by Horner's rule on one quad, over
+// the windows w_hi down to w_lo of one group; the running value Q is kept in
+// a record between groups (the top window starts it).
+__global__ void __launch_bounds__(64) k_horner_steps(const uint32_t* __restrict__ wsum,
+                                                     uint32_t W, uint32_t c, uint32_t w_lo,
+                                                     uint32_t w_hi, uint32_t* __restrict__ state) {
   if (blockIdx.x != 0 || threadIdx.x >= 4) return;
   const fe p2 = fe_const(kP2);
-  fe q = quad_ld(wsum + (size_t)(2 * (W - 1)) * XYTZ_WORDS);
-  for (int w = (int)W - 2; w >= 0; --w) {
+  int w = (int)w_hi;
+  fe q;
+  if (w_hi == W - 1) {
+    q = quad_ld(wsum + (size_t)(2 * w) * XYTZ_WORDS);
+    --w;
+  } else {
+    q = quad_ld(state);
+  }
+  for (; w >= (int)w_lo; --w) {
     for (uint32_t t = 0; t < c; ++t) q = quad_dbl(q, p2);
     q = quad_add_u(q, quad_ld(wsum + (size_t)(2 * w + 1) * XYTZ_WORDS), p2);
   }
-  xytz Q;
-  Q.X = qbcast<0>(q);
-  Q.Y = qbcast<1>(q);
-  Q.T = qbcast<2>(q);
-  Q.Z = qbcast<3>(q);
-  if (threadIdx.x != 0) return;
+  quad_st(state, q);
+}
+
+// The affine Weierstrass result of the group-aggregation record.
+__global__ void __launch_bounds__(64) k_finalize(const uint32_t* __restrict__ state,
+                                                 const uint32_t* __restrict__ flags,
+                                                 uint32_t* __restrict__ result) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  xytz Q = ld_xytz(state);
   fe xw, yw;
   bool fin = te_to_weierstrass(Q, xw, yw);
 #pragma unroll
@@ -131,33 +145,46 @@ constexpr uint64_t QUAD_BELOW = 16384;
 
 }  // namespace
 
-int launch_aggregate(const Plan& pl, const uint32_t* buckets, uint32_t* result, void* ws,
-                     hipStream_t st) {
-  const uint32_t W = (uint32_t)pl.W, c = (uint32_t)pl.c;
+int launch_aggregate_group(const Plan& pl, int g, const uint32_t* buckets, void* ws,
+                           hipStream_t st) {
+  const uint32_t c = (uint32_t)pl.c;
+  const uint32_t w_lo = (uint32_t)pl.group_lo(g), w_cnt = (uint32_t)(pl.group_hi(g) - pl.group_lo(g) + 1);
   uint32_t* lv[2] = {ws_at<uint32_t>(ws, pl.o_lvl0), ws_at<uint32_t>(ws, pl.o_lvl1)};
   uint32_t* wsum = ws_at<uint32_t>(ws, pl.o_wsum);
-  {
-    ProfScope prof(PT_AGG, st);
-    const uint32_t* in = buckets;
-    uint32_t nodes = 1u << c;
-    for (uint32_t h = 0; h < c; ++h) {
-      uint32_t* out = lv[h & 1];
-      const uint64_t outs = (uint64_t)W * (nodes >> 1) * (h + 2);
-      const int to_u = (h + 1 == c) ? 1 : 0;
-      if (outs >= QUAD_BELOW)
-        k_tree_level<<<(unsigned)((outs + 255) / 256), 256, 0, st>>>(in, h, nodes, W, out, to_u);
-      else
-        k_tree_level_quad<<<(unsigned)((4 * outs + 255) / 256), 256, 0, st>>>(in, h, nodes, W, out,
-                                                                             to_u);
-      in = out;
-      nodes >>= 1;
-    }
-    k_window_combine<<<grid_for(4 * (size_t)W, 64), 64, 0, st>>>(in, c, W, wsum);
+  ProfScope prof(PT_AGG, st);
+  const uint32_t* in = buckets;
+  uint32_t nodes = 1u << c;
+  for (uint32_t h = 0; h < c; ++h) {
+    uint32_t* out = lv[h & 1];
+    const uint64_t outs = (uint64_t)w_cnt * (nodes >> 1) * (h + 2);
+    const int to_u = (h + 1 == c) ? 1 : 0;
+    if (outs >= QUAD_BELOW)
+      k_tree_level<<<(unsigned)((outs + 255) / 256), 256, 0, st>>>(in, h, nodes, w_lo, w_cnt, out,
+                                                                   to_u);
+    else
+      k_tree_level_quad<<<(unsigned)((4 * outs + 255) / 256), 256, 0, st>>>(in, h, nodes, w_lo,
+                                                                           w_cnt, out, to_u);
+    in = out;
+    nodes >>= 1;
   }
-  {
-    ProfScope prof(PT_HORNER, st);
-    k_horner<<<1, 64, 0, st>>>(wsum, W, c, ws_at<uint32_t>(ws, pl.o_flags), result);
-  }
+  k_window_combine<<<grid_for(4 * (size_t)w_cnt, 64), 64, 0, st>>>(in, c, w_lo, w_cnt, wsum);
+  HIPCHK(hipGetLastError());
+  return MSM_OK;
+}
+
+int launch_horner_group(const Plan& pl, int g, void* ws, hipStream_t st) {
+  ProfScope prof(PT_HORNER, st);
+  k_horner_steps<<<1, 64, 0, st>>>(ws_at<uint32_t>(ws, pl.o_wsum), (uint32_t)pl.W, (uint32_t)pl.c,
+                                   (uint32_t)pl.group_lo(g), (uint32_t)pl.group_hi(g),
+                                   ws_at<uint32_t>(ws, pl.o_qstate));
+  HIPCHK(hipGetLastError());
+  return MSM_OK;
+}
+
+int launch_finalize(const Plan& pl, uint32_t* result, void* ws, hipStream_t st) {
+  ProfScope prof(PT_HORNER, st);
+  k_finalize<<<1, 64, 0, st>>>(ws_at<uint32_t>(ws, pl.o_qstate), ws_at<uint32_t>(ws, pl.o_flags),
+                               result);
   HIPCHK(hipGetLastError());
   return MSM_OK;
 }

@@ -3,7 +3,9 @@
 // other translation units on the caller's stream.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -40,6 +42,47 @@ hipEvent_t prof_event() {
 }
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------------------------------
+// Internal streams for the window-group pipeline.  msm_run forks from the
+// caller's stream: accumulation stays on the caller's stream, bucket
+// aggregation of finished groups runs on stream `agg`, the group-aggregation
+// (Horner) steps on stream `hor`; the caller's stream finally waits for
+// `hor`.  All streams have the default priority.  A set is held (locked) only
+// while one call enqueues its work; a few sets per device let concurrent
+// callers on different streams overlap.
+// ---------------------------------------------------------------------------
+struct StreamSet {
+  std::mutex mu;
+  bool init = false;
+  hipStream_t agg = nullptr, hor = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  std::vector<hipEvent_t> accdone, aggdone;  // per window group
+};
+
+constexpr int kSetsPerDevice = 4;
+constexpr int kMaxDevices = 16;
+StreamSet g_sets[kMaxDevices][kSetsPerDevice];
+std::atomic<unsigned> g_set_rr{0};
+
+int ensure_events(std::vector<hipEvent_t>& v, size_t n) {
+  while (v.size() < n) {
+    hipEvent_t e = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    v.push_back(e);
+  }
+  return MSM_OK;
+}
+
+int init_set(StreamSet& ss) {
+  if (ss.init) return MSM_OK;
+  HIPCHK(hipStreamCreateWithFlags(&ss.agg, hipStreamNonBlocking));
+  HIPCHK(hipStreamCreateWithFlags(&ss.hor, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&ss.join, hipEventDisableTiming));
+  ss.init = true;
+  return MSM_OK;
+}
 }  // namespace
 
 void set_last_hip_error(int e) { g_last_hip = e; }
@@ -83,11 +126,19 @@ bool make_plan(size_t n, int c, Plan& pl) {
   pl.n = n;
   pl.M = (size_t)pl.W << c;
   pl.NW = n * (size_t)pl.W;
-  // accumulation chunk: about two resident waves' worth of lanes per SIMD
-  // (256 CUs x 4 SIMDs x 2 waves x 64 lanes = 131072), K in [16, 64]
+  // window groups (tunable through MSM_WINDOW_GROUPS; default one group)
+  int want_groups = 1;
+  if (const char* e = std::getenv("MSM_WINDOW_GROUPS")) want_groups = std::max(1, std::atoi(e));
+  want_groups = std::min(want_groups, pl.W);
+  pl.gw = (pl.W + want_groups - 1) / want_groups;
+  pl.G = (pl.W + pl.gw - 1) / pl.gw;
+  // accumulation chunk: a group's launch keeps about 2 waves per SIMD busy
+  // (256 CUs x 4 SIMDs x 2 waves x 64 lanes = 131072 lanes), K in [16, 64]
+  const size_t group_entries = n * (size_t)pl.gw;
   pl.K = 16;
-  while (pl.K < 64 && pl.NW / (2 * pl.K) >= 2 * 131072) pl.K *= 2;
-  pl.chunks = (pl.NW + pl.K - 1) / pl.K;
+  while (pl.K < 64 && group_entries / (2 * pl.K) >= 131072) pl.K *= 2;
+  pl.group_chunks = (group_entries + pl.K - 1) / pl.K;
+  pl.chunks = pl.group_chunks * pl.G;
   pl.ncounts = sort_counts_size(c, pl.W, n);
   if (pl.ncounts == (size_t)-1) return false;
   pl.nb = (pl.ncounts + 4095) / 4096;
@@ -115,6 +166,8 @@ bool make_plan(size_t n, int c, Plan& pl) {
   pl.o_lvl0 = take(pl.lvl_records * XYTZ_WORDS * 4);
   pl.o_lvl1 = take(pl.lvl_records * XYTZ_WORDS * 4);
   pl.o_wsum = take(2 * (size_t)pl.W * XYTZ_WORDS * 4);
+  pl.o_qstate = take(XYTZ_WORDS * 4);
+  pl.o_longlist = take((size_t)pl.G * (pl.group_chunks + 1) * 4);
   pl.bytes = o;
   return true;
 }
@@ -185,7 +238,9 @@ int msm_bucket_accumulate(const uint32_t* xyu, const uint32_t* scalars, size_t n
     rc = launch_sort(pl, scalars, buckets, ws, st);
   }
   if (rc != MSM_OK) return rc;
-  return launch_accumulate(pl, xyu, buckets, ws, st);
+  for (int g = 0; g < pl.G; ++g)
+    if ((rc = launch_accumulate_group(pl, g, xyu, buckets, ws, st)) != MSM_OK) return rc;
+  return MSM_OK;
 }
 
 int msm_run(const uint32_t* xyu, const uint32_t* scalars, size_t n, int c, uint32_t* result,
@@ -203,8 +258,37 @@ int msm_run(const uint32_t* xyu, const uint32_t* scalars, size_t n, int c, uint3
     rc = launch_sort(pl, scalars, buckets, ws, st);
   }
   if (rc != MSM_OK) return rc;
-  if ((rc = launch_accumulate(pl, xyu, buckets, ws, st)) != MSM_OK) return rc;
-  return launch_aggregate(pl, buckets, result, ws, st);
+  if (pl.G == 1) {
+    // one group: nothing to overlap, stay on the caller's stream
+    if ((rc = launch_accumulate_group(pl, 0, xyu, buckets, ws, st)) != MSM_OK) return rc;
+    if ((rc = launch_aggregate_group(pl, 0, buckets, ws, st)) != MSM_OK) return rc;
+    if ((rc = launch_horner_group(pl, 0, ws, st)) != MSM_OK) return rc;
+    return launch_finalize(pl, result, ws, st);
+  }
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return MSM_EINVAL;
+  StreamSet& ss = g_sets[dev][g_set_rr.fetch_add(1) % kSetsPerDevice];
+  std::lock_guard<std::mutex> lock(ss.mu);
+  if ((rc = init_set(ss)) != MSM_OK) return rc;
+  if ((rc = ensure_events(ss.accdone, pl.G)) != MSM_OK) return rc;
+  if ((rc = ensure_events(ss.aggdone, pl.G)) != MSM_OK) return rc;
+  HIPCHK(hipEventRecord(ss.fork, st));
+  HIPCHK(hipStreamWaitEvent(ss.agg, ss.fork, 0));
+  HIPCHK(hipStreamWaitEvent(ss.hor, ss.fork, 0));
+  for (int g = 0; g < pl.G; ++g) {
+    if ((rc = launch_accumulate_group(pl, g, xyu, buckets, ws, st)) != MSM_OK) return rc;
+    HIPCHK(hipEventRecord(ss.accdone[g], st));
+    HIPCHK(hipStreamWaitEvent(ss.agg, ss.accdone[g], 0));
+    if ((rc = launch_aggregate_group(pl, g, buckets, ws, ss.agg)) != MSM_OK) return rc;
+    HIPCHK(hipEventRecord(ss.aggdone[g], ss.agg));
+    HIPCHK(hipStreamWaitEvent(ss.hor, ss.aggdone[g], 0));
+    if ((rc = launch_horner_group(pl, g, ws, ss.hor)) != MSM_OK) return rc;
+  }
+  if ((rc = launch_finalize(pl, result, ws, ss.hor)) != MSM_OK) return rc;
+  HIPCHK(hipEventRecord(ss.join, ss.hor));
+  HIPCHK(hipStreamWaitEvent(st, ss.join, 0));
+  return MSM_OK;
 }
 
 int msm_profile_enable(int on) {
