@@ -243,7 +243,7 @@ def main():
     sweep = {}
     cs = [args.c] if args.c else C_SWEEP
     for c in cs:
-        ws = api.workspace(n, c, dev)
+        ws = api.workspace(n, c, device=dev)
         res = api.words(api.MSM_RESULT_WORDS, dev)
         fn = lambda: api.msm_run(xyu, s_dev, n, c, result=res, ws=ws)
         fn()
@@ -252,7 +252,7 @@ def main():
         print("[bench] c=%d: %.3f ms" % (c, sweep[c]), file=sys.stderr, flush=True)
     best_c = min(sweep, key=sweep.get)
 
-    ws = api.workspace(n, best_c, dev)
+    ws = api.workspace(n, best_c, device=dev)
     res = api.words(api.MSM_RESULT_WORDS, dev)
     step = lambda: api.msm_run(xyu, s_dev, n, best_c, result=res, ws=ws)
     for _ in range(args.warmup):

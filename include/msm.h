@@ -59,6 +59,22 @@ extern "C" {
 
 #define MSM_RESULT_WORDS 32 /* x[12], y[12], inf, flags, 6 reserved */
 
+/* Digit encodings of the scalars (Sec. II-C slices the scalars into c-bit
+ * windows and assigns each point to the bucket of its slice value).
+ *  MSM_DIGITS_UNSIGNED: the plain slices d_w = (s >> w c) mod 2^c,
+ *    W = ceil(253 / c) windows, 2^c buckets per window, bucket b = d_w
+ *    (bucket 0 stays the identity).
+ *  MSM_DIGITS_SIGNED: the slices recoded into d_w in [-2^(c-1), 2^(c-1)] with
+ *    s = sum_w d_w 2^(w c): from the lowest window up, a slice plus the
+ *    incoming carry that reaches 2^(c-1) becomes d_w = v - 2^c with a carry of
+ *    one into the next window; the top window is never recoded.
+ *    W = ceil(254 / c) windows; a point with d_w != 0 is added with the sign
+ *    of d_w to bucket m = |d_w| - 1, 2^(c-1) buckets per window, and the window
+ *    sum weights bucket m by m + 1.  Same MSM, half the buckets to aggregate.
+ *    Requires c >= 2. */
+#define MSM_DIGITS_SIGNED 0
+#define MSM_DIGITS_UNSIGNED 1
+
 /* Batched point addition out_i = a_i + b_i (Sec. II-D; the paper's "task").
  * a_xytz: SoA, 4 coordinates x 12 words x count.  b: SoA, 4 coordinates
  * (MSM_FORM_XYTZ, complete addition) or 3 coordinates (MSM_FORM_XYU, mixed
@@ -95,38 +111,123 @@ int msm_points_prepare(const uint32_t* xy_std, const uint32_t* inf, uint32_t* xy
  * Errors: MSM_EINVAL for null pointers or n = 0. */
 int msm_gen_points(const uint32_t* k, size_t n, uint32_t* xy_std, uint32_t* inf, void* stream);
 
-/* Number of window digits W = ceil(253 / c) for window width c. */
-int msm_num_windows(int c);
+/* Number of windows W for window width c and a digit encoding (0 when c is
+ * out of range for the encoding). */
+int msm_num_windows(int c, int encoding);
 
 /* Workspace (device bytes) needed by msm_bucket_accumulate / msm_run for n
- * points and window width c (c = 0: the width msm_run would pick).  Returns 0
- * for invalid arguments. */
-size_t msm_workspace_bytes(size_t n, int c);
+ * points, window width c (c = 0: the width msm_run would pick) and a digit
+ * encoding.  Returns 0 for invalid arguments. */
+size_t msm_workspace_bytes(size_t n, int c, int encoding);
 
 /* Window width msm_run picks for n points when called with c = 0. */
 int msm_default_window(size_t n);
 
-/* Bucket accumulation (Sec. II-C): B[w][b] = sum of P_i whose w-th c-bit
- * digit of s_i equals b, for w < W = ceil(253/c), 0 <= b < 2^c (bucket 0
- * holds the identity).  xyu: AoS prepared points (msm_points_prepare).
- * scalars: 8 words per scalar.  buckets: AoS XYTZ records, record index
- * w*2^c + b, Montgomery form, lazily reduced (< 2p; compare after
- * normalisation -- any projective multiple is the same point).
- * ws: device workspace of ws_bytes >= msm_workspace_bytes(n, c); word 0 of ws
- * receives the status flags (MSM_FLAG_RANGE).
- * Errors: MSM_EINVAL (null, n = 0, n >= 2^26, c not in [1, 20]),
- * MSM_ENOSPC, MSM_EHIP. */
+/* Bucket accumulation (Sec. II-C).  With unsigned digits B[w][b] = sum of
+ * the P_i whose w-th digit d_w(s_i) equals b, 0 <= b < 2^c (bucket 0 holds
+ * the identity); with signed digits B[w][m] = sum of sign(d_w(s_i)) P_i over
+ * the i with |d_w(s_i)| = m + 1, 0 <= m < 2^(c-1).  xyu: AoS prepared points
+ * (msm_points_prepare).  scalars: 8 words per scalar.  buckets: AoS XYTZ
+ * records, record index w * (buckets per window) + bucket, Montgomery form,
+ * lazily reduced (< 2p; compare after normalisation -- any projective
+ * multiple is the same point).  ws: device workspace of
+ * ws_bytes >= msm_workspace_bytes(n, c, encoding); word 0 of ws receives the
+ * status flags (MSM_FLAG_RANGE).
+ * Errors: MSM_EINVAL (null, n = 0, n >= 2^26, c not in [1, 20] -- [2, 20]
+ * for signed digits -- or an unknown encoding), MSM_ENOSPC, MSM_EHIP. */
 int msm_bucket_accumulate(const uint32_t* xyu, const uint32_t* scalars, size_t n, int c,
-                          uint32_t* buckets, void* ws, size_t ws_bytes, void* stream);
+                          int encoding, uint32_t* buckets, void* ws, size_t ws_bytes,
+                          void* stream);
 
 /* Full MSM: result = sum_i s_i P_i (Sec. II-C), Pippenger with window width
- * c (c = 0 picks msm_default_window(n)).  result: MSM_RESULT_WORDS device
- * words: x[12], y[12] (Weierstrass affine, ordinary form, canonical), inf
- * (1 if the sum is the point at infinity, then x = y = 0), flags
- * (MSM_FLAG_RANGE).  Other arguments as for msm_bucket_accumulate.
- * Errors as for msm_bucket_accumulate. */
-int msm_run(const uint32_t* xyu, const uint32_t* scalars, size_t n, int c, uint32_t* result,
-            void* ws, size_t ws_bytes, void* stream);
+ * c (c = 0 picks msm_default_window(n)) and the given digit encoding.
+ * result: MSM_RESULT_WORDS device words: x[12], y[12] (Weierstrass affine,
+ * ordinary form, canonical), inf (1 if the sum is the point at infinity, then
+ * x = y = 0), flags (MSM_FLAG_RANGE).  Other arguments as for
+ * msm_bucket_accumulate.  Errors as for msm_bucket_accumulate. */
+int msm_run(const uint32_t* xyu, const uint32_t* scalars, size_t n, int c, int encoding,
+            uint32_t* result, void* ws, size_t ws_bytes, void* stream);
+
+/* Batched MSMs: many independent MSMs of different sizes as one launch
+ * sequence (Sec. II-C per job; running many independent units side by side
+ * is the paper's way of scaling PADD throughput, Sec. IV).  Jobs with the
+ * same window width form a class; each class runs as one pipeline whose
+ * kernels cover every window of every job of the class, and the classes run
+ * concurrently on internal streams forked from the caller's stream.
+ *
+ * msm_job: device pointers owned by the caller (prepared points, scalars,
+ * MSM_RESULT_WORDS result words), n >= 1 points, window width c (0 = the
+ * msm_default_window(n) choice).  A batch keeps the pointers: between runs
+ * the caller may rewrite the scalars and points in place, not move them.
+ *
+ * msm_batch_workspace_bytes: device bytes a batch of these jobs needs
+ *   (0 for invalid jobs).
+ * msm_batch_create: validates and plans the jobs, copies their tables into
+ *   ws (a synchronous host-to-device copy; ws must stay allocated and
+ *   untouched until msm_batch_destroy) and creates the internal streams.
+ *   use_graph != 0: the first msm_batch_run captures the batch's launches
+ *   into a HIP graph and every run launches that graph.  *out receives the
+ *   batch handle (host memory owned by the library).
+ * msm_batch_run: enqueues one run of every job on `stream` (results valid
+ *   once the stream reaches them).  Runs of one batch must not overlap.
+ * msm_batch_destroy: waits for the batch's work, frees the handle, its
+ *   streams and its graph; NULL is accepted.
+ * Errors: MSM_EINVAL (null pointers, njobs = 0, a job with n = 0 or an
+ * invalid c, more than 2^26 points or 2^31 digits per class), MSM_ENOSPC,
+ * MSM_EHIP. */
+typedef struct msm_job {
+  const uint32_t* xyu;
+  const uint32_t* scalars;
+  uint32_t* result;
+  size_t n;
+  int c;
+} msm_job;
+
+typedef struct msm_batch msm_batch;
+
+size_t msm_batch_workspace_bytes(const msm_job* jobs, size_t njobs, int encoding);
+int msm_batch_create(const msm_job* jobs, size_t njobs, int encoding, void* ws, size_t ws_bytes,
+                     int use_graph, msm_batch** out);
+int msm_batch_run(msm_batch* batch, void* stream);
+int msm_batch_destroy(msm_batch* batch);
+
+/* MSM server: a request loop for MSMs that arrive over time (continuous
+ * batching at request granularity; the paper computes one MSM at a time, so
+ * this is an addition for serving many of them on one GPU).
+ *
+ * msm_server_create: allocates an arena of hbm_budget_bytes device bytes (the
+ *   server's only device allocation) and `streams` (1..16) streams of default
+ *   priority; every request uses the given digit encoding.  *out receives the
+ *   handle (host memory owned by the library).
+ * msm_server_submit: queues one MSM (job as for msm_batch_create; c = 0
+ *   picks msm_default_window(n)).  Its workspace (msm_workspace_bytes) is its
+ *   footprint: it is admitted -- launched on the stream with the fewest
+ *   requests in flight -- as soon as that much of the arena is free and no
+ *   earlier request is still waiting (FIFO).  The job's buffers must stay
+ *   valid until the request is reported finished.  *ticket receives the
+ *   request's id (1, 2, ... in submission order).  MSM_ENOSPC when the
+ *   footprint exceeds the whole budget (nothing is queued).
+ * msm_server_progress: non-blocking; retires requests whose work has
+ *   finished (their results are then valid), admits waiting ones, and writes
+ *   up to cap finished tickets (oldest first) to the HOST array done, their
+ *   number to *ndone.  Tickets not returned stay for the next call.
+ * msm_server_drain: blocks until every submitted request has finished.
+ * msm_server_stats: requests in flight, requests waiting, arena bytes in use
+ *   (any output may be NULL).
+ * msm_server_destroy: waits for the work in flight, frees the arena, the
+ *   streams and the handle; NULL is accepted.
+ * A server is driven from one host thread at a time.
+ * Errors: MSM_EINVAL (null pointers, invalid job or arguments), MSM_ENOSPC,
+ * MSM_EHIP. */
+typedef struct msm_server msm_server;
+
+int msm_server_create(size_t hbm_budget_bytes, int streams, int encoding, msm_server** out);
+int msm_server_submit(msm_server* server, const msm_job* job, uint64_t* ticket);
+int msm_server_progress(msm_server* server, uint64_t* done, size_t cap, size_t* ndone);
+int msm_server_drain(msm_server* server);
+int msm_server_stats(msm_server* server, size_t* in_flight, size_t* queued,
+                     size_t* bytes_in_use);
+int msm_server_destroy(msm_server* server);
 
 /* Per-phase timing for measurement.  While enabled, each call records HIP
  * events on its own stream around its phases: "sort" (histogram, scan,

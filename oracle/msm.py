@@ -12,11 +12,16 @@ result (group aggregation).  Reading of the slicing: unsigned c-bit digits,
 digit 0 contributes nothing, the top window holds the remaining
 253 mod c bits.
 
+A signed-digit encoding of the same windows is also given (it is not in the
+paper; it gives the same MSM with half as many buckets): every scalar is
+rewritten as s = sum_w d_w 2^(w c) with d_w in [-2^(c-1), 2^(c-1)], and a
+point with a negative digit is subtracted from bucket |d_w|.
+
 Everything here is the plain definition, on Weierstrass affine points, so the
 functions below are independent of the twisted-Edwards machinery in ``te``.
 """
 
-from .curve import INF, G, add, smul
+from .curve import INF, G, add, neg, smul
 from .field import R_ORDER
 
 SCALAR_BITS = 253
@@ -72,6 +77,59 @@ def msm_pippenger(scalars, points, c):
     """The three Pippenger steps composed; equals msm_naive for any c >= 1."""
     B = buckets(scalars, points, c)
     return group_aggregate([window_sum(row) for row in B], c)
+
+
+def num_signed_windows(c, bits=SCALAR_BITS):
+    """Windows of the signed encoding: one more bit than the scalar, so the
+    top window never needs a carry out."""
+    return -(-(bits + 1) // c)
+
+
+def signed_digits(s, c):
+    """Digits d_0..d_{W-1} with s = sum_w d_w 2^(w c), written from the
+    definition: walking up from the lowest window, v = slice + carry; when
+    v >= 2^(c-1) (and this is not the top window) the digit is v - 2^c and a
+    carry of one moves up, otherwise the digit is v and no carry moves."""
+    W = num_signed_windows(c)
+    half, full = 1 << (c - 1), 1 << c
+    out, carry = [], 0
+    for w in range(W):
+        v = digit(s, w, c) + carry
+        if v >= half and w + 1 < W:
+            out.append(v - full)
+            carry = 1
+        else:
+            out.append(v)
+            carry = 0
+    return out
+
+
+def signed_buckets(scalars, points, c):
+    """B[w][m] = sum over i with |d_w(s_i)| = m + 1 of sign(d_w(s_i)) P_i."""
+    W = num_signed_windows(c)
+    B = [[INF] * (1 << (c - 1)) for _ in range(W)]
+    for s, pt in zip(scalars, points):
+        for w, d in enumerate(signed_digits(s, c)):
+            if d > 0:
+                B[w][d - 1] = add(B[w][d - 1], pt)
+            elif d < 0:
+                B[w][-d - 1] = add(B[w][-d - 1], neg(pt))
+    return B
+
+
+def signed_window_sum(bucket_row):
+    """S = sum_m (m + 1) * B[m] (bucket m holds digit magnitude m + 1)."""
+    acc = INF
+    for m, pt in enumerate(bucket_row):
+        if pt is not INF:
+            acc = add(acc, smul(m + 1, pt))
+    return acc
+
+
+def msm_pippenger_signed(scalars, points, c):
+    """Pippenger with signed digits; equals msm_naive for any c >= 2."""
+    B = signed_buckets(scalars, points, c)
+    return group_aggregate([signed_window_sum(row) for row in B], c)
 
 
 def closed_form(scalars, ks):

@@ -23,6 +23,14 @@ MSM_RESULT_WORDS = 32
 MSM_MB_MAD64 = 0
 MSM_MB_ADDC = 1
 MSM_MB_COPY = 2
+MSM_DIGITS_SIGNED = 0
+MSM_DIGITS_UNSIGNED = 1
+
+
+class MsmJob(ctypes.Structure):
+    """struct msm_job"""
+    _fields_ = [("xyu", ctypes.c_void_p), ("scalars", ctypes.c_void_p),
+                ("result", ctypes.c_void_p), ("n", ctypes.c_size_t), ("c", ctypes.c_int)]
 
 # every exported symbol and its (restype, argtypes)
 _P = ctypes.c_void_p
@@ -33,11 +41,24 @@ SIGNATURES = {
     "msm_fe_mul_batch": (_I, [_P, _P, _P, _SZ, _I, _P]),
     "msm_points_prepare": (_I, [_P, _P, _P, _SZ, _P, _P]),
     "msm_gen_points": (_I, [_P, _SZ, _P, _P, _P]),
-    "msm_num_windows": (_I, [_I]),
-    "msm_workspace_bytes": (_SZ, [_SZ, _I]),
+    "msm_num_windows": (_I, [_I, _I]),
+    "msm_workspace_bytes": (_SZ, [_SZ, _I, _I]),
     "msm_default_window": (_I, [_SZ]),
-    "msm_bucket_accumulate": (_I, [_P, _P, _SZ, _I, _P, _P, _SZ, _P]),
-    "msm_run": (_I, [_P, _P, _SZ, _I, _P, _P, _SZ, _P]),
+    "msm_bucket_accumulate": (_I, [_P, _P, _SZ, _I, _I, _P, _P, _SZ, _P]),
+    "msm_run": (_I, [_P, _P, _SZ, _I, _I, _P, _P, _SZ, _P]),
+    "msm_batch_workspace_bytes": (_SZ, [ctypes.POINTER(MsmJob), _SZ, _I]),
+    "msm_batch_create": (_I, [ctypes.POINTER(MsmJob), _SZ, _I, _P, _SZ, _I,
+                              ctypes.POINTER(ctypes.c_void_p)]),
+    "msm_batch_run": (_I, [_P, _P]),
+    "msm_batch_destroy": (_I, [_P]),
+    "msm_server_create": (_I, [_SZ, _I, _I, ctypes.POINTER(ctypes.c_void_p)]),
+    "msm_server_submit": (_I, [_P, ctypes.POINTER(MsmJob), ctypes.POINTER(ctypes.c_uint64)]),
+    "msm_server_progress": (_I, [_P, ctypes.POINTER(ctypes.c_uint64), _SZ,
+                                 ctypes.POINTER(ctypes.c_size_t)]),
+    "msm_server_drain": (_I, [_P]),
+    "msm_server_stats": (_I, [_P, ctypes.POINTER(ctypes.c_size_t),
+                              ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+    "msm_server_destroy": (_I, [_P]),
     "msm_last_hip_error": (_I, []),
     "msm_status_string": (ctypes.c_char_p, [_I]),
     "msm_constants": (_I, [_P, _SZ]),

@@ -12,8 +12,9 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (MSM_FLAG_EXCEPT, MSM_FLAG_OFFCURVE, MSM_FLAG_RANGE, MSM_FORM_XYTZ,  # noqa: F401
-                   MSM_FORM_XYU, MSM_RESULT_WORDS, MSMError)
+from ._lib import (MSM_DIGITS_SIGNED, MSM_DIGITS_UNSIGNED, MSM_FLAG_EXCEPT,  # noqa: F401
+                   MSM_FLAG_OFFCURVE, MSM_FLAG_RANGE, MSM_FORM_XYTZ, MSM_FORM_XYU,
+                   MSM_RESULT_WORDS, MSMError, MsmJob)
 
 WORDS = 12
 XYU_WORDS = 36
@@ -109,41 +110,46 @@ def gen_points(k, n, xy_out=None, inf_out=None):
     return xy_out, inf_out
 
 
-def num_windows(c):
-    return _lib.lib().msm_num_windows(c)
+def num_windows(c, encoding=MSM_DIGITS_SIGNED):
+    return _lib.lib().msm_num_windows(c, encoding)
+
+
+def buckets_per_window(c, encoding=MSM_DIGITS_SIGNED):
+    return 1 << (c - 1 if encoding == MSM_DIGITS_SIGNED else c)
 
 
 def default_window(n):
     return _lib.lib().msm_default_window(n)
 
 
-def workspace_bytes(n, c):
-    return _lib.lib().msm_workspace_bytes(n, c)
+def workspace_bytes(n, c, encoding=MSM_DIGITS_SIGNED):
+    return _lib.lib().msm_workspace_bytes(n, c, encoding)
 
 
-def workspace(n, c, device="cuda"):
-    nbytes = workspace_bytes(n, c)
+def workspace(n, c, encoding=MSM_DIGITS_SIGNED, device="cuda"):
+    nbytes = workspace_bytes(n, c, encoding)
     if nbytes == 0:
-        raise ValueError("invalid (n, c) = (%d, %d)" % (n, c))
+        raise ValueError("invalid (n, c, encoding) = (%d, %d, %d)" % (n, c, encoding))
     return torch.empty((nbytes + 3) // 4, dtype=torch.int32, device=device)
 
 
-def bucket_accumulate(xyu, scalars, n, c, buckets=None, ws=None):
+def bucket_accumulate(xyu, scalars, n, c, encoding=MSM_DIGITS_SIGNED, buckets=None, ws=None):
     _dev(xyu, "xyu")
     _dev(scalars, "scalars")
     if xyu.numel() != XYU_WORDS * n or scalars.numel() != SCALAR_WORDS * n:
         raise ValueError("input sizes do not match n")
-    W = num_windows(c)
+    W = num_windows(c, encoding)
     if buckets is None:
-        buckets = words(XYTZ_WORDS * (W << c), xyu.device)
+        buckets = words(XYTZ_WORDS * W * buckets_per_window(c, encoding), xyu.device)
     if ws is None:
-        ws = workspace(n, c, xyu.device)
+        ws = workspace(n, c, encoding, xyu.device)
     _lib.check("msm_bucket_accumulate", _lib.lib().msm_bucket_accumulate(
-        _ptr(xyu), _ptr(scalars), n, c, _ptr(buckets), _ptr(ws), ws.numel() * 4, _stream()))
+        _ptr(xyu), _ptr(scalars), n, c, encoding, _ptr(buckets), _ptr(ws), ws.numel() * 4,
+        _stream()))
     return buckets, ws
 
 
-def msm_run(xyu, scalars, n, c=0, result=None, ws=None):
+def msm_run(xyu, scalars, n, c=0, encoding=MSM_DIGITS_SIGNED, result=None, ws=None):
     _dev(xyu, "xyu")
     _dev(scalars, "scalars")
     if xyu.numel() != XYU_WORDS * n or scalars.numel() != SCALAR_WORDS * n:
@@ -151,10 +157,66 @@ def msm_run(xyu, scalars, n, c=0, result=None, ws=None):
     if result is None:
         result = words(MSM_RESULT_WORDS, xyu.device)
     if ws is None:
-        ws = workspace(n, c, xyu.device)
+        ws = workspace(n, c, encoding, xyu.device)
     _lib.check("msm_run", _lib.lib().msm_run(
-        _ptr(xyu), _ptr(scalars), n, c, _ptr(result), _ptr(ws), ws.numel() * 4, _stream()))
+        _ptr(xyu), _ptr(scalars), n, c, encoding, _ptr(result), _ptr(ws), ws.numel() * 4,
+        _stream()))
     return result
+
+
+def _job_array(jobs):
+    arr = (MsmJob * len(jobs))()
+    for a, (xyu, scalars, result, n, c) in zip(arr, jobs):
+        for t, name in ((xyu, "xyu"), (scalars, "scalars"), (result, "result")):
+            _dev(t, name)
+        if xyu.numel() < XYU_WORDS * n or scalars.numel() < SCALAR_WORDS * n:
+            raise ValueError("job inputs smaller than n")
+        if result.numel() < MSM_RESULT_WORDS:
+            raise ValueError("job result buffer too small")
+        a.xyu, a.scalars, a.result = xyu.data_ptr(), scalars.data_ptr(), result.data_ptr()
+        a.n, a.c = int(n), int(c)
+    return arr
+
+
+def batch_workspace_bytes(jobs, encoding=MSM_DIGITS_SIGNED):
+    """jobs: list of (xyu, scalars, result, n, c) tuples (c = 0: default width)."""
+    arr = _job_array(jobs)
+    return _lib.lib().msm_batch_workspace_bytes(arr, len(jobs), encoding)
+
+
+class Batch:
+    """A planned batch of independent MSMs (msm_batch_create / run / destroy).
+
+    The tensors named by the jobs must stay alive and in place while the batch
+    exists; the batch holds references to them and to its workspace.
+    """
+
+    def __init__(self, jobs, encoding=MSM_DIGITS_SIGNED, use_graph=False):
+        arr = _job_array(jobs)
+        nbytes = _lib.lib().msm_batch_workspace_bytes(arr, len(jobs), encoding)
+        if nbytes == 0:
+            raise ValueError("invalid batch jobs")
+        dev = jobs[0][0].device
+        self.ws = torch.empty((nbytes + 3) // 4, dtype=torch.int32, device=dev)
+        self._keep = [t for j in jobs for t in j[:3]]
+        h = ctypes.c_void_p()
+        _lib.check("msm_batch_create", _lib.lib().msm_batch_create(
+            arr, len(jobs), encoding, _ptr(self.ws), self.ws.numel() * 4,
+            1 if use_graph else 0, ctypes.byref(h)))
+        self._h = h
+
+    def run(self):
+        if self._h is None:
+            raise RuntimeError("batch destroyed")
+        _lib.check("msm_batch_run", _lib.lib().msm_batch_run(self._h, _stream()))
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.lib().msm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.destroy()
 
 
 def constants():
@@ -192,3 +254,57 @@ def microbench(kind, param, buf):
     _dev(buf, "buf")
     _lib.check("msm_microbench", _lib.lib().msm_microbench(
         kind, param, _ptr(buf), buf.numel() * 4, _stream()))
+
+
+class Server:
+    """MSM request server (msm_server_*): HBM-budget admission, concurrent
+    streams, retirement by completion events.  Tensors of a submitted job are
+    referenced until its ticket is reported finished."""
+
+    def __init__(self, budget_bytes, streams=4, encoding=MSM_DIGITS_SIGNED):
+        h = ctypes.c_void_p()
+        _lib.check("msm_server_create", _lib.lib().msm_server_create(
+            int(budget_bytes), int(streams), int(encoding), ctypes.byref(h)))
+        self._h = h
+        self._live = {}
+        self._buf = (ctypes.c_uint64 * 1024)()
+
+    def submit(self, xyu, scalars, result, n, c=0):
+        arr = _job_array([(xyu, scalars, result, n, c)])
+        t = ctypes.c_uint64(0)
+        _lib.check("msm_server_submit", _lib.lib().msm_server_submit(
+            self._h, arr, ctypes.byref(t)))
+        self._live[t.value] = (xyu, scalars, result)
+        return t.value
+
+    def progress(self):
+        """Tickets finished since the last call (their results are valid)."""
+        out = []
+        while True:
+            k = ctypes.c_size_t(0)
+            _lib.check("msm_server_progress", _lib.lib().msm_server_progress(
+                self._h, self._buf, len(self._buf), ctypes.byref(k)))
+            out.extend(self._buf[i] for i in range(k.value))
+            if k.value < len(self._buf):
+                break
+        for t in out:
+            self._live.pop(t, None)
+        return out
+
+    def drain(self):
+        _lib.check("msm_server_drain", _lib.lib().msm_server_drain(self._h))
+
+    def stats(self):
+        a, b, c = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        _lib.check("msm_server_stats", _lib.lib().msm_server_stats(
+            self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.lib().msm_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        self.destroy()

@@ -46,7 +46,7 @@ constexpr uint32_t kGteU[NL] = {0x4f3f8d58u, 0x719243efu, 0x4a7b9d48u, 0xf744d1f
                                 0xa77008dcu, 0x0ab712e3u, 0x1e09b26fu, 0x53f80798u,
                                 0xef3f9f1bu, 0x24125ab8u, 0xfb63f6d1u, 0x01959f77u};
 
-constexpr int SCALAR_BITS = 253;
+constexpr int SCALAR_BITS = 253;  // scalars are below 2^253
 constexpr int SCALAR_WORDS = 8;
 
 inline unsigned grid_for(size_t n, unsigned block) { return (unsigned)((n + block - 1) / block); }
@@ -78,52 +78,90 @@ struct ProfScope {
 };
 
 // ---------------------------------------------------------------------------
-// workspace plan of one MSM (msm_api.hip)
+// jobs and workspace plans (msm_api.hip)
 // ---------------------------------------------------------------------------
-struct Plan {
-  int c = 0, W = 0;
-  size_t n = 0, M = 0, NW = 0, chunks = 0, nb = 0;
-  uint32_t K = 32;  // entries per accumulation chunk
-  // Windows are processed in G groups of gw windows, top windows first, so
-  // that group aggregation of finished groups overlaps the accumulation of
-  // the next ones.  group_chunks bounds the accumulation chunks of a group.
-  int G = 1, gw = 1;
-  size_t group_chunks = 0;
-  int group_hi(int g) const { return W - 1 - g * gw; }
-  int group_lo(int g) const { int lo = W - (g + 1) * gw; return lo < 0 ? 0 : lo; }
-  // byte offsets into the workspace
-  size_t ncounts = 0;  // digit-sort (partition, tile) count matrix size
-  size_t o_flags = 0, o_total = 0, o_maxspan = 0, o_hist = 0, o_counts = 0, o_blocksums = 0,
-         o_digits = 0, o_tmp = 0, o_key = 0, o_idx = 0, o_head = 0, o_tail = 0, o_buckets = 0,
-         o_lvl0 = 0, o_lvl1 = 0, o_wsum = 0, o_qstate = 0, o_longlist = 0, lvl_records = 0, bytes = 0;
+// One pipeline runs a batch of J independent MSMs that share the window width
+// c and the digit encoding; a single MSM is a batch of one.  Window w of job j
+// is segment s = j W + w.  Segment s holds the job's n digits at
+// [W pt_off + w n, W pt_off + (w+1) n) of the digit array and owns the
+// pass-1 sort tiles [W tile_off + w tps, W tile_off + (w+1) tps).
+struct JobDesc {
+  const uint32_t* xyu;      // prepared points (AoS XYU records)
+  const uint32_t* scalars;  // 8 words per scalar
+  uint32_t* result;         // MSM_RESULT_WORDS words
+  uint32_t n;               // points of the job
+  uint32_t pt_off;          // points of the jobs before it
+  uint32_t tile_off;        // tiles per window of the jobs before it
+  uint32_t tps;             // sort tiles per window, ceil(n / SORT_TILE)
 };
 
-int num_windows(int c);
+// Kernel-argument view of a batch's jobs: a device table, or (J = 1) the one
+// job by value so that a single MSM needs no table upload.
+struct JobView {
+  const JobDesc* tab;
+  JobDesc one;
+  uint32_t J;
+  __device__ __forceinline__ JobDesc get(uint32_t j) const { return tab ? tab[j] : one; }
+};
+
+constexpr uint32_t SORT_TILE = 4096;  // digits per pass-1 sort tile
+
+struct Plan {
+  int c = 0, W = 0;
+  int encoding = MSM_DIGITS_SIGNED;
+  int bb = 0;  // bucket-index bits: c (unsigned digits) or c - 1 (signed)
+  uint32_t J = 1;
+  size_t N = 0;       // points over all jobs
+  size_t max_n = 0;   // largest job
+  size_t S = 0;       // segments J W
+  size_t M = 0;       // buckets S 2^bb
+  size_t NW = 0;      // digits N W
+  size_t tiles = 0;   // pass-1 sort tiles over all segments
+  size_t chunks = 0;  // accumulation chunks
+  uint32_t K = 32;    // entries per accumulation chunk
+  uint32_t lo_bits = 0, hi_bits = 0;  // split of the bb bucket bits in the sort
+  size_t ncounts = 0, nb = 0;         // sort count matrix size, its scan blocks
+  JobDesc one{};                      // the job when J = 1
+  // byte offsets into the workspace
+  size_t o_flags = 0, o_total = 0, o_offsets = 0, o_counts = 0, o_blocksums = 0, o_digits = 0,
+         o_tmp = 0, o_key = 0, o_idx = 0, o_head = 0, o_tail = 0, o_buckets = 0, o_lvl0 = 0,
+         o_lvl1 = 0, o_wsum = 0, o_qstate = 0, o_longlist = 0, o_jobs = 0, o_segpts = 0, bytes = 0;
+};
+
+int num_windows(int c, int encoding);
 int default_window(size_t n);
-bool make_plan(size_t n, int c, Plan& pl);
+// plan of a batch with job sizes ns[0..J); false for invalid sizes or c
+bool make_plan(const size_t* ns, uint32_t J, int c, int encoding, Plan& pl);
 
 template <typename T>
 inline T* ws_at(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
 
+// every phase of a planned batch on one stream (msm_api.hip)
+int enqueue_msm(const Plan& pl, void* ws, hipStream_t st);
+
+inline JobView job_view(const Plan& pl, void* ws) {
+  JobView v;
+  v.tab = pl.J == 1 ? nullptr : ws_at<const JobDesc>(ws, pl.o_jobs);
+  v.one = pl.one;
+  v.J = pl.J;
+  return v;
+}
+
 // ---------------------------------------------------------------------------
 // kernel launchers (each returns MSM_OK or MSM_EHIP)
 // ---------------------------------------------------------------------------
-// k_sort.hip: digits -> CSR offsets, sorted (key, idx); empty buckets set to
-// the identity; largest bucket span (in chunks) to ws maxspan
-size_t sort_counts_size(int c, int W, size_t n);
-int launch_sort(const Plan& pl, const uint32_t* scalars, uint32_t* buckets, void* ws,
-                hipStream_t st);
-// k_accum.hip: bucket accumulation and split-bucket merge of window group g
-int launch_accumulate_group(const Plan& pl, int g, const uint32_t* xyu, uint32_t* buckets,
-                            void* ws, hipStream_t st);
-// k_agg.hip: bucket aggregation (window sums) of group g; group aggregation
-// steps over group g's windows; the affine result
-int launch_aggregate_group(const Plan& pl, int g, const uint32_t* buckets, void* ws,
-                           hipStream_t st);
-int launch_horner_group(const Plan& pl, int g, void* ws, hipStream_t st);
-int launch_finalize(const Plan& pl, uint32_t* result, void* ws, hipStream_t st);
+// k_sort.hip: digits -> CSR offsets, sorted (key, idx | sign << 31); empty
+// buckets set to the identity
+void sort_geometry(Plan& pl);  // fills lo_bits, hi_bits, tiles, ncounts, nb
+int launch_sort(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t st);
+// k_accum.hip: bucket accumulation and split-bucket merge
+int launch_accumulate(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t st);
+// k_agg.hip: bucket aggregation (window sums), group aggregation and the
+// affine results of every job
+int launch_aggregate(const Plan& pl, const uint32_t* buckets, void* ws, hipStream_t st);
+int launch_horner(const Plan& pl, void* ws, hipStream_t st);
 // k_elementwise.hip
 int launch_fe_mul(const uint32_t* a, const uint32_t* b, uint32_t* out, uint32_t count,
                   int canonical, hipStream_t st);

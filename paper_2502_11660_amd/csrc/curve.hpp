@@ -67,6 +67,31 @@ __device__ __forceinline__ xytz padd_mixed(const xytz& a, const xyu& b, const fe
   return r;
 }
 
+// a + b or a - b, b prepared: -b = (-X2, Y2, -U2) exchanges Y2 - X2 with
+// Y2 + X2 and negates C, which exchanges F with G.  Same bounds as
+// padd_mixed; the sign costs selects only.
+__device__ __forceinline__ xytz padd_mixed_signed(const xytz& a, const xyu& b, bool neg,
+                                                 const fe& p2) {
+  const fe bm = fe_sub_plus(b.Y, b.X, p2);
+  const fe bp = fe_add(b.Y, b.X);
+  fe A = fe_mul(fe_sub_plus(a.Y, a.X, p2), fe_select(neg, bp, bm));
+  fe B = fe_mul(fe_add(a.Y, a.X), fe_select(neg, bm, bp));
+  fe C = fe_mul(a.T, b.U);
+  fe D = fe_add(a.Z, a.Z);
+  fe E = fe_sub_plus(B, A, p2);
+  const fe Fp = fe_sub_plus(D, C, p2);
+  const fe Gp = fe_add(D, C);
+  fe F = fe_select(neg, Gp, Fp);
+  fe G = fe_select(neg, Fp, Gp);
+  fe H = fe_add(B, A);
+  xytz r;
+  r.X = fe_mul(E, F);
+  r.Y = fe_mul(G, H);
+  r.T = fe_mul(E, H);
+  r.Z = fe_mul(F, G);
+  return r;
+}
+
 // a + b, both extended: 9 multiplications (k T2 formed on the fly).
 __device__ __forceinline__ xytz padd_full(const xytz& a, const xytz& b, const fe& p2) {
   fe A = fe_mul(fe_sub_plus(a.Y, a.X, p2), fe_sub_plus(b.Y, b.X, p2));

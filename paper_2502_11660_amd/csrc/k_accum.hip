@@ -1,5 +1,6 @@
-// Bucket accumulation (Sec. II-C): B[w][b] = sum of the points whose w-th
-// digit is b, with the mixed addition (bucket XYTZ + prepared XYU, Sec. II-D).
+// Bucket accumulation (Sec. II-C): every bucket receives the sum of its
+// entries' points (negated for negative signed digits), with the mixed
+// addition (bucket XYTZ + prepared XYU, Sec. II-D).
 //
 // The digit-sorted entry list is cut into chunks of K entries and each lane
 // sums one chunk, so every lane does the same number of additions whatever
@@ -22,31 +23,40 @@ namespace {
 
 constexpr uint32_t SMALL_SPAN = 8;
 
-// The entries of one window group are [offsets[b0], offsets[b1]); chunk ch of
-// the group covers [E0 + ch K, min(E0 + (ch+1) K, E1)).  head/tail are the
-// group's own partial slots (indexed by ch).
+// Chunk ch covers entries [ch K, min((ch+1) K, E)), E = offsets[M].  The
+// entry's index word is the point index in its job with the digit's sign in
+// bit 31; segpts[s] is the point array of segment s's job (NULL: one job,
+// points at pts).
+
+__device__ __forceinline__ const uint32_t* entry_point(const uint32_t* __restrict__ pts,
+                                                       const uint64_t* __restrict__ segpts,
+                                                       uint32_t bb, uint32_t k, uint32_t e) {
+  const uint32_t* base = segpts ? reinterpret_cast<const uint32_t*>(segpts[k >> bb]) : pts;
+  return base + (size_t)(e & 0x7fffffffu) * XYU_WORDS;
+}
 
 __global__ void __launch_bounds__(256) k_accum(const uint32_t* __restrict__ pts,
+                                               const uint64_t* __restrict__ segpts, uint32_t bb,
                                                const uint32_t* __restrict__ key,
                                                const uint32_t* __restrict__ idx,
-                                               const uint32_t* __restrict__ offsets, uint32_t b0,
-                                               uint32_t b1, uint32_t K,
-                                               uint32_t* __restrict__ buckets,
+                                               const uint32_t* __restrict__ offsets, uint32_t M,
+                                               uint32_t K, uint32_t* __restrict__ buckets,
                                                uint32_t* __restrict__ head,
                                                uint32_t* __restrict__ tail) {
-  const uint32_t E0 = offsets[b0], E1 = offsets[b1];
+  const uint32_t E1 = offsets[M];
   const uint32_t ch = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t s64 = (uint64_t)E0 + (uint64_t)ch * K;
+  const uint64_t s64 = (uint64_t)ch * K;
   if (s64 >= E1) return;
   const uint32_t s = (uint32_t)s64;
   const uint32_t e = (uint32_t)(s64 + K < E1 ? s64 + K : E1);
   const fe p2 = fe_const(kP2);
 
   uint32_t cur = key[s];
-  const bool open_left = (s > E0) && (key[s - 1] == cur);
+  const bool open_left = (s > 0) && (key[s - 1] == cur);
   bool first_seg = true;
   xytz acc = pt_identity();
-  xyu P = ld_xyu(pts + (size_t)idx[s] * XYU_WORDS);
+  uint32_t ie = idx[s];
+  xyu P = ld_xyu(entry_point(pts, segpts, bb, cur, ie));
   for (uint32_t p = s; p < e; ++p) {
     const uint32_t k = key[p];
     if (k != cur) {
@@ -57,10 +67,13 @@ __global__ void __launch_bounds__(256) k_accum(const uint32_t* __restrict__ pts,
       cur = k;
       first_seg = false;
     }
+    // prefetch the next entry's point
     const uint32_t pn = (p + 1 < e) ? p + 1 : p;
-    xyu Pn = ld_xyu(pts + (size_t)idx[pn] * XYU_WORDS);  // prefetch the next point
-    acc = padd_mixed(acc, P, p2);
+    const uint32_t ien = idx[pn];
+    xyu Pn = ld_xyu(entry_point(pts, segpts, bb, key[pn], ien));
+    acc = padd_mixed_signed(acc, P, (ie >> 31) != 0u, p2);
     P = Pn;
+    ie = ien;
   }
   const bool open_right = (e < E1) && (key[e] == cur);
   uint32_t* dst;
@@ -75,19 +88,18 @@ __global__ void __launch_bounds__(256) k_accum(const uint32_t* __restrict__ pts,
 
 // chunk ch holds a tail partial: returns true, the bucket and its last chunk
 __device__ __forceinline__ bool tail_of(const uint32_t* __restrict__ key,
-                                        const uint32_t* __restrict__ offsets, uint32_t E0,
-                                        uint32_t E1, uint32_t K, uint32_t ch, uint32_t& b,
-                                        uint32_t& c1) {
-  const uint64_t s64 = (uint64_t)E0 + (uint64_t)ch * K;
+                                        const uint32_t* __restrict__ offsets, uint32_t E1,
+                                        uint32_t K, uint32_t ch, uint32_t& b, uint32_t& c1) {
+  const uint64_t s64 = (uint64_t)ch * K;
   if (s64 >= E1) return false;
   const uint32_t s = (uint32_t)s64;
   const uint32_t e = (uint32_t)(s64 + K < E1 ? s64 + K : E1);
   const uint32_t last = key[e - 1];
   if (!(e < E1 && key[e] == last)) return false;          // last piece ends here
-  if (s > E0 && key[s - 1] == key[s] && key[s] == last)    // whole chunk is a middle piece
+  if (s > 0 && key[s - 1] == key[s] && key[s] == last)     // whole chunk is a middle piece
     return false;
   b = last;
-  c1 = (offsets[b + 1] - 1 - E0) / K;
+  c1 = (offsets[b + 1] - 1) / K;
   return true;
 }
 
@@ -96,15 +108,15 @@ __device__ __forceinline__ bool tail_of(const uint32_t* __restrict__ key,
 // for k_merge_long.
 __global__ void __launch_bounds__(256) k_merge_small(const uint32_t* __restrict__ key,
                                                      const uint32_t* __restrict__ offsets,
-                                                     uint32_t b0, uint32_t b1, uint32_t K,
+                                                     uint32_t M, uint32_t K,
                                                      const uint32_t* __restrict__ head,
                                                      const uint32_t* __restrict__ tail,
                                                      uint32_t* __restrict__ buckets,
                                                      uint32_t* __restrict__ longlist) {
-  const uint32_t E0 = offsets[b0], E1 = offsets[b1];
+  const uint32_t E1 = offsets[M];
   const uint32_t ch = blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t b, c1;
-  if (!tail_of(key, offsets, E0, E1, K, ch, b, c1)) return;
+  if (!tail_of(key, offsets, E1, K, ch, b, c1)) return;
   const uint32_t span = c1 - ch;
   if (span > SMALL_SPAN) {
     const uint32_t slot = atomicAdd(&longlist[0], 1u);
@@ -125,20 +137,19 @@ __global__ void __launch_bounds__(256) k_merge_small(const uint32_t* __restrict_
 constexpr int LONG_THREADS = 128;
 __global__ void __launch_bounds__(LONG_THREADS) k_merge_long(const uint32_t* __restrict__ key,
                                                              const uint32_t* __restrict__ offsets,
-                                                             uint32_t b0, uint32_t K,
+                                                             uint32_t K,
                                                              const uint32_t* __restrict__ head,
                                                              const uint32_t* __restrict__ tail,
                                                              uint32_t* __restrict__ buckets,
                                                              const uint32_t* __restrict__ longlist) {
   __shared__ uint32_t part[LONG_THREADS][XYTZ_WORDS];
   const uint32_t count = longlist[0];
-  const uint32_t E0 = offsets[b0];
   const fe p2 = fe_const(kP2);
   for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
     const uint32_t ch = longlist[1 + item];
-    const uint32_t e_last = E0 + (ch + 1) * K - 1;  // the tail's bucket ends after this chunk
+    const uint32_t e_last = (ch + 1) * K - 1;  // the tail's bucket ends after this chunk
     const uint32_t b = key[e_last];
-    const uint32_t c1 = (offsets[b + 1] - 1 - E0) / K;
+    const uint32_t c1 = (offsets[b + 1] - 1) / K;
     xytz acc = pt_identity();
     for (uint32_t j = ch + 1 + threadIdx.x; j <= c1; j += LONG_THREADS)
       acc = padd_full(acc, ld_xytz(head + (size_t)j * XYTZ_WORDS), p2);
@@ -162,27 +173,26 @@ __global__ void __launch_bounds__(LONG_THREADS) k_merge_long(const uint32_t* __r
 
 }  // namespace
 
-int launch_accumulate_group(const Plan& pl, int g, const uint32_t* xyu, uint32_t* buckets,
-                            void* ws, hipStream_t st) {
-  const uint32_t* offsets = ws_at<uint32_t>(ws, pl.o_hist);
+int launch_accumulate(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t st) {
+  const uint32_t* offsets = ws_at<uint32_t>(ws, pl.o_offsets);
   const uint32_t* key = ws_at<uint32_t>(ws, pl.o_key);
   const uint32_t* idx = ws_at<uint32_t>(ws, pl.o_idx);
-  uint32_t* head = ws_at<uint32_t>(ws, pl.o_head) + (size_t)g * pl.group_chunks * XYTZ_WORDS;
-  uint32_t* tail = ws_at<uint32_t>(ws, pl.o_tail) + (size_t)g * pl.group_chunks * XYTZ_WORDS;
-  uint32_t* longlist = ws_at<uint32_t>(ws, pl.o_longlist) + (size_t)g * (pl.group_chunks + 1);
-  const uint32_t K = pl.K;
-  const uint32_t w_lo = (uint32_t)pl.group_lo(g), w_hi = (uint32_t)pl.group_hi(g);
-  const uint32_t b0 = w_lo << pl.c, b1 = (w_hi + 1) << pl.c;
-  const unsigned grid = grid_for(pl.group_chunks, 256);
+  uint32_t* head = ws_at<uint32_t>(ws, pl.o_head);
+  uint32_t* tail = ws_at<uint32_t>(ws, pl.o_tail);
+  uint32_t* longlist = ws_at<uint32_t>(ws, pl.o_longlist);
+  const uint64_t* segpts = pl.J == 1 ? nullptr : ws_at<const uint64_t>(ws, pl.o_segpts);
+  const uint32_t K = pl.K, M = (uint32_t)pl.M;
+  const unsigned grid = grid_for(pl.chunks, 256);
   int rc;
   if ((rc = launch_fill_u32(longlist, 1, 0u, st)) != MSM_OK) return rc;
   {
     ProfScope prof(PT_ACCUM, st);
-    k_accum<<<grid, 256, 0, st>>>(xyu, key, idx, offsets, b0, b1, K, buckets, head, tail);
+    k_accum<<<grid, 256, 0, st>>>(pl.one.xyu, segpts, (uint32_t)pl.bb, key, idx, offsets, M, K,
+                                  buckets, head, tail);
   }
   ProfScope prof(PT_MERGE, st);
-  k_merge_small<<<grid, 256, 0, st>>>(key, offsets, b0, b1, K, head, tail, buckets, longlist);
-  k_merge_long<<<64, LONG_THREADS, 0, st>>>(key, offsets, b0, K, head, tail, buckets, longlist);
+  k_merge_small<<<grid, 256, 0, st>>>(key, offsets, M, K, head, tail, buckets, longlist);
+  k_merge_long<<<64, LONG_THREADS, 0, st>>>(key, offsets, K, head, tail, buckets, longlist);
   HIPCHK(hipGetLastError());
   return MSM_OK;
 }

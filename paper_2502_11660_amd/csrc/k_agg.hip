@@ -1,7 +1,10 @@
 // Bucket aggregation and group aggregation (Sec. II-C).
 //
-// Bucket aggregation computes S_w = sum_b b B[w][b].  Writing b in binary,
-// S_w = sum_t 2^t X_t with X_t = sum of the buckets whose index has bit t set.
+// Bucket aggregation computes the window sum S_w = sum_b b B[w][b] (unsigned
+// digits) or sum_m (m + 1) B[w][m] (signed digits: bucket m holds digit
+// magnitude m + 1).  Writing the bucket index b in binary,
+// sum_b b B[w][b] = sum_t 2^t X_t with X_t = sum of the buckets whose index
+// has bit t set; signed digits add the sum of all buckets.
 // The X_t are built by a binary tree over the bucket index: a node covering
 // 2^h consecutive buckets keeps V[t] (t < h, the sum over its buckets with bit
 // t set) and S (the sum of all its buckets).  Merging left child L and right
@@ -11,10 +14,12 @@
 // its dependent depth is only c additions.  Large levels run one addition per
 // lane; small ones use the four-lane quad unit (quad.hpp) to cut latency.
 //
-// Each window then forms S_w = sum_t 2^t X_t by Horner's rule on one quad, and
-// group aggregation Q = sum_w 2^(w c) S_w is Horner's rule over the windows
+// Each window then forms S_w by Horner's rule on one quad, and group
+// aggregation Q = sum_w 2^(w c) S_w is Horner's rule over the windows of a job
 // (c doublings per window), the dependent chain the paper assigns to its
-// low-latency unit.  The result is mapped back to Weierstrass affine form.
+// low-latency unit; one quad per job.  The result is mapped back to
+// Weierstrass affine form.  A "window" below is a segment: one window of one
+// job of the batch.
 #include "common.hpp"
 #include "convert.hpp"
 #include "quad.hpp"
@@ -79,55 +84,51 @@ __global__ void __launch_bounds__(256) k_tree_level_quad(const uint32_t* __restr
   quad_st(out + rec_index(w, nodes_out, n, slots_out, s) * XYTZ_WORDS, r);
 }
 
-// Per window: S_w = sum_t 2^t X_t (X_t in XYUZ form, slot t of the tree's
-// root), by Horner's rule on one quad.  Writes S_w as XYTZ (record 2w) and
-// XYUZ (record 2w + 1).
+// Per window: S_w = sum_t 2^t X_t (+ S for signed digits), X_t in XYUZ form
+// (slot t < bb of the tree's root), S in XYTZ form (slot bb), by Horner's rule
+// on one quad.  Writes S_w as XYTZ (record 2w) and XYUZ (record 2w + 1).
 __global__ void __launch_bounds__(64) k_window_combine(const uint32_t* __restrict__ root,
-                                                       uint32_t c, uint32_t w_lo, uint32_t w_cnt,
+                                                       uint32_t bb, uint32_t w_cnt,
+                                                       int add_total,
                                                        uint32_t* __restrict__ wsum) {
-  const uint32_t wq = (blockIdx.x * blockDim.x + threadIdx.x) >> 2;
-  if (wq >= w_cnt) return;
-  const uint32_t w = w_lo + wq;
+  const uint32_t w = (blockIdx.x * blockDim.x + threadIdx.x) >> 2;
+  if (w >= w_cnt) return;
   const fe p2 = fe_const(kP2);
-  const uint32_t* V = root + (size_t)w * (c + 1) * XYTZ_WORDS;
-  fe acc = quad_add_u(quad_identity(), quad_ld(V + (size_t)(c - 1) * XYTZ_WORDS), p2);
-  for (int t = (int)c - 2; t >= 0; --t) {
-    acc = quad_dbl(acc, p2);
+  const uint32_t* V = root + (size_t)w * (bb + 1) * XYTZ_WORDS;
+  fe acc = quad_identity();
+  for (int t = (int)bb - 1; t >= 0; --t) {
+    if (t + 1 < (int)bb) acc = quad_dbl(acc, p2);
     acc = quad_add_u(acc, quad_ld(V + (size_t)t * XYTZ_WORDS), p2);
   }
+  if (add_total) acc = quad_add(acc, quad_ld(V + (size_t)bb * XYTZ_WORDS), p2);
   quad_st(wsum + (size_t)(2 * w) * XYTZ_WORDS, acc);
   quad_st(wsum + (size_t)(2 * w + 1) * XYTZ_WORDS, quad_to_u(acc));
 }
 
-// Group aggregation Q = sum_w 2^(w c) S_w by Horner's rule on one quad, over
-// the windows w_hi down to w_lo of one group; the running value Q is kept in
-// a record between groups (the top window starts it).
-__global__ void __launch_bounds__(64) k_horner_steps(const uint32_t* __restrict__ wsum,
-                                                     uint32_t W, uint32_t c, uint32_t w_lo,
-                                                     uint32_t w_hi, uint32_t* __restrict__ state) {
-  if (blockIdx.x != 0 || threadIdx.x >= 4) return;
+// Group aggregation of job j (quad j): Q = sum_w 2^(w c) S_w by Horner's rule
+// over the job's W windows, then the affine Weierstrass result.
+__global__ void __launch_bounds__(64) k_horner(const uint32_t* __restrict__ wsum, JobView jv,
+                                               uint32_t W, uint32_t c,
+                                               uint32_t* __restrict__ qstate) {
+  const uint32_t j = (blockIdx.x * blockDim.x + threadIdx.x) >> 2;
+  if (j >= jv.J) return;
   const fe p2 = fe_const(kP2);
-  int w = (int)w_hi;
-  fe q;
-  if (w_hi == W - 1) {
-    q = quad_ld(wsum + (size_t)(2 * w) * XYTZ_WORDS);
-    --w;
-  } else {
-    q = quad_ld(state);
-  }
-  for (; w >= (int)w_lo; --w) {
+  const uint32_t* ws = wsum + (size_t)2 * j * W * XYTZ_WORDS;
+  fe q = quad_ld(ws + (size_t)(2 * (W - 1)) * XYTZ_WORDS);
+  for (int w = (int)W - 2; w >= 0; --w) {
     for (uint32_t t = 0; t < c; ++t) q = quad_dbl(q, p2);
-    q = quad_add_u(q, quad_ld(wsum + (size_t)(2 * w + 1) * XYTZ_WORDS), p2);
+    q = quad_add_u(q, quad_ld(ws + (size_t)(2 * w + 1) * XYTZ_WORDS), p2);
   }
-  quad_st(state, q);
+  quad_st(qstate + (size_t)j * XYTZ_WORDS, q);
 }
 
-// The affine Weierstrass result of the group-aggregation record.
-__global__ void __launch_bounds__(64) k_finalize(const uint32_t* __restrict__ state,
-                                                 const uint32_t* __restrict__ flags,
-                                                 uint32_t* __restrict__ result) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  xytz Q = ld_xytz(state);
+// The affine Weierstrass result of each job, one lane per job.
+__global__ void __launch_bounds__(64) k_finalize(const uint32_t* __restrict__ qstate, JobView jv,
+                                                 const uint32_t* __restrict__ flags) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= jv.J) return;
+  uint32_t* result = jv.get(j).result;
+  xytz Q = ld_xytz(qstate + (size_t)j * XYTZ_WORDS);
   fe xw, yw;
   bool fin = te_to_weierstrass(Q, xw, yw);
 #pragma unroll
@@ -136,7 +137,7 @@ __global__ void __launch_bounds__(64) k_finalize(const uint32_t* __restrict__ st
     result[NL + l] = yw.v[l];
   }
   result[2 * NL] = fin ? 0u : 1u;
-  result[2 * NL + 1] = flags ? *flags : 0u;
+  result[2 * NL + 1] = flags[j];
   for (int l = 2 * NL + 2; l < MSM_RESULT_WORDS; ++l) result[l] = 0u;
 }
 
@@ -145,46 +146,38 @@ constexpr uint64_t QUAD_BELOW = 16384;
 
 }  // namespace
 
-int launch_aggregate_group(const Plan& pl, int g, const uint32_t* buckets, void* ws,
-                           hipStream_t st) {
-  const uint32_t c = (uint32_t)pl.c;
-  const uint32_t w_lo = (uint32_t)pl.group_lo(g), w_cnt = (uint32_t)(pl.group_hi(g) - pl.group_lo(g) + 1);
+int launch_aggregate(const Plan& pl, const uint32_t* buckets, void* ws, hipStream_t st) {
+  const uint32_t bb = (uint32_t)pl.bb, S = (uint32_t)pl.S;
   uint32_t* lv[2] = {ws_at<uint32_t>(ws, pl.o_lvl0), ws_at<uint32_t>(ws, pl.o_lvl1)};
   uint32_t* wsum = ws_at<uint32_t>(ws, pl.o_wsum);
   ProfScope prof(PT_AGG, st);
   const uint32_t* in = buckets;
-  uint32_t nodes = 1u << c;
-  for (uint32_t h = 0; h < c; ++h) {
+  uint32_t nodes = 1u << bb;
+  for (uint32_t h = 0; h < bb; ++h) {
     uint32_t* out = lv[h & 1];
-    const uint64_t outs = (uint64_t)w_cnt * (nodes >> 1) * (h + 2);
-    const int to_u = (h + 1 == c) ? 1 : 0;
+    const uint64_t outs = (uint64_t)S * (nodes >> 1) * (h + 2);
+    const int to_u = (h + 1 == bb) ? 1 : 0;
     if (outs >= QUAD_BELOW)
-      k_tree_level<<<(unsigned)((outs + 255) / 256), 256, 0, st>>>(in, h, nodes, w_lo, w_cnt, out,
-                                                                   to_u);
+      k_tree_level<<<(unsigned)((outs + 255) / 256), 256, 0, st>>>(in, h, nodes, 0, S, out, to_u);
     else
-      k_tree_level_quad<<<(unsigned)((4 * outs + 255) / 256), 256, 0, st>>>(in, h, nodes, w_lo,
-                                                                           w_cnt, out, to_u);
+      k_tree_level_quad<<<(unsigned)((4 * outs + 255) / 256), 256, 0, st>>>(in, h, nodes, 0, S,
+                                                                           out, to_u);
     in = out;
     nodes >>= 1;
   }
-  k_window_combine<<<grid_for(4 * (size_t)w_cnt, 64), 64, 0, st>>>(in, c, w_lo, w_cnt, wsum);
+  k_window_combine<<<grid_for(4 * (size_t)S, 64), 64, 0, st>>>(
+      in, bb, S, pl.encoding == MSM_DIGITS_SIGNED ? 1 : 0, wsum);
   HIPCHK(hipGetLastError());
   return MSM_OK;
 }
 
-int launch_horner_group(const Plan& pl, int g, void* ws, hipStream_t st) {
+int launch_horner(const Plan& pl, void* ws, hipStream_t st) {
   ProfScope prof(PT_HORNER, st);
-  k_horner_steps<<<1, 64, 0, st>>>(ws_at<uint32_t>(ws, pl.o_wsum), (uint32_t)pl.W, (uint32_t)pl.c,
-                                   (uint32_t)pl.group_lo(g), (uint32_t)pl.group_hi(g),
-                                   ws_at<uint32_t>(ws, pl.o_qstate));
-  HIPCHK(hipGetLastError());
-  return MSM_OK;
-}
-
-int launch_finalize(const Plan& pl, uint32_t* result, void* ws, hipStream_t st) {
-  ProfScope prof(PT_HORNER, st);
-  k_finalize<<<1, 64, 0, st>>>(ws_at<uint32_t>(ws, pl.o_qstate), ws_at<uint32_t>(ws, pl.o_flags),
-                               result);
+  const JobView jv = job_view(pl, ws);
+  uint32_t* qstate = ws_at<uint32_t>(ws, pl.o_qstate);
+  k_horner<<<grid_for(4 * (size_t)pl.J, 64), 64, 0, st>>>(ws_at<uint32_t>(ws, pl.o_wsum), jv,
+                                                          (uint32_t)pl.W, (uint32_t)pl.c, qstate);
+  k_finalize<<<grid_for(pl.J, 64), 64, 0, st>>>(qstate, jv, ws_at<uint32_t>(ws, pl.o_flags));
   HIPCHK(hipGetLastError());
   return MSM_OK;
 }

@@ -2,24 +2,27 @@
 // their sliced scalar values).
 //
 // The entries are the (segment, point) pairs with a non-zero digit, where a
-// segment is one window of one MSM.  Their key is seg * 2^c + digit; the sort
-// produces, over all M = segments * 2^c buckets:
+// segment is one window of one job.  An entry's key is s * 2^bb + m (segment
+// s, bucket m of bb bits) and its index word is the point's index in its job
+// with the digit's sign in bit 31.  Over all M = segments * 2^bb buckets the
+// sort produces
 //   offsets[0..M]  CSR offsets of each bucket's entries (offsets[M] = total),
-//   key[], idx[]   the entries in bucket order (idx = point index in its MSM),
-// writes the identity into every empty bucket and the largest bucket span
-// (in accumulation chunks) into *maxspan.
+//   key[], idx[]   the entries in bucket order,
+// and writes the identity into every empty bucket.
 //
 // It is a two-pass most-significant-digit counting sort with no global
 // atomics:
-//   slice   digits of every window, stored window-major (coalesced);
-//   pass 1  per tile of one segment, an LDS histogram of the digit's high
-//           bits; the (partition, tile) count matrix is scanned, and each tile
-//           scatters its entries to (partition, tile) ranges through LDS
+//   slice   digits of every window, stored segment-major (coalesced);
+//   pass 1  per tile of one segment, an LDS histogram of the bucket index's
+//           high bits; the (partition, tile) count matrix is scanned, and each
+//           tile scatters its entries to (partition, tile) ranges through LDS
 //           cursors;
 //   pass 2  one block per partition (segment, high bits) counts the low
 //           <= 8 bits in LDS, writes the bucket offsets, and places the
 //           entries in bucket order.  Partitions up to PART_CAP entries are
 //           staged in LDS; larger ones (skewed inputs) are streamed twice.
+// Segments of one job hold n entries each; jobs may differ in n, so a block
+// finds its job by binary search over the job table.
 #include <algorithm>
 
 #include "common.hpp"
@@ -29,69 +32,130 @@ namespace msm {
 namespace {
 
 constexpr int SORT_THREADS = 256;
-constexpr uint32_t TILE = 4096;      // entries per pass-1 tile
-constexpr uint32_t PART_CAP = 8192;  // entries staged in LDS by pass 2
+constexpr uint32_t TILE = SORT_TILE;  // entries per pass-1 tile
+constexpr uint32_t PART_CAP = 8192;   // entries staged in LDS by pass 2
 
 struct SortGeom {
-  uint32_t S;         // segments
-  uint32_t n;         // entries per segment (points of the MSM)
-  uint32_t Tps;       // tiles per segment
-  uint32_t c, lo_bits, hi_bits;
+  JobView jv;
+  uint32_t W, S, bb, lo_bits, hi_bits;
 };
 
-__device__ __forceinline__ uint32_t count_index(const SortGeom& g, uint32_t s, uint32_t hi,
-                                                uint32_t tile) {
-  return (s * (1u << g.hi_bits) + hi) * g.Tps + tile;
+// largest j with key(j) <= x, for a key non-decreasing in j (J >= 1)
+template <typename F>
+__device__ __forceinline__ uint32_t find_job(uint32_t J, uint32_t x, F key) {
+  uint32_t lo = 0, hi = J - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (key(mid) <= x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
 }
 
-// digits[w * n + i] = w-th c-bit digit of scalar i (bits >= 253 flagged, ignored)
-__global__ void __launch_bounds__(256) k_slice(const uint32_t* __restrict__ scalars, uint32_t n,
-                                               int c, int W, uint32_t* __restrict__ digits,
+// the segment, tile and job of pass-1 block b
+struct TileRef {
+  JobDesc d;
+  uint32_t j, w, tile;
+};
+
+__device__ __forceinline__ TileRef tile_ref(const SortGeom& g, uint32_t b) {
+  TileRef r;
+  r.j = g.jv.tab ? find_job(g.jv.J, b, [&](uint32_t j) { return g.W * g.jv.tab[j].tile_off; }) : 0u;
+  r.d = g.jv.get(r.j);
+  const uint32_t local = b - g.W * r.d.tile_off;
+  r.w = local / r.d.tps;
+  r.tile = local % r.d.tps;
+  return r;
+}
+
+// count-matrix index of (segment of job d window w, high bits hi, tile)
+__device__ __forceinline__ size_t count_index(const SortGeom& g, const JobDesc& d, uint32_t w,
+                                              uint32_t hi, uint32_t tile) {
+  const size_t seg_tile0 = (size_t)g.W * d.tile_off + (size_t)w * d.tps;
+  return (seg_tile0 << g.hi_bits) + (size_t)hi * d.tps + tile;
+}
+
+// Digits of every window of every job.  Word (segment s = j W + w, point i)
+// at W pt_off + w n + i holds q | sign << 31, where q = 0 drops the entry and
+// otherwise bucket m = q - 1 (signed digits, q = |d|) or m = q (unsigned
+// digits, q = d, so unsigned bucket 0 never receives points).
+__global__ void __launch_bounds__(256) k_slice(JobView jv, uint32_t N, int c, int W, int encoding,
+                                               uint32_t* __restrict__ digits,
                                                uint32_t* __restrict__ flags) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  scalar256 s = ld_scalar(scalars, i, flags);
-  for (int w = 0; w < W; ++w) digits[(size_t)w * n + i] = digit_at(s, w * c, c);
+  const uint32_t gi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= N) return;
+  const uint32_t j = jv.tab ? find_job(jv.J, gi, [&](uint32_t k) { return jv.tab[k].pt_off; }) : 0u;
+  const JobDesc d = jv.get(j);
+  const uint32_t i = gi - d.pt_off;
+  const scalar256 s = ld_scalar(d.scalars, i, flags + j);
+  uint32_t* out = digits + (size_t)W * d.pt_off + i;
+  if (encoding == MSM_DIGITS_UNSIGNED) {
+    for (int w = 0; w < W; ++w) out[(size_t)w * d.n] = digit_at(s, w * c, c);
+    return;
+  }
+  const uint32_t half = 1u << (c - 1);
+  uint32_t carry = 0;
+  for (int w = 0; w < W; ++w) {
+    const uint32_t v = digit_at(s, w * c, c) + carry;
+    uint32_t q;
+    if (v >= half && w + 1 < W) {  // d = v - 2^c < 0
+      q = ((1u << c) - v) | (v == (1u << c) ? 0u : 0x80000000u);
+      carry = 1;
+    } else {
+      q = v;
+      carry = 0;
+    }
+    out[(size_t)w * d.n] = q;
+  }
+}
+
+// bucket index and the entry's index word of a digit word q != 0
+__device__ __forceinline__ uint32_t bucket_of(uint32_t q, uint32_t off) {
+  return (q & 0x7fffffffu) - off;
 }
 
 // pass 1a: per-tile histogram of the high bits
-__global__ void __launch_bounds__(SORT_THREADS) k_part_count(SortGeom g,
+__global__ void __launch_bounds__(SORT_THREADS) k_part_count(SortGeom g, uint32_t off,
                                                              const uint32_t* __restrict__ digits,
                                                              uint32_t* __restrict__ counts) {
   __shared__ uint32_t hist[1u << 12];
-  const uint32_t s = blockIdx.x / g.Tps, tile = blockIdx.x % g.Tps;
+  const TileRef t = tile_ref(g, blockIdx.x);
   const uint32_t H = 1u << g.hi_bits;
   for (uint32_t b = threadIdx.x; b < H; b += SORT_THREADS) hist[b] = 0;
   __syncthreads();
-  const uint32_t e0 = tile * TILE, e1 = min(e0 + TILE, g.n);
-  const uint32_t* dg = digits + (size_t)s * g.n;
+  const uint32_t e0 = t.tile * TILE, e1 = min(e0 + TILE, t.d.n);
+  const uint32_t* dg = digits + (size_t)g.W * t.d.pt_off + (size_t)t.w * t.d.n;
   for (uint32_t e = e0 + threadIdx.x; e < e1; e += SORT_THREADS) {
-    uint32_t d = dg[e];
-    if (d) atomicAdd(&hist[d >> g.lo_bits], 1u);
+    const uint32_t q = dg[e];
+    if (q) atomicAdd(&hist[bucket_of(q, off) >> g.lo_bits], 1u);
   }
   __syncthreads();
   for (uint32_t b = threadIdx.x; b < H; b += SORT_THREADS)
-    counts[count_index(g, s, b, tile)] = hist[b];
+    counts[count_index(g, t.d, t.w, b, t.tile)] = hist[b];
 }
 
-// pass 1b: scatter into (partition, tile) ranges; tmp entry = {idx, key}
-__global__ void __launch_bounds__(SORT_THREADS) k_part_scatter(SortGeom g,
+// pass 1b: scatter into (partition, tile) ranges; tmp entry = {idx | sign, key}
+__global__ void __launch_bounds__(SORT_THREADS) k_part_scatter(SortGeom g, uint32_t off,
                                                                const uint32_t* __restrict__ digits,
                                                                const uint32_t* __restrict__ scanned,
                                                                uint2* __restrict__ tmp) {
   __shared__ uint32_t cur[1u << 12];
-  const uint32_t s = blockIdx.x / g.Tps, tile = blockIdx.x % g.Tps;
+  const TileRef t = tile_ref(g, blockIdx.x);
   const uint32_t H = 1u << g.hi_bits;
-  for (uint32_t b = threadIdx.x; b < H; b += SORT_THREADS) cur[b] = scanned[count_index(g, s, b, tile)];
+  for (uint32_t b = threadIdx.x; b < H; b += SORT_THREADS)
+    cur[b] = scanned[count_index(g, t.d, t.w, b, t.tile)];
   __syncthreads();
-  const uint32_t e0 = tile * TILE, e1 = min(e0 + TILE, g.n);
-  const uint32_t* dg = digits + (size_t)s * g.n;
-  const uint32_t keybase = s << g.c;
+  const uint32_t e0 = t.tile * TILE, e1 = min(e0 + TILE, t.d.n);
+  const uint32_t* dg = digits + (size_t)g.W * t.d.pt_off + (size_t)t.w * t.d.n;
+  const uint32_t keybase = (t.j * g.W + t.w) << g.bb;
   for (uint32_t e = e0 + threadIdx.x; e < e1; e += SORT_THREADS) {
-    uint32_t d = dg[e];
-    if (d) {
-      uint32_t pos = atomicAdd(&cur[d >> g.lo_bits], 1u);
-      tmp[pos] = make_uint2(e, keybase + d);
+    const uint32_t q = dg[e];
+    if (q) {
+      const uint32_t m = bucket_of(q, off);
+      const uint32_t pos = atomicAdd(&cur[m >> g.lo_bits], 1u);
+      tmp[pos] = make_uint2(e | (q & 0x80000000u), keybase + m);
     }
   }
 }
@@ -117,49 +181,48 @@ __device__ void lds_exclusive_scan256(uint32_t* v, uint32_t L) {
 // pass 2: one block per partition (segment s, high bits hi)
 __global__ void __launch_bounds__(SORT_THREADS) k_part_sort(
     SortGeom g, const uint32_t* __restrict__ scanned, const uint32_t* __restrict__ total_p,
-    const uint2* __restrict__ tmp, uint32_t K, uint32_t* __restrict__ key, uint32_t* __restrict__ idx,
-    uint32_t* __restrict__ offsets, uint32_t* __restrict__ buckets, uint32_t* __restrict__ maxspan) {
+    size_t ncounts, const uint2* __restrict__ tmp, uint32_t* __restrict__ key,
+    uint32_t* __restrict__ idx, uint32_t* __restrict__ offsets, uint32_t* __restrict__ buckets) {
   __shared__ uint2 ent[PART_CAP];
   __shared__ uint32_t hist[256], cur[256];
-  __shared__ uint32_t bmax;
   const uint32_t H = 1u << g.hi_bits, L = 1u << g.lo_bits;
-  const uint32_t p = blockIdx.x, s = p / H, hi = p % H;
+  const uint32_t p = blockIdx.x, s = p >> g.hi_bits, hi = p & (H - 1);
+  const uint32_t j = s / g.W, w = s % g.W;
+  const JobDesc d = g.jv.get(j);
   const uint32_t total = *total_p;
-  const uint32_t start = scanned[count_index(g, s, hi, 0)];
-  const uint32_t end = (p + 1 < g.S * H) ? scanned[count_index(g, (p + 1) / H, (p + 1) % H, 0)] : total;
+  // partitions are contiguous in the count matrix: the next one starts tps
+  // entries later
+  const size_t ci = count_index(g, d, w, hi, 0);
+  const uint32_t start = scanned[ci];
+  const uint32_t end = (ci + d.tps < ncounts) ? scanned[ci + d.tps] : total;
   const uint32_t size = end - start;
   const bool staged = size <= PART_CAP;
   if (threadIdx.x < 256) hist[threadIdx.x] = 0;
-  if (threadIdx.x == 0) bmax = 0;
   __syncthreads();
-  for (uint32_t j = threadIdx.x; j < size; j += SORT_THREADS) {
-    uint2 e = tmp[start + j];
-    if (staged) ent[j] = e;
+  for (uint32_t k = threadIdx.x; k < size; k += SORT_THREADS) {
+    uint2 e = tmp[start + k];
+    if (staged) ent[k] = e;
     atomicAdd(&hist[e.y & (L - 1)], 1u);
   }
   __syncthreads();
   for (uint32_t lo = threadIdx.x; lo < L; lo += SORT_THREADS) cur[lo] = hist[lo];
   __syncthreads();
   lds_exclusive_scan256(cur, L);  // cur[lo] = local start of bucket lo
-  const uint32_t bucket0 = (s << g.c) + hi * L;
+  const uint32_t bucket0 = (s << g.bb) + hi * L;
   if (threadIdx.x < L) {
-    const uint32_t lo = threadIdx.x, cnt = hist[lo], o = start + cur[lo];
-    offsets[bucket0 + lo] = o;
-    if (cnt == 0) {
-      if (buckets) st_xytz(buckets + (size_t)(bucket0 + lo) * XYTZ_WORDS, pt_identity());
-    } else {
-      atomicMax(&bmax, (o + cnt - 1) / K - o / K);
-    }
+    const uint32_t lo = threadIdx.x;
+    offsets[bucket0 + lo] = start + cur[lo];
+    if (hist[lo] == 0 && buckets)
+      st_xytz(buckets + (size_t)(bucket0 + lo) * XYTZ_WORDS, pt_identity());
   }
-  if (p == 0 && threadIdx.x == 0) offsets[g.S << g.c] = total;
+  if (p == 0 && threadIdx.x == 0) offsets[g.S << g.bb] = total;
   __syncthreads();
-  for (uint32_t j = threadIdx.x; j < size; j += SORT_THREADS) {
-    uint2 e = staged ? ent[j] : tmp[start + j];
+  for (uint32_t k = threadIdx.x; k < size; k += SORT_THREADS) {
+    uint2 e = staged ? ent[k] : tmp[start + k];
     uint32_t pos = start + atomicAdd(&cur[e.y & (L - 1)], 1u);
     key[pos] = e.y;
     idx[pos] = e.x;
   }
-  if (threadIdx.x == 0 && bmax) atomicMax(maxspan, bmax);
 }
 
 // Exclusive scan in three passes, SCAN_ITEMS elements per block.
@@ -242,62 +305,56 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_add(uint32_t* __restrict_
   }
 }
 
-// Split of the c digit bits: enough high bits that a partition of uniformly
-// distributed digits holds about n / 2^hi <= PART_CAP / 2 entries, at most 8
-// low bits (pass-2 histogram) and at most 12 high bits (pass-1 histogram).
-void split_bits(uint32_t c, size_t n, uint32_t& lo, uint32_t& hi) {
-  uint32_t want = 0;
-  while (want < 12 && (n >> want) > PART_CAP / 2) ++want;
-  hi = std::max<uint32_t>(want, c > 8 ? c - 8 : 0);
-  hi = std::min<uint32_t>(hi, std::min<uint32_t>(c, 12));
-  lo = c - hi;
-}
-
 }  // namespace
 
-size_t sort_counts_size(int c, int W, size_t n) {
-  uint32_t lo, hi;
-  split_bits((uint32_t)c, n, lo, hi);
-  if (lo > 8) return (size_t)-1;
-  const size_t Tps = (n + TILE - 1) / TILE;
-  return (size_t)W * ((size_t)1 << hi) * Tps;
+// Split of the bb bucket bits: enough high bits that a partition of uniformly
+// distributed digits of the largest job holds about max_n / 2^hi <=
+// PART_CAP / 2 entries, at most 8 low bits (pass-2 histogram) and at most 12
+// high bits (pass-1 histogram).  Also the tile count and count-matrix size.
+void sort_geometry(Plan& pl) {
+  const uint32_t bb = (uint32_t)pl.bb;
+  uint32_t want = 0;
+  while (want < 12 && (pl.max_n >> want) > PART_CAP / 2) ++want;
+  uint32_t hi = std::max<uint32_t>(want, bb > 8 ? bb - 8 : 0);
+  hi = std::min<uint32_t>(hi, std::min<uint32_t>(bb, 12));
+  pl.hi_bits = hi;
+  pl.lo_bits = bb - hi;
+  pl.ncounts = pl.tiles << hi;
+  pl.nb = (pl.ncounts + SCAN_ITEMS - 1) / SCAN_ITEMS;
 }
 
-int launch_sort(const Plan& pl, const uint32_t* scalars, uint32_t* buckets, void* ws,
-                hipStream_t st) {
+int launch_sort(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t st) {
   uint32_t* flags = ws_at<uint32_t>(ws, pl.o_flags);
   uint32_t* total = ws_at<uint32_t>(ws, pl.o_total);
-  uint32_t* maxspan = ws_at<uint32_t>(ws, pl.o_maxspan);
-  uint32_t* offsets = ws_at<uint32_t>(ws, pl.o_hist);
+  uint32_t* offsets = ws_at<uint32_t>(ws, pl.o_offsets);
   uint32_t* counts = ws_at<uint32_t>(ws, pl.o_counts);
   uint32_t* blocksums = ws_at<uint32_t>(ws, pl.o_blocksums);
   uint32_t* digits = ws_at<uint32_t>(ws, pl.o_digits);
   uint2* tmp = ws_at<uint2>(ws, pl.o_tmp);
   uint32_t* key = ws_at<uint32_t>(ws, pl.o_key);
   uint32_t* idx = ws_at<uint32_t>(ws, pl.o_idx);
-  const uint32_t n = (uint32_t)pl.n;
+  if (pl.lo_bits > 8 || pl.hi_bits > 12 || pl.nb > (size_t)SCAN_ITEMS) return MSM_EINVAL;
 
   SortGeom g;
-  g.S = (uint32_t)pl.W;
-  g.n = n;
-  g.Tps = (n + TILE - 1) / TILE;
-  g.c = (uint32_t)pl.c;
-  split_bits(g.c, n, g.lo_bits, g.hi_bits);
-  const size_t ncounts = (size_t)g.S * ((size_t)1 << g.hi_bits) * g.Tps;
-  const size_t nb = (ncounts + SCAN_ITEMS - 1) / SCAN_ITEMS;
-  if (nb > (size_t)SCAN_ITEMS || ncounts != pl.ncounts) return MSM_EINVAL;
+  g.jv = job_view(pl, ws);
+  g.W = (uint32_t)pl.W;
+  g.S = (uint32_t)pl.S;
+  g.bb = (uint32_t)pl.bb;
+  g.lo_bits = pl.lo_bits;
+  g.hi_bits = pl.hi_bits;
+  const uint32_t off = pl.encoding == MSM_DIGITS_SIGNED ? 1u : 0u;
 
   int rc;
-  if ((rc = launch_fill_u32(flags, 1, 0u, st)) != MSM_OK) return rc;
-  if ((rc = launch_fill_u32(maxspan, 1, 0u, st)) != MSM_OK) return rc;
-  k_slice<<<grid_for(n, 256), 256, 0, st>>>(scalars, n, pl.c, pl.W, digits, flags);
-  k_part_count<<<g.S * g.Tps, SORT_THREADS, 0, st>>>(g, digits, counts);
-  k_scan_block<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(counts, ncounts, blocksums);
-  k_scan_top<<<1, SCAN_THREADS, 0, st>>>(blocksums, (uint32_t)nb, total);
-  k_scan_add<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(counts, ncounts, blocksums);
-  k_part_scatter<<<g.S * g.Tps, SORT_THREADS, 0, st>>>(g, digits, counts, tmp);
-  k_part_sort<<<g.S << g.hi_bits, SORT_THREADS, 0, st>>>(g, counts, total, tmp, pl.K, key, idx,
-                                                          offsets, buckets, maxspan);
+  if ((rc = launch_fill_u32(flags, pl.J, 0u, st)) != MSM_OK) return rc;
+  k_slice<<<grid_for(pl.N, 256), 256, 0, st>>>(g.jv, (uint32_t)pl.N, pl.c, pl.W, pl.encoding,
+                                                digits, flags);
+  k_part_count<<<(unsigned)pl.tiles, SORT_THREADS, 0, st>>>(g, off, digits, counts);
+  k_scan_block<<<(unsigned)pl.nb, SCAN_THREADS, 0, st>>>(counts, pl.ncounts, blocksums);
+  k_scan_top<<<1, SCAN_THREADS, 0, st>>>(blocksums, (uint32_t)pl.nb, total);
+  k_scan_add<<<(unsigned)pl.nb, SCAN_THREADS, 0, st>>>(counts, pl.ncounts, blocksums);
+  k_part_scatter<<<(unsigned)pl.tiles, SORT_THREADS, 0, st>>>(g, off, digits, counts, tmp);
+  k_part_sort<<<(unsigned)(pl.S << pl.hi_bits), SORT_THREADS, 0, st>>>(
+      g, counts, total, pl.ncounts, tmp, key, idx, offsets, buckets);
   HIPCHK(hipGetLastError());
   return MSM_OK;
 }

@@ -43,46 +43,6 @@ hipEvent_t prof_event() {
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// ---------------------------------------------------------------------------
-// Internal streams for the window-group pipeline.  msm_run forks from the
-// caller's stream: accumulation stays on the caller's stream, bucket
-// aggregation of finished groups runs on stream `agg`, the group-aggregation
-// (Horner) steps on stream `hor`; the caller's stream finally waits for
-// `hor`.  All streams have the default priority.  A set is held (locked) only
-// while one call enqueues its work; a few sets per device let concurrent
-// callers on different streams overlap.
-// ---------------------------------------------------------------------------
-struct StreamSet {
-  std::mutex mu;
-  bool init = false;
-  hipStream_t agg = nullptr, hor = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
-  std::vector<hipEvent_t> accdone, aggdone;  // per window group
-};
-
-constexpr int kSetsPerDevice = 4;
-constexpr int kMaxDevices = 16;
-StreamSet g_sets[kMaxDevices][kSetsPerDevice];
-std::atomic<unsigned> g_set_rr{0};
-
-int ensure_events(std::vector<hipEvent_t>& v, size_t n) {
-  while (v.size() < n) {
-    hipEvent_t e = nullptr;
-    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    v.push_back(e);
-  }
-  return MSM_OK;
-}
-
-int init_set(StreamSet& ss) {
-  if (ss.init) return MSM_OK;
-  HIPCHK(hipStreamCreateWithFlags(&ss.agg, hipStreamNonBlocking));
-  HIPCHK(hipStreamCreateWithFlags(&ss.hor, hipStreamNonBlocking));
-  HIPCHK(hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming));
-  HIPCHK(hipEventCreateWithFlags(&ss.join, hipEventDisableTiming));
-  ss.init = true;
-  return MSM_OK;
-}
 }  // namespace
 
 void set_last_hip_error(int e) { g_last_hip = e; }
@@ -90,6 +50,8 @@ void set_last_hip_error(int e) { g_last_hip = e; }
 ProfScope::ProfScope(int t, hipStream_t s) : tag(t), st(s) {
   std::lock_guard<std::mutex> g(g_prof.mu);
   if (!g_prof.on) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   a = prof_event();
   if (a && hipEventRecord(a, st) == hipSuccess) active = true;
 }
@@ -101,15 +63,20 @@ ProfScope::~ProfScope() {
   if (b && hipEventRecord(b, st) == hipSuccess) g_prof.recs.push_back({tag, a, b});
 }
 
-int num_windows(int c) { return (SCALAR_BITS + c - 1) / c; }
+int num_windows(int c, int encoding) {
+  if (encoding == MSM_DIGITS_SIGNED) return (c >= 2 && c <= 20) ? (SCALAR_BITS + c) / c : 0;
+  if (encoding == MSM_DIGITS_UNSIGNED) return (c >= 1 && c <= 20) ? (SCALAR_BITS + c - 1) / c : 0;
+  return 0;
+}
 
 int default_window(size_t n) {
-  // additions ~ n W (accumulation) + ~2.6 * 2^c W (aggregation incl. merges)
+  // additions ~ n W (accumulation) + ~1.3 * 2^c W (signed-digit aggregation
+  // of 2^(c-1) buckets per window, merges included)
   int best = 8;
   double best_cost = 1e300;
   for (int c = 4; c <= 18; ++c) {
-    double W = num_windows(c);
-    double cost = (double)n * W + 2.6 * std::ldexp(1.0, c) * W;
+    double W = num_windows(c, MSM_DIGITS_SIGNED);
+    double cost = (double)n * W + 1.3 * std::ldexp(1.0, c) * W;
     if (cost < best_cost) {
       best_cost = cost;
       best = c;
@@ -118,58 +85,84 @@ int default_window(size_t n) {
   return best;
 }
 
-bool make_plan(size_t n, int c, Plan& pl) {
-  if (n == 0 || n >= (1u << 26) || c < 1 || c > 20) return false;
+bool make_plan(const size_t* ns, uint32_t J, int c, int encoding, Plan& pl) {
   pl = Plan();
+  const int W = num_windows(c, encoding);
+  if (W == 0 || J == 0 || !ns) return false;
   pl.c = c;
-  pl.W = num_windows(c);
-  pl.n = n;
-  pl.M = (size_t)pl.W << c;
-  pl.NW = n * (size_t)pl.W;
-  // window groups (tunable through MSM_WINDOW_GROUPS; default one group)
-  int want_groups = 1;
-  if (const char* e = std::getenv("MSM_WINDOW_GROUPS")) want_groups = std::max(1, std::atoi(e));
-  want_groups = std::min(want_groups, pl.W);
-  pl.gw = (pl.W + want_groups - 1) / want_groups;
-  pl.G = (pl.W + pl.gw - 1) / pl.gw;
-  // accumulation chunk: a group's launch keeps about 2 waves per SIMD busy
+  pl.W = W;
+  pl.encoding = encoding;
+  pl.bb = encoding == MSM_DIGITS_SIGNED ? c - 1 : c;
+  pl.J = J;
+  size_t tps_sum = 0;
+  for (uint32_t j = 0; j < J; ++j) {
+    if (ns[j] == 0 || ns[j] >= ((size_t)1 << 26)) return false;
+    pl.N += ns[j];
+    pl.max_n = std::max(pl.max_n, ns[j]);
+    tps_sum += (ns[j] + SORT_TILE - 1) / SORT_TILE;
+  }
+  pl.S = (size_t)J * W;
+  pl.M = pl.S << pl.bb;
+  pl.NW = pl.N * (size_t)W;
+  pl.tiles = tps_sum * (size_t)W;
+  // entry positions, keys (s 2^bb + m) and point indices are 32-bit words
+  if (pl.N >= ((size_t)1 << 31) || pl.NW >= ((size_t)1 << 31) || pl.M >= ((size_t)1 << 31) ||
+      pl.tiles >= ((size_t)1 << 31))
+    return false;
+  sort_geometry(pl);
+  if (pl.lo_bits > 8 || pl.nb > 4096) return false;
+  if (J == 1) {
+    pl.one.n = (uint32_t)ns[0];
+    pl.one.tps = (uint32_t)((ns[0] + SORT_TILE - 1) / SORT_TILE);
+  }
+  // accumulation chunk: the launch keeps about 2 waves per SIMD busy
   // (256 CUs x 4 SIMDs x 2 waves x 64 lanes = 131072 lanes), K in [16, 64]
-  const size_t group_entries = n * (size_t)pl.gw;
   pl.K = 16;
-  while (pl.K < 64 && group_entries / (2 * pl.K) >= 131072) pl.K *= 2;
-  pl.group_chunks = (group_entries + pl.K - 1) / pl.K;
-  pl.chunks = pl.group_chunks * pl.G;
-  pl.ncounts = sort_counts_size(c, pl.W, n);
-  if (pl.ncounts == (size_t)-1) return false;
-  pl.nb = (pl.ncounts + 4095) / 4096;
-  if (pl.nb > 4096) return false;
+  while (pl.K < 64 && pl.NW / (2 * pl.K) >= 131072) pl.K *= 2;
+  pl.chunks = (pl.NW + pl.K - 1) / pl.K;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
     o = align_up(o + bytes, 256);
     return at;
   };
-  pl.o_flags = take(4);
+  const size_t rec = XYTZ_WORDS * 4;
+  pl.o_flags = take((size_t)J * 4);
   pl.o_total = take(4);
-  pl.o_maxspan = take(4);
-  pl.o_hist = take((pl.M + 1) * 4);
+  pl.o_offsets = take((pl.M + 1) * 4);
   pl.o_counts = take(pl.ncounts * 4);
   pl.o_blocksums = take(4096 * 4);
   pl.o_digits = take(pl.NW * 4);
   pl.o_tmp = take(pl.NW * 8);
   pl.o_key = take(pl.NW * 4);
   pl.o_idx = take(pl.NW * 4);
-  pl.o_head = take(pl.chunks * XYTZ_WORDS * 4);
-  pl.o_tail = take(pl.chunks * XYTZ_WORDS * 4);
-  pl.o_buckets = take(pl.M * XYTZ_WORDS * 4);
-  pl.lvl_records = pl.M;  // the largest tree level holds W * 2^c records
-  pl.o_lvl0 = take(pl.lvl_records * XYTZ_WORDS * 4);
-  pl.o_lvl1 = take(pl.lvl_records * XYTZ_WORDS * 4);
-  pl.o_wsum = take(2 * (size_t)pl.W * XYTZ_WORDS * 4);
-  pl.o_qstate = take(XYTZ_WORDS * 4);
-  pl.o_longlist = take((size_t)pl.G * (pl.group_chunks + 1) * 4);
+  pl.o_head = take(pl.chunks * rec);
+  pl.o_tail = take(pl.chunks * rec);
+  pl.o_longlist = take((pl.chunks + 1) * 4);
+  // buckets, then the tree levels ping-pong between lvl0 (level 0's M
+  // records) and the bucket array, which level 0 has consumed
+  pl.o_buckets = take(pl.M * rec);
+  pl.o_lvl0 = take(pl.M * rec);
+  pl.o_lvl1 = pl.o_buckets;
+  pl.o_wsum = take(2 * pl.S * rec);
+  pl.o_qstate = take((size_t)J * rec);
+  pl.o_jobs = take((size_t)J * sizeof(JobDesc));
+  pl.o_segpts = take(pl.S * 8);
   pl.bytes = o;
   return true;
+}
+
+int enqueue_msm(const Plan& pl, void* ws, hipStream_t st) {
+  uint32_t* buckets = ws_at<uint32_t>(ws, pl.o_buckets);
+  int rc;
+  {
+    ProfScope prof(PT_SORT, st);
+    rc = launch_sort(pl, buckets, ws, st);
+  }
+  if (rc != MSM_OK) return rc;
+  if ((rc = launch_accumulate(pl, buckets, ws, st)) != MSM_OK) return rc;
+  if ((rc = launch_aggregate(pl, buckets, ws, st)) != MSM_OK) return rc;
+  return launch_horner(pl, ws, st);
 }
 
 }  // namespace msm
@@ -190,14 +183,14 @@ const char* msm_status_string(int status) {
   }
 }
 
-int msm_num_windows(int c) { return (c >= 1 && c <= 20) ? num_windows(c) : 0; }
+int msm_num_windows(int c, int encoding) { return num_windows(c, encoding); }
 
 int msm_default_window(size_t n) { return default_window(n); }
 
-size_t msm_workspace_bytes(size_t n, int c) {
+size_t msm_workspace_bytes(size_t n, int c, int encoding) {
   if (c == 0) c = default_window(n);
   Plan pl;
-  if (!make_plan(n, c, pl)) return 0;
+  if (!make_plan(&n, 1, c, encoding, pl)) return 0;
   return pl.bytes;
 }
 
@@ -226,69 +219,35 @@ int msm_gen_points(const uint32_t* k, size_t n, uint32_t* xy_std, uint32_t* inf,
 }
 
 int msm_bucket_accumulate(const uint32_t* xyu, const uint32_t* scalars, size_t n, int c,
-                          uint32_t* buckets, void* ws, size_t ws_bytes, void* stream) {
+                          int encoding, uint32_t* buckets, void* ws, size_t ws_bytes,
+                          void* stream) {
   if (!xyu || !scalars || !buckets || !ws) return MSM_EINVAL;
   Plan pl;
-  if (!make_plan(n, c, pl)) return MSM_EINVAL;
+  if (!make_plan(&n, 1, c, encoding, pl)) return MSM_EINVAL;
   if (ws_bytes < pl.bytes) return MSM_ENOSPC;
+  pl.one.xyu = xyu;
+  pl.one.scalars = scalars;
   hipStream_t st = (hipStream_t)stream;
   int rc;
   {
     ProfScope prof(PT_SORT, st);
-    rc = launch_sort(pl, scalars, buckets, ws, st);
+    rc = launch_sort(pl, buckets, ws, st);
   }
   if (rc != MSM_OK) return rc;
-  for (int g = 0; g < pl.G; ++g)
-    if ((rc = launch_accumulate_group(pl, g, xyu, buckets, ws, st)) != MSM_OK) return rc;
-  return MSM_OK;
+  return launch_accumulate(pl, buckets, ws, st);
 }
 
-int msm_run(const uint32_t* xyu, const uint32_t* scalars, size_t n, int c, uint32_t* result,
-            void* ws, size_t ws_bytes, void* stream) {
+int msm_run(const uint32_t* xyu, const uint32_t* scalars, size_t n, int c, int encoding,
+            uint32_t* result, void* ws, size_t ws_bytes, void* stream) {
   if (!xyu || !scalars || !result || !ws) return MSM_EINVAL;
   if (c == 0) c = default_window(n);
   Plan pl;
-  if (!make_plan(n, c, pl)) return MSM_EINVAL;
+  if (!make_plan(&n, 1, c, encoding, pl)) return MSM_EINVAL;
   if (ws_bytes < pl.bytes) return MSM_ENOSPC;
-  hipStream_t st = (hipStream_t)stream;
-  uint32_t* buckets = ws_at<uint32_t>(ws, pl.o_buckets);
-  int rc;
-  {
-    ProfScope prof(PT_SORT, st);
-    rc = launch_sort(pl, scalars, buckets, ws, st);
-  }
-  if (rc != MSM_OK) return rc;
-  if (pl.G == 1) {
-    // one group: nothing to overlap, stay on the caller's stream
-    if ((rc = launch_accumulate_group(pl, 0, xyu, buckets, ws, st)) != MSM_OK) return rc;
-    if ((rc = launch_aggregate_group(pl, 0, buckets, ws, st)) != MSM_OK) return rc;
-    if ((rc = launch_horner_group(pl, 0, ws, st)) != MSM_OK) return rc;
-    return launch_finalize(pl, result, ws, st);
-  }
-  int dev = 0;
-  HIPCHK(hipGetDevice(&dev));
-  if (dev < 0 || dev >= kMaxDevices) return MSM_EINVAL;
-  StreamSet& ss = g_sets[dev][g_set_rr.fetch_add(1) % kSetsPerDevice];
-  std::lock_guard<std::mutex> lock(ss.mu);
-  if ((rc = init_set(ss)) != MSM_OK) return rc;
-  if ((rc = ensure_events(ss.accdone, pl.G)) != MSM_OK) return rc;
-  if ((rc = ensure_events(ss.aggdone, pl.G)) != MSM_OK) return rc;
-  HIPCHK(hipEventRecord(ss.fork, st));
-  HIPCHK(hipStreamWaitEvent(ss.agg, ss.fork, 0));
-  HIPCHK(hipStreamWaitEvent(ss.hor, ss.fork, 0));
-  for (int g = 0; g < pl.G; ++g) {
-    if ((rc = launch_accumulate_group(pl, g, xyu, buckets, ws, st)) != MSM_OK) return rc;
-    HIPCHK(hipEventRecord(ss.accdone[g], st));
-    HIPCHK(hipStreamWaitEvent(ss.agg, ss.accdone[g], 0));
-    if ((rc = launch_aggregate_group(pl, g, buckets, ws, ss.agg)) != MSM_OK) return rc;
-    HIPCHK(hipEventRecord(ss.aggdone[g], ss.agg));
-    HIPCHK(hipStreamWaitEvent(ss.hor, ss.aggdone[g], 0));
-    if ((rc = launch_horner_group(pl, g, ws, ss.hor)) != MSM_OK) return rc;
-  }
-  if ((rc = launch_finalize(pl, result, ws, ss.hor)) != MSM_OK) return rc;
-  HIPCHK(hipEventRecord(ss.join, ss.hor));
-  HIPCHK(hipStreamWaitEvent(st, ss.join, 0));
-  return MSM_OK;
+  pl.one.xyu = xyu;
+  pl.one.scalars = scalars;
+  pl.one.result = result;
+  return enqueue_msm(pl, ws, (hipStream_t)stream);
 }
 
 int msm_profile_enable(int on) {

@@ -68,22 +68,48 @@ def test_argument_validation_without_gpu(lib):
     assert lib.msm_fe_mul_batch(p, None, p, 4, 1, None) == _lib.MSM_EINVAL
     assert lib.msm_points_prepare(p, None, p, 0, p, None) == _lib.MSM_EINVAL
     assert lib.msm_gen_points(p, 0, p, p, None) == _lib.MSM_EINVAL
-    assert lib.msm_run(p, p, 0, 8, p, p, 1 << 30, None) == _lib.MSM_EINVAL
-    assert lib.msm_run(p, p, 16, 21, p, p, 1 << 30, None) == _lib.MSM_EINVAL
-    assert lib.msm_run(p, p, 16, 8, p, p, 100, None) == _lib.MSM_ENOSPC
-    assert lib.msm_bucket_accumulate(p, p, 16, 8, None, p, 1 << 30, None) == _lib.MSM_EINVAL
-    assert lib.msm_bucket_accumulate(p, p, 1 << 26, 8, p, p, 1 << 40, None) == _lib.MSM_EINVAL
-    assert lib.msm_workspace_bytes(0, 8) == 0
-    assert lib.msm_workspace_bytes(1024, 21) == 0
-    assert lib.msm_workspace_bytes(1024, 8) > 0
+    S, U = _lib.MSM_DIGITS_SIGNED, _lib.MSM_DIGITS_UNSIGNED
+    assert lib.msm_run(p, p, 0, 8, S, p, p, 1 << 30, None) == _lib.MSM_EINVAL
+    assert lib.msm_run(p, p, 16, 21, S, p, p, 1 << 30, None) == _lib.MSM_EINVAL
+    assert lib.msm_run(p, p, 16, 1, S, p, p, 1 << 30, None) == _lib.MSM_EINVAL  # signed: c >= 2
+    assert lib.msm_run(p, p, 16, 8, 7, p, p, 1 << 30, None) == _lib.MSM_EINVAL
+    assert lib.msm_run(p, p, 16, 8, S, p, p, 100, None) == _lib.MSM_ENOSPC
+    assert lib.msm_bucket_accumulate(p, p, 16, 8, U, None, p, 1 << 30, None) == _lib.MSM_EINVAL
+    assert lib.msm_bucket_accumulate(p, p, 1 << 26, 8, U, p, p, 1 << 40, None) == _lib.MSM_EINVAL
+    assert lib.msm_workspace_bytes(0, 8, S) == 0
+    assert lib.msm_workspace_bytes(1024, 21, S) == 0
+    assert lib.msm_workspace_bytes(1024, 1, S) == 0
+    assert lib.msm_workspace_bytes(1024, 1, U) > 0
+    assert lib.msm_workspace_bytes(1024, 8, S) > 0
+    # batches: validated on the host
+    Job = _lib.MsmJob
+    jobs = (Job * 2)(Job(16, 16, 16, 100, 8), Job(16, 16, 16, 0, 8))
+    assert lib.msm_batch_workspace_bytes(jobs, 2, S) == 0          # n = 0
+    assert lib.msm_batch_workspace_bytes(jobs, 1, S) > 0
+    assert lib.msm_batch_workspace_bytes(jobs, 0, S) == 0
+    h = ctypes.c_void_p()
+    assert lib.msm_batch_create(jobs, 2, S, p, 1 << 40, 0, ctypes.byref(h)) == _lib.MSM_EINVAL
+    assert lib.msm_batch_create(jobs, 1, S, p, 100, 0, ctypes.byref(h)) == _lib.MSM_ENOSPC
+    assert h.value is None
+    assert lib.msm_batch_run(None, None) == _lib.MSM_EINVAL
+    assert lib.msm_batch_destroy(None) == _lib.MSM_OK
     assert lib.msm_status_string(_lib.MSM_ENOSPC).startswith(b"MSM_ENOSPC")
 
 
 def test_window_helpers(lib):
+    S, U = _lib.MSM_DIGITS_SIGNED, _lib.MSM_DIGITS_UNSIGNED
     for c in range(1, 21):
-        assert lib.msm_num_windows(c) == -(-253 // c)
-    assert lib.msm_num_windows(0) == 0
+        assert lib.msm_num_windows(c, U) == -(-253 // c)
+        assert lib.msm_num_windows(c, S) == (-(-254 // c) if c >= 2 else 0)
+    assert lib.msm_num_windows(0, U) == 0
+    assert lib.msm_num_windows(8, 5) == 0
     for n in (1, 1024, 1 << 16, 1 << 20):
         c = lib.msm_default_window(n)
-        assert 1 <= c <= 20
-        assert lib.msm_workspace_bytes(n, 0) == lib.msm_workspace_bytes(n, c)
+        assert 2 <= c <= 20
+        assert lib.msm_workspace_bytes(n, 0, S) == lib.msm_workspace_bytes(n, c, S)
+    # signed digits halve the bucket storage
+    assert lib.msm_workspace_bytes(1 << 16, 16, S) < lib.msm_workspace_bytes(1 << 16, 16, U)
+    # a batch of one job needs what a single MSM needs
+    Job = _lib.MsmJob
+    one = (Job * 1)(Job(16, 16, 16, 5000, 11))
+    assert lib.msm_batch_workspace_bytes(one, 1, S) == lib.msm_workspace_bytes(5000, 11, S)

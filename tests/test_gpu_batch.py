@@ -1,0 +1,145 @@
+"""GPU parity of batched MSMs (msm_batch_*) against the oracle.
+
+Every job's result must equal the oracle's closed form ((sum s_i k_i) mod r) G
+for its own points P_i = k_i G, and equal what msm_run returns for the same
+job alone, whatever the mix of sizes and window widths in the batch, with and
+without graph replay.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import msm
+from paper_2502_11660_amd import api, inputs
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    return api.to_device(a)
+
+
+def _prepared_pool(pts):
+    xy = H.soa(pts, 2)
+    xyu, status = api.points_prepare(_dev(xy), len(pts))
+    assert int(api.to_host(status)[0]) == 0
+    return xyu
+
+
+def _result(t):
+    return api.decode_result(api.to_host(t))
+
+
+def _jobs_from_pool(xyu_pool, sizes, widths, seed):
+    """Jobs over slices of a prepared pool (offsets wrap), fresh scalars."""
+    npool = xyu_pool.numel() // api.XYU_WORDS
+    jobs, meta = [], []
+    off = 0
+    for j, (n, c) in enumerate(zip(sizes, widths)):
+        if off + n > npool:
+            off = 0
+        xyu = xyu_pool[off * api.XYU_WORDS:(off + n) * api.XYU_WORDS]
+        sc = [inputs.words_to_int(r) for r in inputs.scalars_mod_r(seed + j, n)]
+        st = _dev(H.scalar_words(sc))
+        res = api.words(api.MSM_RESULT_WORDS)
+        jobs.append((xyu, st, res, n, c))
+        meta.append((off, sc))
+        off += n
+    return jobs, meta
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_mixed_sizes_and_widths(oracle_pool, use_graph):
+    ks, pts = oracle_pool
+    xyu_pool = _prepared_pool(pts)
+    sizes = [1, 7, 100, 1000, 2048, 333, 64, 1500, 5, 2000]
+    widths = [0, 4, 8, 8, 11, 0, 8, 11, 2, 13]
+    jobs, meta = _jobs_from_pool(xyu_pool, sizes, widths, 5000)
+    b = api.Batch(jobs, use_graph=use_graph)
+    for rep in range(2):
+        b.run()
+        torch.cuda.synchronize()
+        for (xyu, st, res, n, c), (off, sc) in zip(jobs, meta):
+            got, flags = _result(res)
+            assert flags == 0
+            assert got == msm.closed_form(sc, ks[off:off + n]), (rep, n, c)
+        # new scalars in place: the next run (or graph replay) must follow
+        for j, (xyu, st, res, n, c) in enumerate(jobs):
+            sc = [inputs.words_to_int(r) for r in inputs.scalars_mod_r(7000 + 31 * rep + j, n)]
+            st.copy_(_dev(H.scalar_words(sc)))
+            meta[j] = (meta[j][0], sc)
+    b.destroy()
+
+
+def test_batch_matches_single_runs_bitwise(oracle_pool):
+    ks, pts = oracle_pool
+    xyu_pool = _prepared_pool(pts)
+    sizes = [900, 17, 2048, 1024, 256]
+    jobs, meta = _jobs_from_pool(xyu_pool, sizes, [9, 9, 12, 9, 5], 6100)
+    b = api.Batch(jobs)
+    b.run()
+    torch.cuda.synchronize()
+    for (xyu, st, res, n, c), (off, sc) in zip(jobs, meta):
+        alone = api.msm_run(xyu, st, n, c)
+        assert np.array_equal(api.to_host(alone), api.to_host(res))
+        assert _result(res)[0] == msm.closed_form(sc, ks[off:off + n])
+
+
+def test_batch_degenerate_jobs(oracle_pool):
+    """A zero-scalar job (infinity) and an out-of-range scalar flag only their
+    own job; a single-point job and one with a repeated scalar."""
+    ks, pts = oracle_pool
+    xyu_pool = _prepared_pool(pts[:64])
+    from oracle.field import R_ORDER
+    scal = [
+        [0] * 20,
+        [3] * 30,
+        [R_ORDER - 1],
+        [5 | (1 << 254)] + [1] * 9,
+    ]
+    jobs, offs = [], [0, 20, 50, 51]
+    for sc, off in zip(scal, offs):
+        n = len(sc)
+        jobs.append((xyu_pool[off * 36:(off + n) * 36], _dev(H.scalar_words(sc)),
+                     api.words(api.MSM_RESULT_WORDS), n, 8))
+    b = api.Batch(jobs, use_graph=True)
+    b.run()
+    torch.cuda.synchronize()
+    got = [_result(j[2]) for j in jobs]
+    assert got[0] == (None, 0)
+    assert got[1] == (msm.closed_form(scal[1], ks[20:50]), 0)
+    assert got[2] == (msm.closed_form(scal[2], ks[50:51]), 0)
+    trunc = [s & ((1 << 253) - 1) for s in scal[3]]
+    assert got[3] == (msm.closed_form(trunc, ks[51:61]), api.MSM_FLAG_RANGE)
+
+
+def test_batch_64_jobs_log_uniform_sizes():
+    """64 jobs, n = floor(2^u), u ~ U[10, 15], GPU-generated points with
+    known discrete logs; default window widths (several classes)."""
+    seed = inputs.config_seed(4)
+    sizes = inputs.log_uniform_sizes(seed, 64, 10, 15)
+    ntot = int(sum(sizes))
+    kw = inputs.nonzero_scalars_mod_r(seed, ntot, stream=1)
+    xy, inf = api.gen_points(_dev(kw), ntot)
+    xyu, status = api.points_prepare(xy, ntot, inf=inf)
+    ks = [inputs.words_to_int(r) for r in kw]
+    sw = inputs.scalars_mod_r(seed, ntot, stream=2)
+    ss = [inputs.words_to_int(r) for r in sw]
+    s_dev = _dev(sw)
+    jobs, off = [], 0
+    for n in sizes:
+        n = int(n)
+        jobs.append((xyu[off * 36:(off + n) * 36], s_dev[off * 8:(off + n) * 8],
+                     api.words(api.MSM_RESULT_WORDS), n, 0))
+        off += n
+    b = api.Batch(jobs, use_graph=True)
+    for _ in range(2):
+        b.run()
+    torch.cuda.synchronize()
+    assert int(api.to_host(status)[0]) == 0
+    off = 0
+    for (x, s, res, n, c) in jobs:
+        assert _result(res) == (msm.closed_form(ss[off:off + n], ks[off:off + n]), 0), n
+        off += n

@@ -31,20 +31,23 @@ def _prepared(pts):
     return xyu
 
 
-def _run(xyu, scalars, c):
+SIGNED, UNSIGNED = api.MSM_DIGITS_SIGNED, api.MSM_DIGITS_UNSIGNED
+
+
+def _run(xyu, scalars, c, encoding=SIGNED):
     n = len(scalars)
-    res = api.msm_run(xyu, _dev(H.scalar_words(scalars)), n, c)
+    res = api.msm_run(xyu, _dev(H.scalar_words(scalars)), n, c, encoding)
     pt, flags = api.decode_result(api.to_host(res))
     return pt, flags
 
 
-def test_bucket_accumulate_config1(oracle_pool):
-    """n = 1024, c = 8: every bucket B[w][b] equals its definition."""
+def test_bucket_accumulate_config1_unsigned(oracle_pool):
+    """n = 1024, c = 8, plain slices: every bucket B[w][b] equals its definition."""
     ks, pts = oracle_pool
     n, c = 1024, 8
     sc = [inputs.words_to_int(r) for r in inputs.scalars_mod_r(inputs.config_seed(1), n)]
     xyu = _prepared(pts[:n])
-    buckets, ws = api.bucket_accumulate(xyu, _dev(H.scalar_words(sc)), n, c)
+    buckets, ws = api.bucket_accumulate(xyu, _dev(H.scalar_words(sc)), n, c, UNSIGNED)
     W = msm.num_windows(c)
     got = H.unaos(api.to_host(buckets), 4, W << c)
     want = msm.buckets(sc, pts[:n], c)
@@ -54,28 +57,48 @@ def test_bucket_accumulate_config1(oracle_pool):
     assert int(api.to_host(ws[:1])[0]) == 0
 
 
+def test_bucket_accumulate_config1_signed(oracle_pool):
+    """n = 1024, c = 8, signed digits: B[w][m] = signed sum of its points."""
+    ks, pts = oracle_pool
+    n, c = 1024, 8
+    sc = [inputs.words_to_int(r) for r in inputs.scalars_mod_r(inputs.config_seed(1), n)]
+    xyu = _prepared(pts[:n])
+    buckets, ws = api.bucket_accumulate(xyu, _dev(H.scalar_words(sc)), n, c, SIGNED)
+    W = msm.num_signed_windows(c)
+    B = 1 << (c - 1)
+    got = H.unaos(api.to_host(buckets), 4, W * B)
+    want = msm.signed_buckets(sc, pts[:n], c)
+    for w in range(W):
+        for m in range(B):
+            assert H.normalize_extended_mont(got[w * B + m]) == te.w_to_te(want[w][m]), (w, m)
+    assert int(api.to_host(ws[:1])[0]) == 0
+
+
 def test_msm_config1_closed_form_and_naive(oracle_pool):
     ks, pts = oracle_pool
     n, c = 1024, 8
     sc = [inputs.words_to_int(r) for r in inputs.scalars_mod_r(inputs.config_seed(1), n)]
     xyu = _prepared(pts[:n])
-    got, flags = _run(xyu, sc, c)
-    assert flags == 0
-    assert got == msm.closed_form(sc, ks[:n])
-    # direct definition on a prefix
-    m = 48
-    got_m, _ = _run(_prepared(pts[:m]), sc[:m], c)
-    assert got_m == msm.msm_naive(sc[:m], pts[:m])
+    for enc in (SIGNED, UNSIGNED):
+        got, flags = _run(xyu, sc, c, enc)
+        assert flags == 0
+        assert got == msm.closed_form(sc, ks[:n])
+        # direct definition on a prefix
+        m = 48
+        got_m, _ = _run(_prepared(pts[:m]), sc[:m], c, enc)
+        assert got_m == msm.msm_naive(sc[:m], pts[:m])
 
 
-@pytest.mark.parametrize("c", [1, 2, 3, 5, 7, 10, 12, 13, 16])
+@pytest.mark.parametrize("c", [1, 2, 3, 5, 7, 10, 11, 12, 13, 16, 17])
 def test_msm_window_widths(oracle_pool, c):
     ks, pts = oracle_pool
     n = 200 + 37 * c
     sc = [inputs.words_to_int(r) for r in inputs.scalars_mod_r(1000 + c, n)]
-    got, flags = _run(_prepared(pts[:n]), sc, c)
-    assert flags == 0
-    assert got == msm.closed_form(sc, ks[:n])
+    xyu = _prepared(pts[:n])
+    for enc in ((UNSIGNED,) if c == 1 else (SIGNED, UNSIGNED)):
+        got, flags = _run(xyu, sc, c, enc)
+        assert flags == 0
+        assert got == msm.closed_form(sc, ks[:n]), enc
 
 
 @pytest.mark.parametrize("n", [1, 2, 31, 32, 33, 65, 1000])
@@ -93,6 +116,16 @@ def test_msm_degenerate_scalars(oracle_pool):
     # all zero -> point at infinity
     got, _ = _run(xyu, [0] * n, 8)
     assert got is None
+    # every slice at its maximum: signed recoding carries through all windows;
+    # at c = 2 the top window reaches the largest digit 2^(c-1)
+    top = (1 << 253) - 1
+    for c in (11, 2):
+        got, _ = _run(xyu, [top] * n, c)
+        assert got == msm.closed_form([top] * n, ks[:n]), c
+    # slices at exactly 2^(c-1), the recoding boundary
+    half = sum(1 << (w * 8 + 7) for w in range(31))
+    got, _ = _run(xyu, [half] * n, 8)
+    assert got == msm.closed_form([half] * n, ks[:n])
     # all equal: every point in the same bucket of every window (skew)
     s = 0x1234567890ABCDEF1234567890ABCDEF1234567890ABCDEF1234567890ABCDE % R_ORDER
     got, _ = _run(xyu, [s] * n, 8)
@@ -139,7 +172,7 @@ def test_msm_point_order_and_repeat_invariance(oracle_pool):
     assert a == b == c2 == msm.closed_form(sc, ks[:n])
 
 
-@pytest.mark.parametrize("c", [16])
+@pytest.mark.parametrize("c", [16, 17])
 def test_msm_full_size_closed_form(c):
     """n = 2^20 GPU-generated points (checked on a sample), closed form."""
     n = 1 << 20
@@ -172,8 +205,8 @@ def test_msm_skewed_partition_larger_than_lds_stage(oracle_pool):
     sel_p = [pts[i % len(pts)] for i in range(n)]
     s = 0x0123456789ABCDEF0123456789ABCDEF0123456789ABCDEF0123456789ABCDE % R_ORDER
     xyu = _prepared(sel_p)
-    for c in (8, 13):
-        got, _ = _run(xyu, [s] * n, c)
+    for c, enc in ((8, SIGNED), (13, SIGNED), (8, UNSIGNED)):
+        got, _ = _run(xyu, [s] * n, c, enc)
         assert got == msm.closed_form([s] * n, sel_k), c
     # half the scalars equal, half random: mixed bucket sizes
     sc = [s if i % 2 else inputs.words_to_int(r)

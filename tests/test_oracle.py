@@ -260,6 +260,55 @@ def test_digits_recombine():
             assert sum(msm.digit(s, w, c) << (w * c) for w in range(W)) == s
 
 
+def test_signed_digits_worked_example():
+    """c = 4, s = 0x878, worked by hand: slices 8, 7, 8, 0 become
+    8 -> -8 (carry), 7+1 -> -8 (carry), 8+1 -> -7 (carry), 0+1 -> 1."""
+    d = msm.signed_digits(0x878, 4)
+    assert d[:4] == [-8, -8, -7, 1] and not any(d[4:])
+    assert len(d) == 64                     # ceil(254 / 4)
+
+
+def test_signed_digits_recombine_and_ranges():
+    cases = [0, 1, R_ORDER - 1, (1 << 253) - 1, int("10" * 126, 2)]
+    cases += [RNG.randrange(1 << 253) for _ in range(40)]
+    for c in (2, 3, 4, 7, 8, 11, 13, 16, 17, 20):
+        W = msm.num_signed_windows(c)
+        assert W * c >= 254 > (W - 1) * c
+        half = 1 << (c - 1)
+        for s in cases:
+            d = msm.signed_digits(s, c)
+            assert len(d) == W
+            assert sum(x << (w * c) if x >= 0 else -((-x) << (w * c))
+                       for w, x in enumerate(d)) == s
+            assert all(-half <= x < half for x in d[:-1]), (c, s)
+            assert 0 <= d[-1] <= half
+    # exhaustive on small scalars
+    for c in (2, 3, 5):
+        half = 1 << (c - 1)
+        for s in range(1 << 11):
+            d = msm.signed_digits(s, c)
+            assert sum(x * (1 << (w * c)) for w, x in enumerate(d)) == s
+            assert all(-half <= x < half for x in d[:-1])
+
+
+@pytest.mark.parametrize("c", [2, 3, 6, 13])
+def test_signed_pippenger_equals_definition(c):
+    n = 4
+    ks = [RNG.randrange(1, R_ORDER) for _ in range(n)]
+    pts = [points.fixed_base_mul(k) for k in ks]
+    sc = [RNG.randrange(R_ORDER) for _ in range(n)]
+    sc[1] = sc[0]            # shared buckets in every window
+    sc[2] = R_ORDER - 1      # mostly negative digits
+    assert msm.msm_pippenger_signed(sc, pts, c) == msm.msm_naive(sc, pts)
+    # bucket contents by their definition: the signed digit sum of each bucket
+    B = msm.signed_buckets(sc, pts, c)
+    w = 1
+    for m in range(1 << (c - 1)):
+        coeff = sum((1 if x > 0 else -1) * k for s, k in zip(sc, ks)
+                    for x in [msm.signed_digits(s, c)[w]] if abs(x) == m + 1)
+        assert B[w][m] == curve.smul(coeff % R_ORDER, curve.G)
+
+
 # --------------------------------------------------------------------------
 # twisted Edwards
 # --------------------------------------------------------------------------
