@@ -7,13 +7,15 @@ points P_i = k_i G with uniform scalars mod r -- the n = 2^20 workload the
 headline metric is quoted on.  Points are generated and prepared on the GPU
 before the timed region (preparation is reported separately).
 
-value = PADDs/s, counted by the algorithm's formula
-        n W + 2 (2^c - 1) W + W c + W - 1   per MSM,  W = ceil(253 / c),
-ms_per_step = MSM latency.
+value = PADDs/s: the point additions and doublings one MSM executes (every
+non-zero digit's mixed addition, the aggregation tree's additions, the window
+and group Horner steps; split-bucket merges are not counted) divided by the
+MSM time; ms_per_step = MSM latency.
 
 Prints one JSON line.  Extra keys: the window sweep, per-phase times, the
 standalone PADD kernel (2^22 independent pairs), the roofline of the dominant
-kernel and the CPU oracle baseline.
+kernel, the CPU oracle baseline, and the batched (64 MSMs of log-uniform
+sizes) and served (Poisson arrivals) workloads against the plain path.
 """
 
 import argparse
@@ -28,7 +30,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 N_POINTS = 1 << 20
-C_SWEEP = list(range(10, 17))
+C_SWEEP = list(range(13, 18))
 MAD_PER_MUL = 276          # 144 a*b + 132 m*p word products per Montgomery multiply
 MULS_MIXED = 7             # mixed PADD (Z2 = 1, U2 = k T2)
 MULS_COMPLETE = 9          # complete PADD with k T2 formed on the fly
@@ -36,9 +38,24 @@ MULS_COMPLETE = 9          # complete PADD with k T2 formed on the fly
 PEAK_MAD_PER_S = 256 * 64 * 2.4e9
 
 
-def padd_count(n, c):
+def padd_count_formula(n, c):
+    """Unsigned-digit Pippenger count n W + 2 (2^c - 1) W + W c + W - 1."""
     W = -(-253 // c)
     return n * W + 2 * ((1 << c) - 1) * W + W * c + W - 1
+
+
+def padd_count_executed(entries, c, signed=True, jobs=1):
+    """Additions and doublings the implementation executes for one MSM:
+    accumulation (one mixed addition per non-zero digit), the aggregation
+    tree (2^(bb+1) - bb - 2 per window), the window Horner steps and the
+    group Horner steps (c doublings and one addition per window but the top)."""
+    W = -(-(254 if signed else 253) // c)
+    bb = c - 1 if signed else c
+    S = W * jobs
+    tree = S * ((1 << (bb + 1)) - bb - 2)
+    combine = S * (2 * bb - 1 + (1 if signed else 0))
+    horner = jobs * (W - 1) * (c + 1)
+    return entries + tree + combine + horner
 
 
 # ---------------------------------------------------------------------------
@@ -84,7 +101,7 @@ def cpu_baseline(c, seconds=8.0):
                    "inverse per add), %d dependent adds in %.1f s on %d processes; the MSM time "
                    "at n=2^20, c=%d is extrapolated from this rate by the PADD count"
                    % (adds, wall, cores, c)),
-        "msm_ms_extrapolated": padd_count(N_POINTS, c) / rate * 1e3,
+        "msm_ms_extrapolated": None,
     }
 
 
@@ -103,20 +120,28 @@ def timed(fn, reps, torch):
     return s.elapsed_time(e) / reps
 
 
-def nonzero_digit_entries(sw_np, c):
+def nonzero_digit_entries(sw_np, c, signed=True):
     """Number of (point, window) pairs with a non-zero digit: the mixed PADDs
     bucket accumulation performs."""
     import numpy as np
-    W = -(-253 // c)
+    W = -(-(254 if signed else 253) // c)
     words = sw_np.reshape(-1, 8).astype(np.uint64)
+    carry = np.zeros(words.shape[0], dtype=np.uint64)
     total = 0
     for w in range(W):
         pos = w * c
         wi, sh = pos // 32, pos % 32
-        lo = words[:, wi]
+        lo = words[:, wi] if wi < 8 else np.zeros(words.shape[0], dtype=np.uint64)
         hi = words[:, wi + 1] if wi + 1 < 8 else np.zeros_like(lo)
         d = ((lo | (hi << np.uint64(32))) >> np.uint64(sh)) & np.uint64((1 << c) - 1)
-        total += int(np.count_nonzero(d))
+        if signed:
+            v = d + carry
+            neg = (v >= np.uint64(1 << (c - 1))) & (w + 1 < W)
+            mag = np.where(neg, np.uint64(1 << c) - v, v)
+            carry = neg.astype(np.uint64)
+            total += int(np.count_nonzero(mag))
+        else:
+            total += int(np.count_nonzero(d))
     return total
 
 
@@ -195,6 +220,12 @@ def main():
     ap.add_argument("--c", type=int, default=0, help="window width (0: sweep 10..16, take the best)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-padd-kernel", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served workload")
+    ap.add_argument("--serve-seconds", type=float, default=6.0,
+                    help="measured seconds of the served trace (after 1 s of warm-up)")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="served trace of 5 s warm-up + 30 s, plus a run with a 2 GB budget")
     ap.add_argument("--microbench", action="store_true",
                     help="only measure the VALU mad / carry-add issue rates and HBM copy bandwidth")
     args = ap.parse_args()
@@ -276,9 +307,9 @@ def main():
         phases[ph] = tot / max(cnt, 1)
     accum_tot_ms = phases["accum"]
 
-    padds = padd_count(n, best_c)
-    value = padds / (ms_per_step * 1e-3)
     entries = nonzero_digit_entries(sw, best_c)
+    padds = padd_count_executed(entries, best_c)
+    value = padds / (ms_per_step * 1e-3)
     accum_mads = entries * MULS_MIXED * MAD_PER_MUL
     achieved = accum_mads / (accum_tot_ms * 1e-3)
 
@@ -288,8 +319,17 @@ def main():
         padd_k = padd_kernel_bench(torch, api, xyu[:pool_n * 36], pool_n, 1 << 22, 5)
 
     if cpu is not None:
-        cpu["msm_ms_extrapolated"] = padd_count(n, best_c) / cpu["value"] * 1e3
+        cpu["msm_ms_extrapolated"] = padds / cpu["value"] * 1e3
         cpu["sample"] = cpu["sample"].replace("c=16", "c=%d" % best_c)
+
+    del ws
+    ks_pool = [inputs.words_to_int(r) for r in kw[:N_CHECK_POOL]]
+    batched = None
+    if not args.no_batch:
+        batched = batched_bench(torch, api, inputs, xyu, ks_pool, args)
+    served = None
+    if not args.no_serve:
+        served = served_bench(torch, api, inputs, xyu, ks_pool, args)
 
     out = {
         "metric": "PADDs/s and MSM latency (ms) at n=2^20; batched/served MSMs/s + p99 vs plain",
@@ -305,8 +345,10 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": "BLS12-377 G1 MSM, n=2^20 points k_i*G, uniform scalars mod r",
-                   "n": n, "c": best_c, "windows": -(-253 // best_c), "seed": seed,
-                   "padds_per_msm": padds},
+                   "n": n, "c": best_c, "digits": "signed",
+                   "windows": -(-254 // best_c), "seed": seed,
+                   "padds_per_msm": padds,
+                   "padds_per_msm_unsigned_formula": padd_count_formula(n, best_c)},
         "msm_ms": ms_per_step,
         "prepare_ms": prepare_ms,
         "c_sweep_ms": {str(k): v for k, v in sweep.items()},
@@ -318,14 +360,194 @@ def main():
             "peak": PEAK_MAD_PER_S / 1e12,
             "unit": "Tmad/s (32x32->64 multiply-adds)",
             "frac": achieved / PEAK_MAD_PER_S,
-            "traffic": None,
+            "traffic": accum_traffic(),
             "work_per_launch": {"mixed_padds": entries, "mad_per_padd": MULS_MIXED * MAD_PER_MUL},
             "launch_ms": accum_tot_ms,
         },
         "padd_kernel": padd_k,
+        "batched": batched,
+        "served": served,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+# ---------------------------------------------------------------------------
+# batched and served workloads
+# ---------------------------------------------------------------------------
+
+N_CHECK_POOL = 1 << 18   # pool points whose discrete logs the checks use
+
+
+def _closed_form_ok(msm_oracle, api, inputs, res_words, sc_words, ks):
+    ss = [inputs.words_to_int(r) for r in sc_words]
+    return api.decode_result(res_words) == (msm_oracle.closed_form(ss, ks), 0)
+
+
+def batched_bench(torch, api, inputs, xyu_pool, ks_pool, args):
+    """64 MSMs, n_j = floor(2^u), u ~ U[10, 18]: one graph-replayed batch with
+    autotuned widths, against 64 sequential msm_run calls."""
+    import numpy as np
+    from oracle import msm as msm_oracle
+    from paper_2502_11660_amd import autotune
+
+    seed = inputs.config_seed(4)
+    sizes = [int(x) for x in inputs.log_uniform_sizes(seed, 64, 10, 18)]
+    npool = xyu_pool.numel() // 36
+    ntot = sum(sizes)
+    sw = inputs.scalars_mod_r(seed, ntot, stream=2)
+    s_dev = api.to_device(sw)
+    rng = np.random.Generator(np.random.PCG64([seed, 3]))
+    offs = [int(rng.integers(0, N_CHECK_POOL - n + 1)) if n <= N_CHECK_POOL // 2
+            else int(rng.integers(0, npool - n + 1)) for n in sizes]
+    tuner = autotune.Autotuner()
+    t0 = time.perf_counter()
+    for u in sorted({autotune.n_bucket(n) for n in sizes}):
+        tuner.tune(u, xyu_pool, s_dev)
+    tune_s = time.perf_counter() - t0
+    print("[bench] autotuned %d size classes in %.1f s" % (len(tuner.table), tune_s),
+          file=sys.stderr, flush=True)
+    tuned = {k.split("|")[-1]: v["c"] for k, v in tuner.table.items()}
+
+    def jobs_with(cfun, results):
+        jobs, so = [], 0
+        for j, n in enumerate(sizes):
+            o = offs[j]
+            jobs.append((xyu_pool[o * 36:(o + n) * 36], s_dev[so * 8:(so + n) * 8], results[j], n,
+                         cfun(n)))
+            so += n
+        return jobs
+
+    reps = 5
+    out = {"jobs": 64, "points": ntot, "sizes_log2_range": [10, 18], "seed": seed,
+           "autotune_s": tune_s, "tuned_c": tuned}
+    res_b = [api.words(api.MSM_RESULT_WORDS) for _ in sizes]
+    for name, graph in (("batched_graph", True), ("batched_nograph", False)):
+        b = api.Batch(jobs_with(tuner.choose, res_b), use_graph=graph)
+        b.run()
+        ms = timed(b.run, reps, torch)
+        out[name] = {"ms": ms, "msms_per_s": 64 / (ms * 1e-3), "classes": len(
+            {tuner.choose(n) for n in sizes})}
+        b.destroy()
+    maxws = max(api.workspace_bytes(n, c) for n in sizes for c in
+                (api.default_window(n), tuner.choose(n)))
+    ws = torch.empty((maxws + 3) // 4, dtype=torch.int32, device=xyu_pool.device)
+    res_p = [api.words(api.MSM_RESULT_WORDS) for _ in sizes]
+    for name, cfun in (("plain_static_c", api.default_window), ("plain_tuned_c", tuner.choose)):
+        jobs = jobs_with(cfun, res_p)
+
+        def seq():
+            for (x, sc, r, n, c) in jobs:
+                api.msm_run(x, sc, n, c, result=r, ws=ws)
+        seq()
+        ms = timed(seq, reps, torch)
+        out[name] = {"ms": ms, "msms_per_s": 64 / (ms * 1e-3)}
+    torch.cuda.synchronize()
+    same = all(np.array_equal(api.to_host(a), api.to_host(b)) for a, b in zip(res_b, res_p))
+    checked = 0
+    so = 0
+    ok = True
+    for j, n in enumerate(sizes):
+        if offs[j] + n <= len(ks_pool) and checked < 8:
+            ok &= _closed_form_ok(msm_oracle, api, inputs, api.to_host(res_b[j]),
+                                  sw[so:so + n], ks_pool[offs[j]:offs[j] + n])
+            checked += 1
+        so += n
+    out["results_equal_plain_vs_batched"] = bool(same)
+    out["closed_form_checked_jobs"] = checked
+    out["closed_form_ok"] = bool(ok)
+    out["speedup_vs_plain_static"] = out["plain_static_c"]["ms"] / out["batched_graph"]["ms"]
+    print("[bench] batched %.2f ms vs plain %.2f ms" % (out["batched_graph"]["ms"],
+                                                      out["plain_static_c"]["ms"]),
+          file=sys.stderr, flush=True)
+    return out
+
+
+def served_bench(torch, api, inputs, xyu_pool, ks_pool, args):
+    """Poisson arrivals at 200/s, n = floor(2^u), u ~ U[12, 20], replayed
+    through the MSM server and through the plain path one at a time."""
+    import numpy as np
+    from oracle import msm as msm_oracle
+    from paper_2502_11660_amd import autotune, serve
+
+    seed = inputs.config_seed(5)
+    warm, meas = (5.0, 30.0) if args.serve_full else (1.0, args.serve_seconds)
+    arrivals = inputs.poisson_arrivals(seed, 200.0, warm + meas)
+    nreq = len(arrivals)
+    sizes = [int(x) for x in inputs.log_uniform_sizes(seed, nreq, 12, 20, stream=1)]
+    npool = xyu_pool.numel() // 36
+    spool_n = 1 << 21
+    sw = inputs.scalars_mod_r(seed, spool_n, stream=2)
+    s_dev = api.to_device(sw)
+    rng = np.random.Generator(np.random.PCG64([seed, 3]))
+    poffs = [int(rng.integers(0, npool - n + 1)) for n in sizes]
+    soffs = [int(rng.integers(0, spool_n - n + 1)) for n in sizes]
+    tuner = autotune.Autotuner()
+    for u in range(12, 21):
+        if tuner._key(u) not in tuner.table:
+            tuner.tune(u, xyu_pool, s_dev)
+    results = torch.zeros(nreq, api.MSM_RESULT_WORDS, dtype=torch.int32, device=xyu_pool.device)
+
+    def jobs_for(cfun):
+        return [(xyu_pool[po * 36:(po + n) * 36], s_dev[so * 8:(so + n) * 8], results[i], n, cfun(n))
+                for i, (n, po, so) in enumerate(zip(sizes, poffs, soffs))]
+
+    measured = np.asarray(arrivals) >= warm
+    free, _ = torch.cuda.mem_get_info()
+    out = {"rate_per_s": 200.0, "warmup_s": warm, "measured_s": meas, "requests": nreq,
+           "sizes_log2_range": [12, 20], "seed": seed, "streams": 4}
+    budgets = [("half_free_hbm", int(free * 0.5))]
+    if args.serve_full:
+        budgets.append(("2GB", 2 << 30))
+    served_words = None
+    for name, budget in budgets:
+        srv = api.Server(budget, streams=4)
+        print("[bench] serving %d requests, budget %.1f GB ..." % (nreq, budget / 1e9),
+              file=sys.stderr, flush=True)
+        lat, wall = serve.replay_served(srv, arrivals, jobs_for(tuner.choose), progress_every=5.0)
+        srv.destroy()
+        out[name] = serve.summarize(lat, wall, measured)
+        out[name]["budget_bytes"] = budget
+        if served_words is None:
+            torch.cuda.synchronize()
+            served_words = results.cpu().numpy().copy()
+    results.zero_()
+    maxws = max(api.workspace_bytes(n, 0) for n in set(sizes))
+    ws = torch.empty((maxws + 3) // 4, dtype=torch.int32, device=xyu_pool.device)
+    print("[bench] plain replay ...", file=sys.stderr, flush=True)
+    lat_p, wall_p = serve.replay_plain(arrivals, jobs_for(lambda n: 0),
+                                       workspaces=lambda n, c: ws, progress_every=5.0)
+    out["plain_fifo"] = serve.summarize(lat_p, wall_p, measured)
+    plain_words = results.cpu().numpy()
+    out["results_equal_served_vs_plain"] = bool(np.array_equal(served_words, plain_words))
+    ok, checked = True, 0
+    for i, n in enumerate(sizes):
+        if poffs[i] + n <= len(ks_pool) and checked < 6:
+            ok &= _closed_form_ok(msm_oracle, api, inputs, plain_words[i].view(np.uint32),
+                                  sw[soffs[i]:soffs[i] + n], ks_pool[poffs[i]:poffs[i] + n])
+            checked += 1
+    out["closed_form_checked_requests"] = checked
+    out["closed_form_ok"] = bool(ok)
+    return out
+
+
+def accum_traffic():
+    """HBM bytes per accumulation launch from the committed rocprofv3 counter
+    summary, if it was taken on the current accumulation kernel sources."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_accum_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for src in rec.get("sources", []):
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec.get("sources_sha256"):
+        return None
+    return rec.get("bytes_per_launch")
 
 
 if __name__ == "__main__":

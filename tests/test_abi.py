@@ -93,6 +93,20 @@ def test_argument_validation_without_gpu(lib):
     assert h.value is None
     assert lib.msm_batch_run(None, None) == _lib.MSM_EINVAL
     assert lib.msm_batch_destroy(None) == _lib.MSM_OK
+    # server: argument checks come before any device call
+    srv = ctypes.c_void_p()
+    assert lib.msm_server_create(0, 4, S, ctypes.byref(srv)) == _lib.MSM_EINVAL
+    assert lib.msm_server_create(1 << 30, 0, S, ctypes.byref(srv)) == _lib.MSM_EINVAL
+    assert lib.msm_server_create(1 << 30, 17, S, ctypes.byref(srv)) == _lib.MSM_EINVAL
+    assert lib.msm_server_create(1 << 30, 4, 9, ctypes.byref(srv)) == _lib.MSM_EINVAL
+    assert lib.msm_server_create(1 << 30, 4, S, None) == _lib.MSM_EINVAL
+    t = ctypes.c_uint64()
+    assert lib.msm_server_submit(None, jobs, ctypes.byref(t)) == _lib.MSM_EINVAL
+    k = ctypes.c_size_t()
+    assert lib.msm_server_progress(None, None, 0, ctypes.byref(k)) == _lib.MSM_EINVAL
+    assert lib.msm_server_drain(None) == _lib.MSM_EINVAL
+    assert lib.msm_server_stats(None, None, None, None) == _lib.MSM_EINVAL
+    assert lib.msm_server_destroy(None) == _lib.MSM_OK
     assert lib.msm_status_string(_lib.MSM_ENOSPC).startswith(b"MSM_ENOSPC")
 
 
