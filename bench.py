@@ -400,14 +400,14 @@ def batched_bench(torch, api, inputs, xyu_pool, ks_pool, args):
     rng = np.random.Generator(np.random.PCG64([seed, 3]))
     offs = [int(rng.integers(0, N_CHECK_POOL - n + 1)) if n <= N_CHECK_POOL // 2
             else int(rng.integers(0, npool - n + 1)) for n in sizes]
-    tuner = autotune.Autotuner()
+    tuner = autotune.Autotuner(context="batch")
     t0 = time.perf_counter()
     for u in sorted({autotune.n_bucket(n) for n in sizes}):
         tuner.tune(u, xyu_pool, s_dev)
     tune_s = time.perf_counter() - t0
     print("[bench] autotuned %d size classes in %.1f s" % (len(tuner.table), tune_s),
           file=sys.stderr, flush=True)
-    tuned = {k.split("|")[-1]: v["c"] for k, v in tuner.table.items()}
+    tuned = {"u%d" % u: tuner.choose(1 << u) for u in sorted({autotune.n_bucket(n) for n in sizes})}
 
     def jobs_with(cfun, results):
         jobs, so = [], 0
@@ -482,10 +482,11 @@ def served_bench(torch, api, inputs, xyu_pool, ks_pool, args):
     rng = np.random.Generator(np.random.PCG64([seed, 3]))
     poffs = [int(rng.integers(0, npool - n + 1)) for n in sizes]
     soffs = [int(rng.integers(0, spool_n - n + 1)) for n in sizes]
-    tuner = autotune.Autotuner()
+    tuner = autotune.Autotuner(context="solo")
     for u in range(12, 21):
-        if tuner._key(u) not in tuner.table:
+        if not tuner.tuned(u):
             tuner.tune(u, xyu_pool, s_dev)
+    out_tuned = {"u%d" % u: tuner.choose(1 << u) for u in range(12, 21)}
     results = torch.zeros(nreq, api.MSM_RESULT_WORDS, dtype=torch.int32, device=xyu_pool.device)
 
     def jobs_for(cfun):
@@ -495,7 +496,8 @@ def served_bench(torch, api, inputs, xyu_pool, ks_pool, args):
     measured = np.asarray(arrivals) >= warm
     free, _ = torch.cuda.mem_get_info()
     out = {"rate_per_s": 200.0, "warmup_s": warm, "measured_s": meas, "requests": nreq,
-           "sizes_log2_range": [12, 20], "seed": seed, "streams": 4}
+           "sizes_log2_range": [12, 20], "seed": seed, "streams": 4,
+           "tuned_c_solo": out_tuned}
     budgets = [("half_free_hbm", int(free * 0.5))]
     if args.serve_full:
         budgets.append(("2GB", 2 << 30))

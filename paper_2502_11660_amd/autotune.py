@@ -1,9 +1,13 @@
 """Window-width autotuner for batched and served MSMs.
 
-For a size class (n-bucket u = floor(log2 n)) it times batches of MSMs of
-size 2^u at candidate window widths around the static heuristic
-(msm_default_window) and keeps the fastest.  Results are cached per device
-(name and architecture) and n-bucket in a JSON file, by default
+For a size class (n-bucket u = floor(log2 n)) it times MSMs of size 2^u at
+candidate window widths around the static heuristic (msm_default_window) and
+keeps the fastest.  The timing context matters: in a batch many jobs share
+the chip, so narrower windows (less aggregation, more accumulation) win; a
+served request mostly runs alone, where latency favours the solo optimum.
+Context "batch" times batches of up to 64 jobs (about 2^20 points in all),
+context "solo" one job at a time.  Results are cached per device (name and
+architecture), context and n-bucket in a JSON file, by default
 ~/.cache/paper_2502_11660_amd/autotune.json (MSM_AUTOTUNE_CACHE overrides it).
 Timing runs the library's own kernels on the current stream; nothing here
 computes any part of an MSM.
@@ -33,9 +37,12 @@ def n_bucket(n):
 
 
 class Autotuner:
-    def __init__(self, path=None, encoding=api.MSM_DIGITS_SIGNED):
+    def __init__(self, path=None, encoding=api.MSM_DIGITS_SIGNED, context="batch"):
+        if context not in ("batch", "solo"):
+            raise ValueError("context must be 'batch' or 'solo'")
         self.path = path or cache_path()
         self.encoding = encoding
+        self.context = context
         self.table = {}
         try:
             with open(self.path) as f:
@@ -44,7 +51,10 @@ class Autotuner:
             self.table = {}
 
     def _key(self, u):
-        return "%s|enc%d|u%d" % (device_key(), self.encoding, u)
+        return "%s|enc%d|%s|u%d" % (device_key(), self.encoding, self.context, u)
+
+    def tuned(self, u):
+        return self._key(u) in self.table
 
     def choose(self, n):
         """Tuned width for n's size class, else the static heuristic."""
@@ -52,13 +62,14 @@ class Autotuner:
         return int(ent["c"]) if ent else api.default_window(int(n))
 
     def tune(self, u, xyu_pool, scalar_pool, span=(-3, 2), reps=3, batch_points=1 << 20):
-        """Time batches of jobs of size 2^u (about batch_points points in all,
-        at most 64 jobs) over pool slices; store and return the best width."""
+        """Time jobs of size 2^u over pool slices -- batches of about
+        batch_points points (at most 64 jobs) in context "batch", single jobs
+        in context "solo" -- and store and return the best width."""
         n = 1 << u
         npool = xyu_pool.numel() // api.XYU_WORDS
         if n > npool or n > scalar_pool.numel() // api.SCALAR_WORDS:
             raise ValueError("pool smaller than 2^%d" % u)
-        jobs_n = max(1, min(64, batch_points // n))
+        jobs_n = max(1, min(64, batch_points // n)) if self.context == "batch" else 1
         c0 = api.default_window(n)
         cands = [c for c in range(c0 + span[0], c0 + span[1] + 1) if 2 <= c <= 20]
         times = {}

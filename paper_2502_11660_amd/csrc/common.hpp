@@ -121,11 +121,11 @@ struct Plan {
   uint32_t K = 32;    // entries per accumulation chunk
   uint32_t lo_bits = 0, hi_bits = 0;  // split of the bb bucket bits in the sort
   size_t ncounts = 0, nb = 0;         // sort count matrix size, its scan blocks
-  JobDesc one{};                      // the job when J = 1
+  JobDesc one{};  // the job when J = 1; otherwise one.xyu is the base of segment offsets
   // byte offsets into the workspace
   size_t o_flags = 0, o_total = 0, o_offsets = 0, o_counts = 0, o_blocksums = 0, o_digits = 0,
          o_tmp = 0, o_key = 0, o_idx = 0, o_head = 0, o_tail = 0, o_buckets = 0, o_lvl0 = 0,
-         o_lvl1 = 0, o_wsum = 0, o_qstate = 0, o_longlist = 0, o_jobs = 0, o_segpts = 0, bytes = 0;
+         o_lvl1 = 0, o_wsum = 0, o_qstate = 0, o_longlist = 0, o_jobs = 0, o_segoff = 0, bytes = 0;
 };
 
 int num_windows(int c, int encoding);

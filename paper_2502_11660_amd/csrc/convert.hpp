@@ -4,46 +4,9 @@
 
 namespace msm {
 
-__device__ __forceinline__ bool fe_is_one_plain(const fe& a) {
-  uint32_t o = a.v[0] ^ 1u;
-#pragma unroll
-  for (int i = 1; i < NL; ++i) o |= a.v[i];
-  return o == 0;
-}
-
-// a >> t for 0 <= t <= 31
-__device__ __forceinline__ fe fe_shr(const fe& a, uint32_t t) {
-  fe r;
-#pragma unroll
-  for (int i = 0; i < NL - 1; ++i) r.v[i] = __builtin_amdgcn_alignbit(a.v[i + 1], a.v[i], t);
-  r.v[NL - 1] = a.v[NL - 1] >> t;
-  return r;
-}
-
-// x * 2^-t mod p for canonical x and 1 <= t <= 31: adds m p with
-// m = -x mod 2^t (p = 1 mod 2^46, so -p^-1 = -1 mod 2^t), making the sum
-// divisible by 2^t; the quotient is < (x + (2^t - 1) p) / 2^t < p.
-__device__ __forceinline__ fe fe_div_pow2(const fe& x, uint32_t t) {
-  const uint32_t m = (0u - x.v[0]) & ((1u << t) - 1u);
-  uint32_t y[NL + 1];
-  uint64_t acc = 0;
-#pragma unroll
-  for (int i = 0; i < NL; ++i) {
-    acc = (uint64_t)m * kP[i] + x.v[i] + (acc >> 32);
-    y[i] = (uint32_t)acc;
-  }
-  y[NL] = (uint32_t)(acc >> 32);
-  fe r;
-#pragma unroll
-  for (int i = 0; i < NL; ++i) r.v[i] = __builtin_amdgcn_alignbit(y[i + 1], y[i], t);
-  return r;
-}
-
-// Plain C++ multiword helpers for the data-dependent inversion loop.  The
-// hand-scheduled carry sequences of field.hpp pass carries through wave-wide
-// lane masks, which the compiler treats as uniform values; inside the
-// divergent branches of this loop the compiler is left to derive the carry
-// code itself.
+// Plain C++ multiword helpers for the data-dependent inversion loop (the
+// carry sequences of field.hpp pass carries through wave-wide lane masks,
+// which the compiler treats as uniform values).
 
 // r = a - b; returns 1 if a < b
 __device__ __forceinline__ uint32_t fe_sub_c(const fe& a, const fe& b, fe& r) {
@@ -68,47 +31,163 @@ __device__ __forceinline__ fe fe_add_c(const fe& a, const fe& b) {
   return r;
 }
 
-// x - y mod p for canonical x, y
-__device__ __forceinline__ fe fe_sub_mod(const fe& x, const fe& y) {
-  fe d;
-  uint32_t br = fe_sub_c(x, y, d);
-  return br ? fe_add_c(d, fe_const(kP)) : d;
+// ---------------------------------------------------------------------------
+// Modular inversion by the binary extended Euclidean algorithm with the
+// divsteps batched 31 at a time (T. Pornin, "Optimized Binary GCD for Modular
+// Inversion", 2020).  State: a, b >= 0 and u, v mod p with a = u y and
+// b = v y (mod p), starting from (a, b, u, v) = (y, p, 1, 0).  One divstep:
+// if a is odd, order the pair so that a >= b and replace a by a - b; then
+// halve a.  Thirty-one divsteps only look at the low 31 bits of a and b
+// (parity) and at their top bits (the comparisons), so they run on 64-bit
+// approximations built from the low 31 bits and the 33 bits below the common
+// bit length; their effect is a matrix [[f0, g0], [f1, g1]] with
+// |f| + |g| <= 2^31, applied once to the full values:
+//   a <- (f0 a + g0 b) / 2^31,  b <- (f1 a + g1 b) / 2^31
+// (made non-negative by flipping the row's sign when needed), and likewise to
+// u, v with the division by 2^31 done mod p (add m p with m = -x mod 2^31,
+// valid because p = 1 mod 2^46).  After 2 * 377 - 1 divsteps a = 0 and
+// b = gcd = 1, so v = y^-1; 26 rounds of 31 cover them (extra rounds leave
+// the state unchanged once a = 0).  Plain C++ throughout: the loop is
+// data-dependent per lane.
+// ---------------------------------------------------------------------------
+
+constexpr int INV_ROUNDS = 26;
+
+// larger bit length of a and b
+__device__ __forceinline__ uint32_t bitlen_max(const fe& a, const fe& b) {
+  uint32_t n = 0;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    const uint32_t w = a.v[i] | b.v[i];
+    n = w ? (uint32_t)(32 * i + 32) - (uint32_t)__builtin_clz(w) : n;
+  }
+  return n;
 }
 
-// Plain modular inverse a^-1 mod p of a canonical 0 < a < p by the binary
-// extended Euclidean algorithm (invariants x1 a = u, x2 a = v mod p); factors
-// of two are removed up to 31 at a time.  Returns 0 for a = 0.  Every pass
-// removes at least one bit from u or v or makes one of them even, so 2048
-// passes always suffice (at most ~600 are used) and the loop is bounded.
-__device__ __noinline__ fe fe_inv_plain(const fe& a) {
-  if (fe_is_zero_canon(a)) return fe_zero();
-  fe u = a, v = fe_const(kP);
-  fe x1 = fe_zero(), x2 = fe_zero();
-  x1.v[0] = 1u;
-  for (int guard = 0; guard < 2048; ++guard) {
-    if (fe_is_one_plain(u)) return x1;
-    if (fe_is_one_plain(v)) return x2;
-    if ((u.v[0] & 1u) == 0u) {
-      uint32_t t = u.v[0] ? (uint32_t)__builtin_ctz(u.v[0]) : 31u;
-      u = fe_shr(u, t);
-      x1 = fe_div_pow2(x1, t);
-    } else if ((v.v[0] & 1u) == 0u) {
-      uint32_t t = v.v[0] ? (uint32_t)__builtin_ctz(v.v[0]) : 31u;
-      v = fe_shr(v, t);
-      x2 = fe_div_pow2(x2, t);
-    } else {
-      fe d;
-      if (!fe_sub_c(u, v, d)) {  // u >= v
-        u = d;
-        x1 = fe_sub_mod(x1, x2);
-      } else {
-        fe_sub_c(v, u, d);
-        v = d;
-        x2 = fe_sub_mod(x2, x1);
-      }
-    }
+// the 64 bits of x starting at bit pos (0 <= pos < 384), zero-filled
+__device__ __forceinline__ uint64_t bits_at(const fe& x, uint32_t pos) {
+  const uint32_t wi = pos >> 5, sh = pos & 31;
+  uint32_t w0 = 0, w1 = 0, w2 = 0;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    w0 = ((uint32_t)i == wi) ? x.v[i] : w0;
+    w1 = ((uint32_t)i == wi + 1) ? x.v[i] : w1;
+    w2 = ((uint32_t)i == wi + 2) ? x.v[i] : w2;
   }
-  return fe_zero();
+  const uint64_t lo = ((uint64_t)w1 << 32) | w0;
+  uint64_t r = lo >> sh;
+  if (sh) r |= (uint64_t)w2 << (64 - sh);
+  return r;
+}
+
+// w[0..12] = x f + y g as a 13-word two's-complement value; needs
+// |f| + |g| <= 2^31 so that every partial sum fits in int64
+__device__ __forceinline__ void lin_comb(const fe& x, const fe& y, int64_t f, int64_t g,
+                                         uint32_t* w) {
+  int64_t carry = 0;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    const int64_t t = (int64_t)x.v[i] * f + (int64_t)y.v[i] * g + carry;
+    w[i] = (uint32_t)t;
+    carry = t >> 32;
+  }
+  w[NL] = (uint32_t)carry;
+}
+
+// two's complement negation of a 12-word value
+__device__ __forceinline__ fe fe_neg_words(const fe& x) {
+  fe r;
+  uint64_t c = 1;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    c += (uint64_t)(~x.v[i]);
+    r.v[i] = (uint32_t)c;
+    c >>= 32;
+  }
+  return r;
+}
+
+// (x f + y g) / 2^31 for non-negative x, y whose combination is divisible by
+// 2^31 and below 2^384 in magnitude: returns the magnitude, neg = sign
+__device__ __forceinline__ fe comb_shift(const fe& x, const fe& y, int64_t f, int64_t g,
+                                         bool& neg) {
+  uint32_t w[NL + 1];
+  lin_comb(x, y, f, g, w);
+  fe r;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) r.v[i] = __builtin_amdgcn_alignbit(w[i + 1], w[i], 31);
+  neg = (int32_t)w[NL] < 0;
+  return neg ? fe_neg_words(r) : r;
+}
+
+// (x f + y g) / 2^31 mod p for canonical x, y; canonical result
+__device__ __forceinline__ fe comb_shift_mod(const fe& x, const fe& y, int64_t f, int64_t g) {
+  uint32_t w[NL + 1];
+  lin_comb(x, y, f, g, w);
+  const uint32_t m = (0u - w[0]) & 0x7fffffffu;  // makes the sum divisible by 2^31
+  uint32_t r[NL];
+  uint64_t c = 0;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    c = (uint64_t)w[i] + (uint64_t)m * kP[i] + (c >> 32);
+    r[i] = (uint32_t)c;
+  }
+  const int64_t top = (int64_t)(int32_t)w[NL] + (int64_t)(c >> 32);
+  fe q;
+#pragma unroll
+  for (int i = 0; i < NL - 1; ++i) q.v[i] = __builtin_amdgcn_alignbit(r[i + 1], r[i], 31);
+  q.v[NL - 1] = __builtin_amdgcn_alignbit((uint32_t)top, r[NL - 1], 31);
+  // |x f + y g| <= 2^31 p and m p < 2^31 p, so q lies in (-p, 2p)
+  const fe P = fe_const(kP);
+  if ((top >> 31) < 0) return fe_add_c(q, P);
+  fe d;
+  const uint32_t borrow = fe_sub_c(q, P, d);
+  return borrow ? q : d;
+}
+
+// Plain modular inverse y^-1 mod p of a canonical y (0 for y = 0).
+__device__ __noinline__ fe fe_inv_plain(const fe& y) {
+  fe a = y, b = fe_const(kP), u = fe_zero(), v = fe_zero();
+  u.v[0] = 1u;
+  for (int round = 0; round < INV_ROUNDS; ++round) {
+    uint32_t n = bitlen_max(a, b);
+    n = n < 64 ? 64u : n;
+    const uint64_t lo31 = 0x7fffffffull;
+    uint64_t ab = (a.v[0] & lo31) | ((bits_at(a, n - 33) & 0x1ffffffffull) << 31);
+    uint64_t bb = (b.v[0] & lo31) | ((bits_at(b, n - 33) & 0x1ffffffffull) << 31);
+    int64_t f0 = 1, g0 = 0, f1 = 0, g1 = 1;
+    for (int j = 0; j < 31; ++j) {
+      const bool odd = (ab & 1u) != 0;
+      const bool sw = odd && ab < bb;
+      const uint64_t ta = sw ? bb : ab, tb = sw ? ab : bb;
+      const int64_t tf0 = sw ? f1 : f0, tf1 = sw ? f0 : f1;
+      const int64_t tg0 = sw ? g1 : g0, tg1 = sw ? g0 : g1;
+      ab = (odd ? ta - tb : ta) >> 1;
+      bb = tb;
+      f0 = odd ? tf0 - tf1 : tf0;
+      g0 = odd ? tg0 - tg1 : tg0;
+      f1 = tf1 * 2;
+      g1 = tg1 * 2;
+    }
+    bool na, nb;
+    const fe a2 = comb_shift(a, b, f0, g0, na);
+    const fe b2 = comb_shift(a, b, f1, g1, nb);
+    if (na) {
+      f0 = -f0;
+      g0 = -g0;
+    }
+    if (nb) {
+      f1 = -f1;
+      g1 = -g1;
+    }
+    const fe u2 = comb_shift_mod(u, v, f0, g0);
+    const fe v2 = comb_shift_mod(u, v, f1, g1);
+    a = a2;
+    b = b2;
+    u = u2;
+    v = v2;
+  }
+  return v;
 }
 
 // Inverse in Montgomery form: (aR)^-1 R^3 R^-1 = a^-1 R.  Input any value < 2p

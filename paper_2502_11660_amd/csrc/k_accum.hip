@@ -25,18 +25,19 @@ constexpr uint32_t SMALL_SPAN = 8;
 
 // Chunk ch covers entries [ch K, min((ch+1) K, E)), E = offsets[M].  The
 // entry's index word is the point index in its job with the digit's sign in
-// bit 31; segpts[s] is the point array of segment s's job (NULL: one job,
-// points at pts).
+// bit 31; segoff[s] is the word offset of segment s's point array from pts
+// (NULL: one job, points at pts).  Addressing from the kernel argument keeps
+// the point loads global (not flat) memory instructions.
 
 __device__ __forceinline__ const uint32_t* entry_point(const uint32_t* __restrict__ pts,
-                                                       const uint64_t* __restrict__ segpts,
+                                                       const int64_t* __restrict__ segoff,
                                                        uint32_t bb, uint32_t k, uint32_t e) {
-  const uint32_t* base = segpts ? reinterpret_cast<const uint32_t*>(segpts[k >> bb]) : pts;
-  return base + (size_t)(e & 0x7fffffffu) * XYU_WORDS;
+  const int64_t off = segoff ? segoff[k >> bb] : 0;
+  return pts + off + (int64_t)(e & 0x7fffffffu) * XYU_WORDS;
 }
 
 __global__ void __launch_bounds__(256) k_accum(const uint32_t* __restrict__ pts,
-                                               const uint64_t* __restrict__ segpts, uint32_t bb,
+                                               const int64_t* __restrict__ segoff, uint32_t bb,
                                                const uint32_t* __restrict__ key,
                                                const uint32_t* __restrict__ idx,
                                                const uint32_t* __restrict__ offsets, uint32_t M,
@@ -56,7 +57,7 @@ __global__ void __launch_bounds__(256) k_accum(const uint32_t* __restrict__ pts,
   bool first_seg = true;
   xytz acc = pt_identity();
   uint32_t ie = idx[s];
-  xyu P = ld_xyu(entry_point(pts, segpts, bb, cur, ie));
+  xyu P = ld_xyu(entry_point(pts, segoff, bb, cur, ie));
   for (uint32_t p = s; p < e; ++p) {
     const uint32_t k = key[p];
     if (k != cur) {
@@ -70,7 +71,7 @@ __global__ void __launch_bounds__(256) k_accum(const uint32_t* __restrict__ pts,
     // prefetch the next entry's point
     const uint32_t pn = (p + 1 < e) ? p + 1 : p;
     const uint32_t ien = idx[pn];
-    xyu Pn = ld_xyu(entry_point(pts, segpts, bb, key[pn], ien));
+    xyu Pn = ld_xyu(entry_point(pts, segoff, bb, key[pn], ien));
     acc = padd_mixed_signed(acc, P, (ie >> 31) != 0u, p2);
     P = Pn;
     ie = ien;
@@ -180,14 +181,14 @@ int launch_accumulate(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t s
   uint32_t* head = ws_at<uint32_t>(ws, pl.o_head);
   uint32_t* tail = ws_at<uint32_t>(ws, pl.o_tail);
   uint32_t* longlist = ws_at<uint32_t>(ws, pl.o_longlist);
-  const uint64_t* segpts = pl.J == 1 ? nullptr : ws_at<const uint64_t>(ws, pl.o_segpts);
+  const int64_t* segoff = pl.J == 1 ? nullptr : ws_at<const int64_t>(ws, pl.o_segoff);
   const uint32_t K = pl.K, M = (uint32_t)pl.M;
   const unsigned grid = grid_for(pl.chunks, 256);
   int rc;
   if ((rc = launch_fill_u32(longlist, 1, 0u, st)) != MSM_OK) return rc;
   {
     ProfScope prof(PT_ACCUM, st);
-    k_accum<<<grid, 256, 0, st>>>(pl.one.xyu, segpts, (uint32_t)pl.bb, key, idx, offsets, M, K,
+    k_accum<<<grid, 256, 0, st>>>(pl.one.xyu, segoff, (uint32_t)pl.bb, key, idx, offsets, M, K,
                                   buckets, head, tail);
   }
   ProfScope prof(PT_MERGE, st);

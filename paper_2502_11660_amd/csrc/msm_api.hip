@@ -147,7 +147,7 @@ bool make_plan(const size_t* ns, uint32_t J, int c, int encoding, Plan& pl) {
   pl.o_wsum = take(2 * pl.S * rec);
   pl.o_qstate = take((size_t)J * rec);
   pl.o_jobs = take((size_t)J * sizeof(JobDesc));
-  pl.o_segpts = take(pl.S * 8);
+  pl.o_segoff = take(pl.S * 8);
   pl.bytes = o;
   return true;
 }

@@ -101,12 +101,14 @@ int create(const msm_job* jobs, size_t njobs, int encoding, void* ws, size_t ws_
   HIPCHK(hipGetDevice(&b->device));
   b->ws = static_cast<char*>(ws);
   b->use_graph = use_graph != 0;
-  // job tables: JobDesc per job, point array per segment
+  // job tables: JobDesc per job; per segment the word offset of its job's
+  // points from the first job's
   size_t k = 0;
   for (const auto& kv : cls) {
     Plan& pl = b->plans[k];
     std::vector<JobDesc> tab(kv.second.size());
-    std::vector<uint64_t> segpts(pl.S);
+    std::vector<int64_t> segoff(pl.S);
+    const uint32_t* base_pts = jobs[kv.second[0]].xyu;
     uint32_t pt_off = 0, tile_off = 0;
     for (size_t j = 0; j < kv.second.size(); ++j) {
       const msm_job& jb = jobs[kv.second[j]];
@@ -120,13 +122,14 @@ int create(const msm_job* jobs, size_t njobs, int encoding, void* ws, size_t ws_
       d.tps = (uint32_t)((jb.n + SORT_TILE - 1) / SORT_TILE);
       pt_off += d.n;
       tile_off += d.tps;
-      for (int w = 0; w < pl.W; ++w) segpts[j * pl.W + w] = (uint64_t)(uintptr_t)jb.xyu;
+      const int64_t off = (int64_t)(jb.xyu - base_pts);
+      for (int w = 0; w < pl.W; ++w) segoff[j * pl.W + w] = off;
     }
-    if (pl.J == 1) pl.one = tab[0];
+    pl.one = tab[0];
     char* base = b->ws + b->ws_off[k];
     HIPCHK(hipMemcpy(base + pl.o_jobs, tab.data(), tab.size() * sizeof(JobDesc),
                      hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(base + pl.o_segpts, segpts.data(), segpts.size() * 8,
+    HIPCHK(hipMemcpy(base + pl.o_segoff, segoff.data(), segoff.size() * 8,
                      hipMemcpyHostToDevice));
     ++k;
   }
