@@ -536,6 +536,342 @@ def served_bench(torch, api, inputs, xyu_pool, ks_pool, args):
 def accum_traffic():
     """HBM bytes per accumulation launch from the committed rocprofv3 counter
     summary, if it was taken on the current accumulation kernel sources."""
+    from paper_2502_11660_amd import profsum
+    path = os.path.join(ROOT, "profiles", "k_accum_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("sources_sha256") != profsum.sources_sha256(rec.get("sources", [])):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--c", type=int, default=0, help="window width (0: sweep 10..16, take the best)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-padd-kernel", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served workload")
+    ap.add_argument("--serve-seconds", type=float, default=6.0,
+                    help="measured seconds of the served trace (after 1 s of warm-up)")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="served trace of 5 s warm-up + 30 s, plus a run with a 2 GB budget")
+    ap.add_argument("--microbench", action="store_true",
+                    help="only measure the VALU mad / carry-add issue rates and HBM copy bandwidth")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X and has no "
+              "multi-GPU path (requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    if args.microbench:
+        print(json.dumps(microbench()))
+        return
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(16)
+
+    import numpy as np
+    import torch
+
+    from paper_2502_11660_amd import api, inputs
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    n = N_POINTS
+    seed = inputs.config_seed(3)
+    kw = inputs.nonzero_scalars_mod_r(seed, n, stream=1)
+    sw = inputs.scalars_mod_r(seed, n, stream=2)
+    k_dev = api.to_device(kw, dev)
+    s_dev = api.to_device(sw, dev)
+
+    print("[bench] generating %d points on the GPU ..." % n, file=sys.stderr, flush=True)
+    xy, inf = api.gen_points(k_dev, n)
+    torch.cuda.synchronize()
+    xyu = None
+
+    def prep():
+        nonlocal xyu
+        xyu, _ = api.points_prepare(xy, n, inf=inf, out=xyu)
+
+    prep()
+    prepare_ms = timed(prep, 3, torch)
+
+    # window sweep
+    sweep = {}
+    cs = [args.c] if args.c else C_SWEEP
+    for c in cs:
+        ws = api.workspace(n, c, device=dev)
+        res = api.words(api.MSM_RESULT_WORDS, dev)
+        fn = lambda: api.msm_run(xyu, s_dev, n, c, result=res, ws=ws)
+        fn()
+        sweep[c] = timed(fn, 2, torch)
+        del ws
+        print("[bench] c=%d: %.3f ms" % (c, sweep[c]), file=sys.stderr, flush=True)
+    best_c = min(sweep, key=sweep.get)
+
+    ws = api.workspace(n, best_c, device=dev)
+    res = api.words(api.MSM_RESULT_WORDS, dev)
+    step = lambda: api.msm_run(xyu, s_dev, n, best_c, result=res, ws=ws)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    for ph in ("sort", "accum", "merge", "agg", "horner"):
+        api.profile_read(ph)
+    api.profile_enable(True)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(args.steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    api.profile_enable(False)
+    ms_per_step = t0.elapsed_time(t1) / args.steps
+    phases = {}
+    for ph in ("sort", "accum", "merge", "agg", "horner"):
+        tot, cnt = api.profile_read(ph)
+        phases[ph] = tot / max(cnt, 1)
+    accum_tot_ms = phases["accum"]
+
+    entries = nonzero_digit_entries(sw, best_c)
+    padds = padd_count_executed(entries, best_c)
+    value = padds / (ms_per_step * 1e-3)
+    accum_mads = entries * MULS_MIXED * MAD_PER_MUL
+    achieved = accum_mads / (accum_tot_ms * 1e-3)
+
+    padd_k = None
+    if not args.no_padd_kernel:
+        pool_n = 8192
+        padd_k = padd_kernel_bench(torch, api, xyu[:pool_n * 36], pool_n, 1 << 22, 5)
+
+    if cpu is not None:
+        cpu["msm_ms_extrapolated"] = padds / cpu["value"] * 1e3
+        cpu["sample"] = cpu["sample"].replace("c=16", "c=%d" % best_c)
+
+    del ws
+    ks_pool = [inputs.words_to_int(r) for r in kw[:N_CHECK_POOL]]
+    batched = None
+    if not args.no_batch:
+        batched = batched_bench(torch, api, inputs, xyu, ks_pool, args)
+    served = None
+    if not args.no_serve:
+        served = served_bench(torch, api, inputs, xyu, ks_pool, args)
+
+    out = {
+        "metric": "PADDs/s and MSM latency (ms) at n=2^20; batched/served MSMs/s + p99 vs plain",
+        "value": value,
+        "unit": "PADD/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "BLS12-377 G1 MSM, n=2^20 points k_i*G, uniform scalars mod r",
+                   "n": n, "c": best_c, "digits": "signed",
+                   "windows": -(-254 // best_c), "seed": seed,
+                   "padds_per_msm": padds,
+                   "padds_per_msm_unsigned_formula": padd_count_formula(n, best_c)},
+        "msm_ms": ms_per_step,
+        "prepare_ms": prepare_ms,
+        "c_sweep_ms": {str(k): v for k, v in sweep.items()},
+        "phase_ms": phases,
+        "roofline": {
+            "kernel": "k_accum (bucket accumulation, mixed PADD)",
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_MAD_PER_S / 1e12,
+            "unit": "Tmad/s (32x32->64 multiply-adds)",
+            "frac": achieved / PEAK_MAD_PER_S,
+            "traffic": accum_traffic(),
+            "work_per_launch": {"mixed_padds": entries, "mad_per_padd": MULS_MIXED * MAD_PER_MUL},
+            "launch_ms": accum_tot_ms,
+        },
+        "padd_kernel": padd_k,
+        "batched": batched,
+        "served": served,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+# ---------------------------------------------------------------------------
+# batched and served workloads
+# ---------------------------------------------------------------------------
+
+N_CHECK_POOL = 1 << 18   # pool points whose discrete logs the checks use
+
+
+def _closed_form_ok(msm_oracle, api, inputs, res_words, sc_words, ks):
+    ss = [inputs.words_to_int(r) for r in sc_words]
+    return api.decode_result(res_words) == (msm_oracle.closed_form(ss, ks), 0)
+
+
+def batched_bench(torch, api, inputs, xyu_pool, ks_pool, args):
+    """64 MSMs, n_j = floor(2^u), u ~ U[10, 18]: one graph-replayed batch with
+    autotuned widths, against 64 sequential msm_run calls."""
+    import numpy as np
+    from oracle import msm as msm_oracle
+    from paper_2502_11660_amd import autotune
+
+    seed = inputs.config_seed(4)
+    sizes = [int(x) for x in inputs.log_uniform_sizes(seed, 64, 10, 18)]
+    npool = xyu_pool.numel() // 36
+    ntot = sum(sizes)
+    sw = inputs.scalars_mod_r(seed, ntot, stream=2)
+    s_dev = api.to_device(sw)
+    rng = np.random.Generator(np.random.PCG64([seed, 3]))
+    offs = [int(rng.integers(0, N_CHECK_POOL - n + 1)) if n <= N_CHECK_POOL // 2
+            else int(rng.integers(0, npool - n + 1)) for n in sizes]
+    tuner = autotune.Autotuner(context="batch")
+    t0 = time.perf_counter()
+    for u in sorted({autotune.n_bucket(n) for n in sizes}):
+        tuner.tune(u, xyu_pool, s_dev)
+    tune_s = time.perf_counter() - t0
+    print("[bench] autotuned %d size classes in %.1f s" % (len(tuner.table), tune_s),
+          file=sys.stderr, flush=True)
+    tuned = {"u%d" % u: tuner.choose(1 << u) for u in sorted({autotune.n_bucket(n) for n in sizes})}
+
+    def jobs_with(cfun, results):
+        jobs, so = [], 0
+        for j, n in enumerate(sizes):
+            o = offs[j]
+            jobs.append((xyu_pool[o * 36:(o + n) * 36], s_dev[so * 8:(so + n) * 8], results[j], n,
+                         cfun(n)))
+            so += n
+        return jobs
+
+    reps = 5
+    out = {"jobs": 64, "points": ntot, "sizes_log2_range": [10, 18], "seed": seed,
+           "autotune_s": tune_s, "tuned_c": tuned}
+    res_b = [api.words(api.MSM_RESULT_WORDS) for _ in sizes]
+    for name, graph in (("batched_graph", True), ("batched_nograph", False)):
+        b = api.Batch(jobs_with(tuner.choose, res_b), use_graph=graph)
+        b.run()
+        ms = timed(b.run, reps, torch)
+        out[name] = {"ms": ms, "msms_per_s": 64 / (ms * 1e-3), "classes": len(
+            {tuner.choose(n) for n in sizes})}
+        b.destroy()
+    maxws = max(api.workspace_bytes(n, c) for n in sizes for c in
+                (api.default_window(n), tuner.choose(n)))
+    ws = torch.empty((maxws + 3) // 4, dtype=torch.int32, device=xyu_pool.device)
+    res_p = [api.words(api.MSM_RESULT_WORDS) for _ in sizes]
+    for name, cfun in (("plain_static_c", api.default_window), ("plain_tuned_c", tuner.choose)):
+        jobs = jobs_with(cfun, res_p)
+
+        def seq():
+            for (x, sc, r, n, c) in jobs:
+                api.msm_run(x, sc, n, c, result=r, ws=ws)
+        seq()
+        ms = timed(seq, reps, torch)
+        out[name] = {"ms": ms, "msms_per_s": 64 / (ms * 1e-3)}
+    torch.cuda.synchronize()
+    same = all(np.array_equal(api.to_host(a), api.to_host(b)) for a, b in zip(res_b, res_p))
+    checked = 0
+    so = 0
+    ok = True
+    for j, n in enumerate(sizes):
+        if offs[j] + n <= len(ks_pool) and checked < 8:
+            ok &= _closed_form_ok(msm_oracle, api, inputs, api.to_host(res_b[j]),
+                                  sw[so:so + n], ks_pool[offs[j]:offs[j] + n])
+            checked += 1
+        so += n
+    out["results_equal_plain_vs_batched"] = bool(same)
+    out["closed_form_checked_jobs"] = checked
+    out["closed_form_ok"] = bool(ok)
+    out["speedup_vs_plain_static"] = out["plain_static_c"]["ms"] / out["batched_graph"]["ms"]
+    print("[bench] batched %.2f ms vs plain %.2f ms" % (out["batched_graph"]["ms"],
+                                                      out["plain_static_c"]["ms"]),
+          file=sys.stderr, flush=True)
+    return out
+
+
+def served_bench(torch, api, inputs, xyu_pool, ks_pool, args):
+    """Poisson arrivals at 200/s, n = floor(2^u), u ~ U[12, 20], replayed
+    through the MSM server and through the plain path one at a time."""
+    import numpy as np
+    from oracle import msm as msm_oracle
+    from paper_2502_11660_amd import autotune, serve
+
+    seed = inputs.config_seed(5)
+    warm, meas = (5.0, 30.0) if args.serve_full else (1.0, args.serve_seconds)
+    arrivals = inputs.poisson_arrivals(seed, 200.0, warm + meas)
+    nreq = len(arrivals)
+    sizes = [int(x) for x in inputs.log_uniform_sizes(seed, nreq, 12, 20, stream=1)]
+    npool = xyu_pool.numel() // 36
+    spool_n = 1 << 21
+    sw = inputs.scalars_mod_r(seed, spool_n, stream=2)
+    s_dev = api.to_device(sw)
+    rng = np.random.Generator(np.random.PCG64([seed, 3]))
+    poffs = [int(rng.integers(0, npool - n + 1)) for n in sizes]
+    soffs = [int(rng.integers(0, spool_n - n + 1)) for n in sizes]
+    tuner = autotune.Autotuner(context="solo")
+    for u in range(12, 21):
+        if not tuner.tuned(u):
+            tuner.tune(u, xyu_pool, s_dev)
+    out_tuned = {"u%d" % u: tuner.choose(1 << u) for u in range(12, 21)}
+    results = torch.zeros(nreq, api.MSM_RESULT_WORDS, dtype=torch.int32, device=xyu_pool.device)
+
+    def jobs_for(cfun):
+        return [(xyu_pool[po * 36:(po + n) * 36], s_dev[so * 8:(so + n) * 8], results[i], n, cfun(n))
+                for i, (n, po, so) in enumerate(zip(sizes, poffs, soffs))]
+
+    measured = np.asarray(arrivals) >= warm
+    free, _ = torch.cuda.mem_get_info()
+    out = {"rate_per_s": 200.0, "warmup_s": warm, "measured_s": meas, "requests": nreq,
+           "sizes_log2_range": [12, 20], "seed": seed, "streams": 4,
+           "tuned_c_solo": out_tuned}
+    budgets = [("half_free_hbm", int(free * 0.5))]
+    if args.serve_full:
+        budgets.append(("2GB", 2 << 30))
+    served_words = None
+    for name, budget in budgets:
+        srv = api.Server(budget, streams=4)
+        print("[bench] serving %d requests, budget %.1f GB ..." % (nreq, budget / 1e9),
+              file=sys.stderr, flush=True)
+        lat, wall = serve.replay_served(srv, arrivals, jobs_for(tuner.choose), progress_every=5.0)
+        srv.destroy()
+        out[name] = serve.summarize(lat, wall, measured)
+        out[name]["budget_bytes"] = budget
+        if served_words is None:
+            torch.cuda.synchronize()
+            served_words = results.cpu().numpy().copy()
+    results.zero_()
+    maxws = max(api.workspace_bytes(n, 0) for n in set(sizes))
+    ws = torch.empty((maxws + 3) // 4, dtype=torch.int32, device=xyu_pool.device)
+    print("[bench] plain replay ...", file=sys.stderr, flush=True)
+    lat_p, wall_p = serve.replay_plain(arrivals, jobs_for(lambda n: 0),
+                                       workspaces=lambda n, c: ws, progress_every=5.0)
+    out["plain_fifo"] = serve.summarize(lat_p, wall_p, measured)
+    plain_words = results.cpu().numpy()
+    out["results_equal_served_vs_plain"] = bool(np.array_equal(served_words, plain_words))
+    ok, checked = True, 0
+    for i, n in enumerate(sizes):
+        if poffs[i] + n <= len(ks_pool) and checked < 6:
+            ok &= _closed_form_ok(msm_oracle, api, inputs, plain_words[i].view(np.uint32),
+                                  sw[soffs[i]:soffs[i] + n], ks_pool[poffs[i]:poffs[i] + n])
+            checked += 1
+    out["closed_form_checked_requests"] = checked
+    out["closed_form_ok"] = bool(ok)
+    return out
+
+
+def accum_traffic():
+    """HBM bytes per accumulation launch from the committed rocprofv3 counter
+    summary, if it was taken on the current accumulation kernel sources."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_accum_traffic.json")
     try:
