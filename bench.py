@@ -169,7 +169,7 @@ def padd_kernel_bench(torch, api, xyu_pool, pool_n, pairs, reps):
     Bm = soa_b.index_select(2, jb).contiguous().view(-1)
     Bc = a_pool.view(4, 12, pool_n).index_select(2, jb).contiguous().view(-1)
     out = torch.empty_like(A)
-    res = {}
+    res = {"_a_pool": a_pool}
     for name, B, form, muls, nbytes in (("mixed", Bm, api.MSM_FORM_XYU, MULS_MIXED, 48 * 4 * 2 + 36 * 4),
                                         ("complete", Bc, api.MSM_FORM_XYTZ, MULS_COMPLETE, 48 * 4 * 3)):
         fn = lambda: api.padd_batch(A, B, pairs, form, out=out)
@@ -184,6 +184,51 @@ def padd_kernel_bench(torch, api, xyu_pool, pool_n, pairs, reps):
             "frac_of_valu_mad_peak": rate * muls * MAD_PER_MUL / PEAK_MAD_PER_S,
             "hbm_GBps": rate * nbytes / 1e9,
         }
+    return res
+
+
+def chain_and_stream_bench(torch, api, xyu_pool, a_pool_soa, pool_n):
+    """The paper's latency workload (a dependent chain of complete additions
+    over 2^18 points) and its throughput workload (independent accumulators
+    fed prepared points, result returned once)."""
+    recs = a_pool_soa.view(48, pool_n).t().contiguous()          # AoS XYTZ
+    out = {"paper_latency_us_per_padd": 1.05, "paper_throughput_mtask_per_s": 67.0}
+    chain = {}
+    for name, unit, count in (("quad", api.MSM_UNIT_QUAD, 1 << 18), ("lane", api.MSM_UNIT_LANE, 1 << 16)):
+        pts = recs.repeat((count + pool_n - 1) // pool_n, 1)[:count].contiguous().view(-1)
+        api.padd_chain(pts, 64, unit)
+        ms = timed(lambda: api.padd_chain(pts, count, unit), 1, torch)
+        chain[name] = {"count": count, "ms": ms, "us_per_padd": ms * 1e3 / count}
+    out["latency_chain_complete_padd"] = chain
+    npool = xyu_pool.numel() // 36
+    stream = {}
+    for n, A in ((1 << 18, 10), (1 << 18, 1 << 14), (1 << 20, 1 << 17)):
+        n = min(n, npool)
+        api.accumulate_stream(xyu_pool, n, A)
+        ms = timed(lambda: api.accumulate_stream(xyu_pool, n, A), 3, torch)
+        stream["n%d_A%d" % (n, A)] = {"points": n, "accumulators": A, "ms": ms,
+                                       "mtask_per_s": n / (ms * 1e-3) / 1e6}
+    out["accumulation_stream_mixed_padd"] = stream
+    return out
+
+
+def field_core_bench(torch, api, inputs, count=1 << 20, rounds=64):
+    """Montgomery vs Barrett vs Karatsuba-Montgomery field multiplies:
+    count lanes, each chaining `rounds` products."""
+    a = api.to_device(inputs.base_field_elements(inputs.config_seed(2), count, stream=7).T.copy())
+    b = api.to_device(inputs.base_field_elements(inputs.config_seed(2), count, stream=8).T.copy())
+    out = api.words(12 * count)
+    res = {}
+    for name, var, mads in (("montgomery", api.MSM_MUL_MONT, MAD_PER_MUL),
+                            ("barrett_k378", api.MSM_MUL_BARRETT, 144 + 99 + 78),
+                            ("karatsuba_montgomery", api.MSM_MUL_KARATSUBA, 3 * 36 + 132)):
+        api.fe_mul_chain(a, b, count, var, 2, out=out)
+        ms = timed(lambda: api.fe_mul_chain(a, b, count, var, rounds, out=out), 3, torch)
+        rate = count * rounds / (ms * 1e-3)
+        res[name] = {"ms": ms, "mul_per_s": rate, "word_mads_per_mul": mads,
+                     "mad_per_s": rate * mads, "frac_of_valu_mad_peak": rate * mads / PEAK_MAD_PER_S}
+    res["lanes"] = count
+    res["rounds"] = rounds
     return res
 
 
@@ -314,9 +359,12 @@ def main():
     achieved = accum_mads / (accum_tot_ms * 1e-3)
 
     padd_k = None
+    chain_stream = None
     if not args.no_padd_kernel:
         pool_n = 8192
         padd_k = padd_kernel_bench(torch, api, xyu[:pool_n * 36], pool_n, 1 << 22, 5)
+        chain_stream = chain_and_stream_bench(torch, api, xyu, padd_k.pop("_a_pool"), pool_n)
+        chain_stream["field_cores"] = field_core_bench(torch, api, inputs)
 
     if cpu is not None:
         cpu["msm_ms_extrapolated"] = padds / cpu["value"] * 1e3
@@ -365,6 +413,7 @@ def main():
             "launch_ms": accum_tot_ms,
         },
         "padd_kernel": padd_k,
+        "padd_workloads": chain_stream,
         "batched": batched,
         "served": served,
         "cpu_baseline": cpu,
@@ -650,9 +699,12 @@ def main():
     achieved = accum_mads / (accum_tot_ms * 1e-3)
 
     padd_k = None
+    chain_stream = None
     if not args.no_padd_kernel:
         pool_n = 8192
         padd_k = padd_kernel_bench(torch, api, xyu[:pool_n * 36], pool_n, 1 << 22, 5)
+        chain_stream = chain_and_stream_bench(torch, api, xyu, padd_k.pop("_a_pool"), pool_n)
+        chain_stream["field_cores"] = field_core_bench(torch, api, inputs)
 
     if cpu is not None:
         cpu["msm_ms_extrapolated"] = padds / cpu["value"] * 1e3
@@ -701,6 +753,7 @@ def main():
             "launch_ms": accum_tot_ms,
         },
         "padd_kernel": padd_k,
+        "padd_workloads": chain_stream,
         "batched": batched,
         "served": served,
         "cpu_baseline": cpu,

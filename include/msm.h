@@ -84,6 +84,30 @@ extern "C" {
 int msm_padd_batch(const uint32_t* a_xytz, const uint32_t* b, uint32_t* out_xytz, size_t count,
                    int b_form, void* stream);
 
+/* The paper's two PADD workloads outside an MSM (Sec. IV).
+ *
+ * msm_padd_chain -- latency: out = P_0 + P_1 + ... + P_{count-1}, added one
+ *   after another into a single accumulator (starting at the identity), each
+ *   addition waiting for the previous one, with the complete addition.
+ *   pts_xytz: AoS XYTZ records (48 words each, Montgomery form, coordinates
+ *   < 2p).  unit: MSM_UNIT_QUAD (four lanes share one point: the latency unit
+ *   bucket and group aggregation use) or MSM_UNIT_LANE (one lane does the
+ *   whole addition).  out_xytz: one AoS XYTZ record, lazily reduced (< 2p).
+ *   Errors: MSM_EINVAL (null pointers, count = 0 or >= 2^31, unknown unit).
+ *
+ * msm_accumulate_stream -- throughput: `accumulators` independent running
+ *   sums; accumulator a = sum of the prepared points i = a, a + A, a + 2A, ...
+ *   (A = accumulators), mixed addition, each sum written once at the end.
+ *   xyu: AoS prepared records (msm_points_prepare).  out_xytz: A AoS XYTZ
+ *   records (lazily reduced; accumulators without points hold the identity).
+ *   Errors: MSM_EINVAL (null pointers, n = 0, A = 0, n or A >= 2^31). */
+#define MSM_UNIT_QUAD 0
+#define MSM_UNIT_LANE 1
+int msm_padd_chain(const uint32_t* pts_xytz, size_t count, int unit, uint32_t* out_xytz,
+                   void* stream);
+int msm_accumulate_stream(const uint32_t* xyu, size_t n, size_t accumulators, uint32_t* out_xytz,
+                          void* stream);
+
 /* Batched Montgomery product out_i = a_i * b_i * 2^-384 mod p (the field core
  * of every PADD, Sec. III-B/III-C with Montgomery reduction as proposed in
  * Sec. V-C).  a, b, out: SoA with one coordinate (12 x count words).  Inputs
@@ -92,6 +116,24 @@ int msm_padd_batch(const uint32_t* a_xytz, const uint32_t* b, uint32_t* out_xytz
  * Errors: MSM_EINVAL as for msm_padd_batch. */
 int msm_fe_mul_batch(const uint32_t* a, const uint32_t* b, uint32_t* out, size_t count,
                      int canonical, void* stream);
+
+/* Field-multiplication cores compared (the paper's future work, Sec. V-C:
+ * Montgomery reduction and Karatsuba multiplication): out_i = a_i * b_i^rounds
+ * in the variant's arithmetic, each product waiting for the previous one.
+ *  MSM_MUL_MONT: the production Montgomery multiply (R = 2^384):
+ *    out = a b^rounds R^-rounds mod p.
+ *  MSM_MUL_BARRETT: plain residues, Barrett reduction with k = 378:
+ *    out = a b^rounds mod p.
+ *  MSM_MUL_KARATSUBA: Montgomery with one Karatsuba level over 6-word halves
+ *    and a separate reduction: same output as MSM_MUL_MONT.
+ * a, b, out: SoA, one coordinate (12 x count words); inputs canonical
+ * (< p); output canonical.  Errors: MSM_EINVAL (null pointers, count = 0 or
+ * >= 2^31, rounds < 1, unknown variant), MSM_EHIP. */
+#define MSM_MUL_MONT 0
+#define MSM_MUL_BARRETT 1
+#define MSM_MUL_KARATSUBA 2
+int msm_fe_mul_chain(const uint32_t* a, const uint32_t* b, uint32_t* out, size_t count,
+                     int variant, int rounds, void* stream);
 
 /* Convert Weierstrass affine points (x, y), y^2 = x^3 + 1, to prepared
  * twisted-Edwards form (Sec. II-D: inputs as (X, Y, U = k T), Z = 1).

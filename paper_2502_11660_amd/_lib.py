@@ -25,6 +25,11 @@ MSM_MB_ADDC = 1
 MSM_MB_COPY = 2
 MSM_DIGITS_SIGNED = 0
 MSM_DIGITS_UNSIGNED = 1
+MSM_UNIT_QUAD = 0
+MSM_UNIT_LANE = 1
+MSM_MUL_MONT = 0
+MSM_MUL_BARRETT = 1
+MSM_MUL_KARATSUBA = 2
 
 
 class MsmJob(ctypes.Structure):
@@ -59,6 +64,9 @@ SIGNATURES = {
     "msm_server_stats": (_I, [_P, ctypes.POINTER(ctypes.c_size_t),
                               ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
     "msm_server_destroy": (_I, [_P]),
+    "msm_padd_chain": (_I, [_P, _SZ, _I, _P, _P]),
+    "msm_fe_mul_chain": (_I, [_P, _P, _P, _SZ, _I, _I, _P]),
+    "msm_accumulate_stream": (_I, [_P, _SZ, _SZ, _P, _P]),
     "msm_last_hip_error": (_I, []),
     "msm_status_string": (ctypes.c_char_p, [_I]),
     "msm_constants": (_I, [_P, _SZ]),

@@ -14,7 +14,8 @@ import torch
 from . import _lib
 from ._lib import (MSM_DIGITS_SIGNED, MSM_DIGITS_UNSIGNED, MSM_FLAG_EXCEPT,  # noqa: F401
                    MSM_FLAG_OFFCURVE, MSM_FLAG_RANGE, MSM_FORM_XYTZ, MSM_FORM_XYU,
-                   MSM_RESULT_WORDS, MSMError, MsmJob)
+                   MSM_MUL_BARRETT, MSM_MUL_KARATSUBA, MSM_MUL_MONT, MSM_RESULT_WORDS,
+                   MSM_UNIT_LANE, MSM_UNIT_QUAD, MSMError, MsmJob)
 
 WORDS = 12
 XYU_WORDS = 36
@@ -68,6 +69,30 @@ def padd_batch(a_xytz, b, count, b_form, out=None):
     return out
 
 
+def padd_chain(pts_xytz, count, unit=MSM_UNIT_QUAD, out=None):
+    """Sum of count AoS XYTZ records added one after another (latency chain)."""
+    _dev(pts_xytz, "pts_xytz")
+    if pts_xytz.numel() < XYTZ_WORDS * count:
+        raise ValueError("pts_xytz smaller than count records")
+    if out is None:
+        out = words(XYTZ_WORDS, pts_xytz.device)
+    _lib.check("msm_padd_chain", _lib.lib().msm_padd_chain(
+        _ptr(pts_xytz), count, unit, _ptr(out), _stream()))
+    return out
+
+
+def accumulate_stream(xyu, n, accumulators, out=None):
+    """accumulators independent mixed-PADD running sums over strided points."""
+    _dev(xyu, "xyu")
+    if xyu.numel() < XYU_WORDS * n:
+        raise ValueError("xyu smaller than n records")
+    if out is None:
+        out = words(XYTZ_WORDS * accumulators, xyu.device)
+    _lib.check("msm_accumulate_stream", _lib.lib().msm_accumulate_stream(
+        _ptr(xyu), n, accumulators, _ptr(out), _stream()))
+    return out
+
+
 def fe_mul_batch(a, b, count, canonical=True, out=None):
     _dev(a, "a")
     _dev(b, "b")
@@ -77,6 +102,19 @@ def fe_mul_batch(a, b, count, canonical=True, out=None):
         out = words(WORDS * count, a.device)
     _lib.check("msm_fe_mul_batch", _lib.lib().msm_fe_mul_batch(
         _ptr(a), _ptr(b), _ptr(out), count, 1 if canonical else 0, _stream()))
+    return out
+
+
+def fe_mul_chain(a, b, count, variant=MSM_MUL_MONT, rounds=1, out=None):
+    """out_i = a_i * b_i^rounds with the chosen field-multiplication core."""
+    _dev(a, "a")
+    _dev(b, "b")
+    if a.numel() != WORDS * count or b.numel() != WORDS * count:
+        raise ValueError("operand sizes do not match count")
+    if out is None:
+        out = words(WORDS * count, a.device)
+    _lib.check("msm_fe_mul_chain", _lib.lib().msm_fe_mul_chain(
+        _ptr(a), _ptr(b), _ptr(out), count, variant, rounds, _stream()))
     return out
 
 

@@ -81,6 +81,11 @@ def test_argument_validation_without_gpu(lib):
     assert lib.msm_workspace_bytes(1024, 1, S) == 0
     assert lib.msm_workspace_bytes(1024, 1, U) > 0
     assert lib.msm_workspace_bytes(1024, 8, S) > 0
+    assert lib.msm_padd_chain(p, 0, 0, p, None) == _lib.MSM_EINVAL
+    assert lib.msm_padd_chain(p, 4, 5, p, None) == _lib.MSM_EINVAL
+    assert lib.msm_padd_chain(None, 4, 0, p, None) == _lib.MSM_EINVAL
+    assert lib.msm_accumulate_stream(p, 0, 4, p, None) == _lib.MSM_EINVAL
+    assert lib.msm_accumulate_stream(p, 4, 0, p, None) == _lib.MSM_EINVAL
     # batches: validated on the host
     Job = _lib.MsmJob
     jobs = (Job * 2)(Job(16, 16, 16, 100, 8), Job(16, 16, 16, 0, 8))
