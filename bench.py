@@ -247,6 +247,15 @@ def microbench():
         rate = 16.0 * iters * threads / (ms * 1e-3)
         out[name] = {"ops_per_s": rate, "frac_of_peak": rate / PEAK_MAD_PER_S,
                      "lane_ops_per_cu_per_clk_at_2.4GHz": rate / (256 * 2.4e9)}
+    for name, kind, per in (("lone_wave_mad64_8_chains", api._lib.MSM_MB_MAD64_LONE, 16),
+                            ("lone_wave_mad64_dependent", api._lib.MSM_MB_MAD64_DEP, 16),
+                            ("lone_wave_fe_mul_dependent", api._lib.MSM_MB_FEMUL_DEP, 1)):
+        iters = 20000 if per == 16 else 2000
+        api.microbench(kind, 10, buf)
+        ms = timed(lambda: api.microbench(kind, iters, buf), 3, torch)
+        ops = per * iters
+        out[name] = {"ops": ops, "ms": ms, "ns_per_op": ms * 1e6 / ops,
+                     "cycles_per_op_at_2.4GHz": ms * 1e-3 * 2.4e9 / ops}
     nbytes = 1 << 31
     big = torch.empty(2 * nbytes // 4, dtype=torch.int32, device="cuda")
     api.microbench(api._lib.MSM_MB_COPY, nbytes, big)

@@ -290,10 +290,17 @@ int msm_profile_read(const char* phase, double* total_ms, int* launches);
  *   for both, buf is a device buffer of at least 2048 * 256 * 8 bytes.
  * kind MSM_MB_COPY: copies param bytes (a multiple of 16) from the first half
  *   of buf to the second; buf_bytes >= 2 * param, buf 16-byte aligned.
+ * Lone-wave kinds (one wave of 64 lanes; buf >= 512 bytes), for the latency
+ * of dependent chains: MSM_MB_MAD64_LONE issues 16 * param mads in 8
+ * independent chains, MSM_MB_MAD64_DEP 16 * param mads in one dependent
+ * chain, MSM_MB_FEMUL_DEP param dependent Montgomery products.
  * The caller times the launch on `stream`.  Errors: MSM_EINVAL, MSM_EHIP. */
 #define MSM_MB_MAD64 0
 #define MSM_MB_ADDC 1
 #define MSM_MB_COPY 2
+#define MSM_MB_MAD64_LONE 3
+#define MSM_MB_MAD64_DEP 4
+#define MSM_MB_FEMUL_DEP 5
 int msm_microbench(int kind, size_t param, void* buf, size_t buf_bytes, void* stream);
 
 /* HIP error code (hipError_t value) behind the last MSM_EHIP on this thread. */

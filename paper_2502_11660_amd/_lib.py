@@ -8,7 +8,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmsm_gfx950.so")
+# MSM_LIB_PATH selects another build of the same library (e.g. a variant
+# compiled with different kernel options); default: the in-tree build.
+LIB_PATH = os.environ.get("MSM_LIB_PATH") or os.path.join(HERE, "libmsm_gfx950.so")
 
 MSM_OK = 0
 MSM_EINVAL = -1
@@ -23,6 +25,9 @@ MSM_RESULT_WORDS = 32
 MSM_MB_MAD64 = 0
 MSM_MB_ADDC = 1
 MSM_MB_COPY = 2
+MSM_MB_MAD64_LONE = 3
+MSM_MB_MAD64_DEP = 4
+MSM_MB_FEMUL_DEP = 5
 MSM_DIGITS_SIGNED = 0
 MSM_DIGITS_UNSIGNED = 1
 MSM_UNIT_QUAD = 0

@@ -137,38 +137,366 @@ __device__ __forceinline__ void redc_step0(uint64_t& acc, uint32_t& m) {
   acc = ((uint64_t)nhi << 32) | nlo;
 }
 
-// Montgomery product r = a*b*R^{-1} mod p, lazily reduced.
-// Requires a*b < R*p (e.g. a, b < 12p); returns r < 2p.
+// Grouped multiply-adds: n products of one column in one asm block.  The
+// compiler separates consecutive asm blocks by a wait state, which a lone
+// wave (the latency-bound aggregation chains) pays in full, so a column's
+// products are issued a group of up to eight at a time.  MACN adds to the
+// deferred carry word hi; MACFN starts it from the first product's carry.
+// The first factor is a VGPR; CB is the second factor's constraint ("v" for
+// a VGPR, "s" for an SGPR such as a constant of p).
+#define MSM_MACN_1(CB, acc, hi, a0, b0) \
+  asm("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc" \
+      : "+v"(acc), "+v"(hi) \
+      : "v"(a0), CB(b0) \
+      : "vcc")
+
+#define MSM_MACN_2(CB, acc, hi, a0, b0, a1, b1) \
+  asm("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %4, %5, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc" \
+      : "+v"(acc), "+v"(hi) \
+      : "v"(a0), CB(b0), "v"(a1), CB(b1) \
+      : "vcc")
+
+#define MSM_MACN_3(CB, acc, hi, a0, b0, a1, b1, a2, b2) \
+  asm("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %4, %5, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %6, %7, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc" \
+      : "+v"(acc), "+v"(hi) \
+      : "v"(a0), CB(b0), "v"(a1), CB(b1), "v"(a2), CB(b2) \
+      : "vcc")
+
+#define MSM_MACN_4(CB, acc, hi, a0, b0, a1, b1, a2, b2, a3, b3) \
+  asm("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %4, %5, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %6, %7, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %8, %9, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc" \
+      : "+v"(acc), "+v"(hi) \
+      : "v"(a0), CB(b0), "v"(a1), CB(b1), "v"(a2), CB(b2), "v"(a3), CB(b3) \
+      : "vcc")
+
+#define MSM_MACN_5(CB, acc, hi, a0, b0, a1, b1, a2, b2, a3, b3, a4, b4) \
+  asm("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %4, %5, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %6, %7, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %8, %9, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %10, %11, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc" \
+      : "+v"(acc), "+v"(hi) \
+      : "v"(a0), CB(b0), "v"(a1), CB(b1), "v"(a2), CB(b2), "v"(a3), CB(b3), "v"(a4), CB(b4) \
+      : "vcc")
+
+#define MSM_MACN_6(CB, acc, hi, a0, b0, a1, b1, a2, b2, a3, b3, a4, b4, a5, b5) \
+  asm("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %4, %5, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %6, %7, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %8, %9, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %10, %11, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %12, %13, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc" \
+      : "+v"(acc), "+v"(hi) \
+      : "v"(a0), CB(b0), "v"(a1), CB(b1), "v"(a2), CB(b2), "v"(a3), CB(b3), "v"(a4), CB(b4), "v"(a5), CB(b5) \
+      : "vcc")
+
+#define MSM_MACN_7(CB, acc, hi, a0, b0, a1, b1, a2, b2, a3, b3, a4, b4, a5, b5, a6, b6) \
+  asm("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %4, %5, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %6, %7, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %8, %9, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %10, %11, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %12, %13, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %14, %15, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc" \
+      : "+v"(acc), "+v"(hi) \
+      : "v"(a0), CB(b0), "v"(a1), CB(b1), "v"(a2), CB(b2), "v"(a3), CB(b3), "v"(a4), CB(b4), "v"(a5), CB(b5), "v"(a6), CB(b6) \
+      : "vcc")
+
+#define MSM_MACN_8(CB, acc, hi, a0, b0, a1, b1, a2, b2, a3, b3, a4, b4, a5, b5, a6, b6, a7, b7) \
+  asm("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %4, %5, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %6, %7, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %8, %9, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %10, %11, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %12, %13, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %14, %15, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %16, %17, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc" \
+      : "+v"(acc), "+v"(hi) \
+      : "v"(a0), CB(b0), "v"(a1), CB(b1), "v"(a2), CB(b2), "v"(a3), CB(b3), "v"(a4), CB(b4), "v"(a5), CB(b5), "v"(a6), CB(b6), "v"(a7), CB(b7) \
+      : "vcc")
+
+#define MSM_MACFN_1(CB, acc, hi, a0, b0) \
+  asm("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\t" \
+      "v_cndmask_b32_e64 %1, 0, 1, vcc" \
+      : "+v"(acc), "=&v"(hi) \
+      : "v"(a0), CB(b0) \
+      : "vcc")
+
+#define MSM_MACFN_2(CB, acc, hi, a0, b0, a1, b1) \
+  asm("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\t" \
+      "v_cndmask_b32_e64 %1, 0, 1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %4, %5, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc" \
+      : "+v"(acc), "=&v"(hi) \
+      : "v"(a0), CB(b0), "v"(a1), CB(b1) \
+      : "vcc")
+
+#define MSM_MACFN_3(CB, acc, hi, a0, b0, a1, b1, a2, b2) \
+  asm("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\t" \
+      "v_cndmask_b32_e64 %1, 0, 1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %4, %5, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %6, %7, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc" \
+      : "+v"(acc), "=&v"(hi) \
+      : "v"(a0), CB(b0), "v"(a1), CB(b1), "v"(a2), CB(b2) \
+      : "vcc")
+
+#define MSM_MACFN_4(CB, acc, hi, a0, b0, a1, b1, a2, b2, a3, b3) \
+  asm("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\t" \
+      "v_cndmask_b32_e64 %1, 0, 1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %4, %5, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %6, %7, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %8, %9, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc" \
+      : "+v"(acc), "=&v"(hi) \
+      : "v"(a0), CB(b0), "v"(a1), CB(b1), "v"(a2), CB(b2), "v"(a3), CB(b3) \
+      : "vcc")
+
+#define MSM_MACFN_5(CB, acc, hi, a0, b0, a1, b1, a2, b2, a3, b3, a4, b4) \
+  asm("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\t" \
+      "v_cndmask_b32_e64 %1, 0, 1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %4, %5, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %6, %7, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %8, %9, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %10, %11, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc" \
+      : "+v"(acc), "=&v"(hi) \
+      : "v"(a0), CB(b0), "v"(a1), CB(b1), "v"(a2), CB(b2), "v"(a3), CB(b3), "v"(a4), CB(b4) \
+      : "vcc")
+
+#define MSM_MACFN_6(CB, acc, hi, a0, b0, a1, b1, a2, b2, a3, b3, a4, b4, a5, b5) \
+  asm("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\t" \
+      "v_cndmask_b32_e64 %1, 0, 1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %4, %5, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %6, %7, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %8, %9, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %10, %11, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %12, %13, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc" \
+      : "+v"(acc), "=&v"(hi) \
+      : "v"(a0), CB(b0), "v"(a1), CB(b1), "v"(a2), CB(b2), "v"(a3), CB(b3), "v"(a4), CB(b4), "v"(a5), CB(b5) \
+      : "vcc")
+
+#define MSM_MACFN_7(CB, acc, hi, a0, b0, a1, b1, a2, b2, a3, b3, a4, b4, a5, b5, a6, b6) \
+  asm("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\t" \
+      "v_cndmask_b32_e64 %1, 0, 1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %4, %5, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %6, %7, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %8, %9, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %10, %11, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %12, %13, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %14, %15, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc" \
+      : "+v"(acc), "=&v"(hi) \
+      : "v"(a0), CB(b0), "v"(a1), CB(b1), "v"(a2), CB(b2), "v"(a3), CB(b3), "v"(a4), CB(b4), "v"(a5), CB(b5), "v"(a6), CB(b6) \
+      : "vcc")
+
+#define MSM_MACFN_8(CB, acc, hi, a0, b0, a1, b1, a2, b2, a3, b3, a4, b4, a5, b5, a6, b6, a7, b7) \
+  asm("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\t" \
+      "v_cndmask_b32_e64 %1, 0, 1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %4, %5, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %6, %7, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %8, %9, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %10, %11, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %12, %13, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %14, %15, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc\n\t" \
+      "v_mad_u64_u32 %0, vcc, %16, %17, %0\n\t" \
+      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc" \
+      : "+v"(acc), "=&v"(hi) \
+      : "v"(a0), CB(b0), "v"(a1), CB(b1), "v"(a2), CB(b2), "v"(a3), CB(b3), "v"(a4), CB(b4), "v"(a5), CB(b5), "v"(a6), CB(b6), "v"(a7), CB(b7) \
+      : "vcc")
+
+template <int N, bool SGPR_Y>
+__device__ __forceinline__ void mac_group(uint64_t& acc, uint32_t& hi, const uint32_t* x,
+                                          const uint32_t* y, bool first) {
+#define MSM_G1 x[0], y[0]
+#define MSM_G2 MSM_G1, x[1], y[1]
+#define MSM_G3 MSM_G2, x[2], y[2]
+#define MSM_G4 MSM_G3, x[3], y[3]
+#define MSM_G5 MSM_G4, x[4], y[4]
+#define MSM_G6 MSM_G5, x[5], y[5]
+#define MSM_G7 MSM_G6, x[6], y[6]
+#define MSM_G8 MSM_G7, x[7], y[7]
+#define MSM_CALL(f, ...) f(__VA_ARGS__)
+#define MSM_GROUP(n)                                      \
+  if (first && SGPR_Y)                                    \
+    MSM_CALL(MSM_MACFN_##n, "s", acc, hi, MSM_G##n);      \
+  else if (first)                                         \
+    MSM_CALL(MSM_MACFN_##n, "v", acc, hi, MSM_G##n);      \
+  else if (SGPR_Y)                                        \
+    MSM_CALL(MSM_MACN_##n, "s", acc, hi, MSM_G##n);       \
+  else                                                    \
+    MSM_CALL(MSM_MACN_##n, "v", acc, hi, MSM_G##n);
+  if constexpr (N == 1) { MSM_GROUP(1) }
+  if constexpr (N == 2) { MSM_GROUP(2) }
+  if constexpr (N == 3) { MSM_GROUP(3) }
+  if constexpr (N == 4) { MSM_GROUP(4) }
+  if constexpr (N == 5) { MSM_GROUP(5) }
+  if constexpr (N == 6) { MSM_GROUP(6) }
+  if constexpr (N == 7) { MSM_GROUP(7) }
+  if constexpr (N == 8) { MSM_GROUP(8) }
+#undef MSM_GROUP
+#undef MSM_CALL
+#undef MSM_G8
+#undef MSM_G7
+#undef MSM_G6
+#undef MSM_G5
+#undef MSM_G4
+#undef MSM_G3
+#undef MSM_G2
+#undef MSM_G1
+}
+
+// (acc, hi) += sum of the L products x[t] y[t] (y in SGPRs when SGPR_Y);
+// first: hi starts from the first product's carry
+template <int L, bool SGPR_Y>
+__device__ __forceinline__ void mac_run(uint64_t& acc, uint32_t& hi, const uint32_t* x,
+                                        const uint32_t* y, bool first) {
+  if constexpr (L > 0) {
+    constexpr int G = L < 8 ? L : 8;
+    mac_group<G, SGPR_Y>(acc, hi, x, y, first);
+    if constexpr (L > G) mac_run<L - G, SGPR_Y>(acc, hi, x + G, y + G, false);
+  }
+}
+
+// column K < 12 of a*b + m*p: a_i b_{K-i} (i <= K), m_j p_{K-j} (j < K); then
+// the reduction digit m_K
+template <int K>
+__device__ __forceinline__ void mont_low_column(const fe& a, const fe& b, uint32_t* m,
+                                                uint64_t& acc) {
+  uint32_t x[K + 1], y[K + 1], mx[K], py[K];
+#pragma unroll
+  for (int i = 0; i <= K; ++i) {
+    x[i] = a.v[i];
+    y[i] = b.v[K - i];
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    mx[j] = m[j];
+    py[j] = kP[K - j];
+  }
+  uint32_t hi;
+  mac_run<K + 1, false>(acc, hi, x, y, true);
+  mac_run<K, true>(acc, hi, mx, py, false);
+  redc_step(acc, hi, m[K]);
+}
+
+// column K >= 12: a_i b_{K-i} and m_i p_{K-i} for i = K-11 .. 11; the low
+// word is result word K - 12
+template <int K>
+__device__ __forceinline__ uint32_t mont_high_column(const fe& a, const fe& b, const uint32_t* m,
+                                                     uint64_t& acc) {
+  constexpr int I0 = K - (NL - 1), L = NL - I0;
+  uint32_t x[L], y[L], mx[L], py[L];
+#pragma unroll
+  for (int i = I0; i < NL; ++i) {
+    x[i - I0] = a.v[i];
+    y[i - I0] = b.v[K - i];
+    mx[i - I0] = m[i];
+    py[i - I0] = kP[K - i];
+  }
+  uint32_t hi;
+  mac_run<L, false>(acc, hi, x, y, true);
+  mac_run<L, true>(acc, hi, mx, py, false);
+  const uint32_t w = (uint32_t)acc;
+  acc = ((uint64_t)hi << 32) | (acc >> 32);
+  return w;
+}
+
+// Montgomery product r = a*b*R^{-1} mod p, lazily reduced: product scanning
+// with the reduction interleaved per column (the m_j p terms join column k
+// once m_j is known).  Requires a*b < R*p (e.g. a, b < 12p); returns r < 2p.
 __device__ __forceinline__ fe fe_mul(const fe& a, const fe& b) {
   uint32_t m[NL];
   fe r;
   uint64_t acc;
-  uint32_t hi;
-  // column 0
   MSM_MUL0(acc, a.v[0], b.v[0]);
   redc_step0(acc, m[0]);
-  // columns 1..11: a*b terms, m*p terms, then the reduction digit
-#pragma unroll
-  for (int k = 1; k < NL; ++k) {
-    MSM_MACF(acc, hi, a.v[0], b.v[k]);
-#pragma unroll
-    for (int i = 1; i <= k; ++i) MSM_MAC(acc, hi, a.v[i], b.v[k - i]);
-#pragma unroll
-    for (int j = 0; j < k; ++j) MSM_MAC_S(acc, hi, m[j], kP[k - j]);
-    redc_step(acc, hi, m[k]);
-  }
-  // columns 12..22 produce the result words
-#pragma unroll
-  for (int k = NL; k < 2 * NL - 1; ++k) {
-    MSM_MACF(acc, hi, a.v[k - (NL - 1)], b.v[NL - 1]);
-#pragma unroll
-    for (int i = k - (NL - 1) + 1; i < NL; ++i) MSM_MAC(acc, hi, a.v[i], b.v[k - i]);
-#pragma unroll
-    for (int j = k - (NL - 1); j < NL; ++j) MSM_MAC_S(acc, hi, m[j], kP[k - j]);
-    r.v[k - NL] = (uint32_t)acc;
-    acc = ((uint64_t)hi << 32) | (acc >> 32);
-  }
-  r.v[NL - 1] = (uint32_t)acc;
+  mont_low_column<1>(a, b, m, acc);
+  mont_low_column<2>(a, b, m, acc);
+  mont_low_column<3>(a, b, m, acc);
+  mont_low_column<4>(a, b, m, acc);
+  mont_low_column<5>(a, b, m, acc);
+  mont_low_column<6>(a, b, m, acc);
+  mont_low_column<7>(a, b, m, acc);
+  mont_low_column<8>(a, b, m, acc);
+  mont_low_column<9>(a, b, m, acc);
+  mont_low_column<10>(a, b, m, acc);
+  mont_low_column<11>(a, b, m, acc);
+  r.v[0] = mont_high_column<12>(a, b, m, acc);
+  r.v[1] = mont_high_column<13>(a, b, m, acc);
+  r.v[2] = mont_high_column<14>(a, b, m, acc);
+  r.v[3] = mont_high_column<15>(a, b, m, acc);
+  r.v[4] = mont_high_column<16>(a, b, m, acc);
+  r.v[5] = mont_high_column<17>(a, b, m, acc);
+  r.v[6] = mont_high_column<18>(a, b, m, acc);
+  r.v[7] = mont_high_column<19>(a, b, m, acc);
+  r.v[8] = mont_high_column<20>(a, b, m, acc);
+  r.v[9] = mont_high_column<21>(a, b, m, acc);
+  r.v[10] = mont_high_column<22>(a, b, m, acc);
+  r.v[11] = (uint32_t)acc;
   return r;
 }
 

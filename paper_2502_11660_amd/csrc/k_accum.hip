@@ -56,8 +56,6 @@ __global__ void __launch_bounds__(256) k_accum(const uint32_t* __restrict__ pts,
   const bool open_left = (s > 0) && (key[s - 1] == cur);
   bool first_seg = true;
   xytz acc = pt_identity();
-  uint32_t ie = idx[s];
-  xyu P = ld_xyu(entry_point(pts, segoff, bb, cur, ie));
   for (uint32_t p = s; p < e; ++p) {
     const uint32_t k = key[p];
     if (k != cur) {
@@ -68,13 +66,9 @@ __global__ void __launch_bounds__(256) k_accum(const uint32_t* __restrict__ pts,
       cur = k;
       first_seg = false;
     }
-    // prefetch the next entry's point
-    const uint32_t pn = (p + 1 < e) ? p + 1 : p;
-    const uint32_t ien = idx[pn];
-    xyu Pn = ld_xyu(entry_point(pts, segoff, bb, key[pn], ien));
+    const uint32_t ie = idx[p];
+    const xyu P = ld_xyu(entry_point(pts, segoff, bb, k, ie));
     acc = padd_mixed_signed(acc, P, (ie >> 31) != 0u, p2);
-    P = Pn;
-    ie = ien;
   }
   const bool open_right = (e < E1) && (key[e] == cur);
   uint32_t* dst;

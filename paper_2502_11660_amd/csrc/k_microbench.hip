@@ -1,7 +1,8 @@
 // Microbenchmarks that give the rooflines their denominators: the VALU issue
 // rate of the 32x32->64 multiply-add the field core is built on (and of the
 // carry add that accompanies it), and a plain HBM copy used both as the
-// bandwidth reference and to calibrate memory-traffic counters.
+// bandwidth reference and to calibrate memory-traffic counters; and the
+// issue rate of a lone wave, which sets the latency of dependent chains.
 #include "common.hpp"
 
 namespace msm {
@@ -36,6 +37,30 @@ __global__ void __launch_bounds__(MB_THREADS) k_mb_addc(uint64_t* __restrict__ o
   out[blockIdx.x * blockDim.x + threadIdx.x] = c0 ^ c1 ^ c2 ^ c3 ^ c4 ^ c5 ^ c6 ^ c7;
 }
 
+// one dependent v_mad_u64_u32 chain per lane, 16 instructions per iteration
+__global__ void __launch_bounds__(64) k_mb_mad64_dep(uint64_t* __restrict__ out, uint32_t iters) {
+  uint32_t a = 0x9e3779b9u + threadIdx.x, b = 0x7f4a7c15u;
+  uint64_t c = 1;
+  for (uint32_t it = 0; it < iters; ++it) {
+#define MB_MAD(c) asm volatile("v_mad_u64_u32 %0, vcc, %1, %2, %0" : "+v"(c) : "v"(a), "v"(b) : "vcc");
+    MB_MAD(c) MB_MAD(c) MB_MAD(c) MB_MAD(c) MB_MAD(c) MB_MAD(c) MB_MAD(c) MB_MAD(c)
+    MB_MAD(c) MB_MAD(c) MB_MAD(c) MB_MAD(c) MB_MAD(c) MB_MAD(c) MB_MAD(c) MB_MAD(c)
+#undef MB_MAD
+  }
+  out[threadIdx.x] = c;
+}
+
+// a dependent chain of Montgomery products in one wave: x = x * y, iters times
+__global__ void __launch_bounds__(64) k_mb_femul_dep(uint64_t* __restrict__ out, uint32_t iters) {
+  fe x = fe_const(kR2), y = fe_const(kOne);
+  x.v[0] ^= threadIdx.x;
+  for (uint32_t it = 0; it < iters; ++it) x = fe_mul(x, y);
+  uint64_t h = 0;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) h = h * 31 + x.v[i];
+  out[threadIdx.x] = h;
+}
+
 __global__ void __launch_bounds__(256) k_mb_copy(const uint4* __restrict__ in, uint4* __restrict__ out,
                                                  size_t n) {
   size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -60,6 +85,18 @@ extern "C" int msm_microbench(int kind, size_t param, void* buf, size_t buf_byte
         k_mb_mad64<<<MB_BLOCKS, MB_THREADS, 0, st>>>((uint64_t*)buf, (uint32_t)param);
       else
         k_mb_addc<<<MB_BLOCKS, MB_THREADS, 0, st>>>((uint64_t*)buf, (uint32_t)param);
+      break;
+    }
+    case MSM_MB_MAD64_LONE:
+    case MSM_MB_MAD64_DEP:
+    case MSM_MB_FEMUL_DEP: {
+      if (buf_bytes < 64 * 8 || param == 0 || param >= (1u << 31)) return MSM_EINVAL;
+      if (kind == MSM_MB_MAD64_LONE)
+        k_mb_mad64<<<1, 64, 0, st>>>((uint64_t*)buf, (uint32_t)param);
+      else if (kind == MSM_MB_MAD64_DEP)
+        k_mb_mad64_dep<<<1, 64, 0, st>>>((uint64_t*)buf, (uint32_t)param);
+      else
+        k_mb_femul_dep<<<1, 64, 0, st>>>((uint64_t*)buf, (uint32_t)param);
       break;
     }
     case MSM_MB_COPY: {
