@@ -426,7 +426,7 @@ __device__ __forceinline__ void mac_run(uint64_t& acc, uint32_t& hi, const uint3
 template <int K>
 __device__ __forceinline__ void mont_low_column(const fe& a, const fe& b, uint32_t* m,
                                                 uint64_t& acc) {
-  uint32_t x[K + 1], y[K + 1], mx[K], py[K];
+  uint32_t x[2 * K + 1], y[2 * K + 1];
 #pragma unroll
   for (int i = 0; i <= K; ++i) {
     x[i] = a.v[i];
@@ -434,12 +434,11 @@ __device__ __forceinline__ void mont_low_column(const fe& a, const fe& b, uint32
   }
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    mx[j] = m[j];
-    py[j] = kP[K - j];
+    x[K + 1 + j] = m[j];
+    y[K + 1 + j] = kP[K - j];
   }
   uint32_t hi;
-  mac_run<K + 1, false>(acc, hi, x, y, true);
-  mac_run<K, true>(acc, hi, mx, py, false);
+  mac_run<2 * K + 1, false>(acc, hi, x, y, true);
   redc_step(acc, hi, m[K]);
 }
 
@@ -449,17 +448,16 @@ template <int K>
 __device__ __forceinline__ uint32_t mont_high_column(const fe& a, const fe& b, const uint32_t* m,
                                                      uint64_t& acc) {
   constexpr int I0 = K - (NL - 1), L = NL - I0;
-  uint32_t x[L], y[L], mx[L], py[L];
+  uint32_t x[2 * L], y[2 * L];
 #pragma unroll
   for (int i = I0; i < NL; ++i) {
     x[i - I0] = a.v[i];
     y[i - I0] = b.v[K - i];
-    mx[i - I0] = m[i];
-    py[i - I0] = kP[K - i];
+    x[L + i - I0] = m[i];
+    y[L + i - I0] = kP[K - i];
   }
   uint32_t hi;
-  mac_run<L, false>(acc, hi, x, y, true);
-  mac_run<L, true>(acc, hi, mx, py, false);
+  mac_run<2 * L, false>(acc, hi, x, y, true);
   const uint32_t w = (uint32_t)acc;
   acc = ((uint64_t)hi << 32) | (acc >> 32);
   return w;
@@ -509,54 +507,63 @@ __device__ __forceinline__ fe fe_sqr(const fe& a) { return fe_mul(a, a); }
 // unreduced add / subtract (12-word carry chains)
 // ---------------------------------------------------------------------------
 
-#define MSM_ADD0(r, cy, a, b) \
-  asm("v_add_co_u32_e64 %0, %1, %2, %3" : "=v"(r), "=s"(cy) : "v"(a), "v"(b))
-#define MSM_ADDC(r, cy, a, b, ci) \
-  asm("v_addc_co_u32_e64 %0, %1, %2, %3, %4" : "=v"(r), "=s"(cy) : "v"(a), "v"(b), "s"(ci))
-#define MSM_ADDC_LAST(r, a, b, ci) \
-  asm("v_addc_co_u32_e64 %0, %1, %2, %3, %4" : "=v"(r), "=s"(dummy) : "v"(a), "v"(b), "s"(ci))
 #define MSM_SUB0(r, cy, a, b) \
   asm("v_sub_co_u32_e64 %0, %1, %2, %3" : "=v"(r), "=s"(cy) : "v"(a), "v"(b))
 #define MSM_SUBB(r, cy, a, b, ci) \
   asm("v_subb_co_u32_e64 %0, %1, %2, %3, %4" : "=v"(r), "=s"(cy) : "v"(a), "v"(b), "s"(ci))
 
+// 12-word carry chains, each in a single asm block (the compiler separates
+// asm blocks by a wait state; one block per word cost a lone wave 11 of them
+// per chain).
+
 // r = a + b (no reduction; caller guarantees a + b < 2^384)
 __device__ __forceinline__ fe fe_add(const fe& a, const fe& b) {
   fe r;
-  uint64_t cy, cy2, dummy;
-  MSM_ADD0(r.v[0], cy, a.v[0], b.v[0]);
-#pragma unroll
-  for (int i = 1; i < NL - 1; ++i) {
-    MSM_ADDC(r.v[i], cy2, a.v[i], b.v[i], cy);
-    cy = cy2;
-  }
-  MSM_ADDC_LAST(r.v[NL - 1], a.v[NL - 1], b.v[NL - 1], cy);
-  (void)dummy;
+  asm("v_add_co_u32_e32 %0, vcc, %12, %24\n\t"
+      "v_addc_co_u32_e32 %1, vcc, %13, %25, vcc\n\t"
+      "v_addc_co_u32_e32 %2, vcc, %14, %26, vcc\n\t"
+      "v_addc_co_u32_e32 %3, vcc, %15, %27, vcc\n\t"
+      "v_addc_co_u32_e32 %4, vcc, %16, %28, vcc\n\t"
+      "v_addc_co_u32_e32 %5, vcc, %17, %29, vcc\n\t"
+      "v_addc_co_u32_e32 %6, vcc, %18, %30, vcc\n\t"
+      "v_addc_co_u32_e32 %7, vcc, %19, %31, vcc\n\t"
+      "v_addc_co_u32_e32 %8, vcc, %20, %32, vcc\n\t"
+      "v_addc_co_u32_e32 %9, vcc, %21, %33, vcc\n\t"
+      "v_addc_co_u32_e32 %10, vcc, %22, %34, vcc\n\t"
+      "v_addc_co_u32_e32 %11, vcc, %23, %35, vcc"
+      : "=&v"(r.v[0]), "=&v"(r.v[1]), "=&v"(r.v[2]), "=&v"(r.v[3]), "=&v"(r.v[4]), "=&v"(r.v[5]), "=&v"(r.v[6]), "=&v"(r.v[7]), "=&v"(r.v[8]), "=&v"(r.v[9]), "=&v"(r.v[10]), "=&v"(r.v[11])
+      : "v"(a.v[0]), "v"(a.v[1]), "v"(a.v[2]), "v"(a.v[3]), "v"(a.v[4]), "v"(a.v[5]), "v"(a.v[6]), "v"(a.v[7]), "v"(a.v[8]), "v"(a.v[9]), "v"(a.v[10]), "v"(a.v[11]),
+        "v"(b.v[0]), "v"(b.v[1]), "v"(b.v[2]), "v"(b.v[3]), "v"(b.v[4]), "v"(b.v[5]), "v"(b.v[6]), "v"(b.v[7]), "v"(b.v[8]), "v"(b.v[9]), "v"(b.v[10]), "v"(b.v[11])
+      : "vcc");
+  return r;
+}
+
+// r = c - b for b <= c (no borrow out)
+__device__ __forceinline__ fe fe_sub_nb(const fe& c, const fe& b) {
+  fe r;
+  asm("v_sub_co_u32_e32 %0, vcc, %12, %24\n\t"
+      "v_subb_co_u32_e32 %1, vcc, %13, %25, vcc\n\t"
+      "v_subb_co_u32_e32 %2, vcc, %14, %26, vcc\n\t"
+      "v_subb_co_u32_e32 %3, vcc, %15, %27, vcc\n\t"
+      "v_subb_co_u32_e32 %4, vcc, %16, %28, vcc\n\t"
+      "v_subb_co_u32_e32 %5, vcc, %17, %29, vcc\n\t"
+      "v_subb_co_u32_e32 %6, vcc, %18, %30, vcc\n\t"
+      "v_subb_co_u32_e32 %7, vcc, %19, %31, vcc\n\t"
+      "v_subb_co_u32_e32 %8, vcc, %20, %32, vcc\n\t"
+      "v_subb_co_u32_e32 %9, vcc, %21, %33, vcc\n\t"
+      "v_subb_co_u32_e32 %10, vcc, %22, %34, vcc\n\t"
+      "v_subb_co_u32_e32 %11, vcc, %23, %35, vcc"
+      : "=&v"(r.v[0]), "=&v"(r.v[1]), "=&v"(r.v[2]), "=&v"(r.v[3]), "=&v"(r.v[4]), "=&v"(r.v[5]), "=&v"(r.v[6]), "=&v"(r.v[7]), "=&v"(r.v[8]), "=&v"(r.v[9]), "=&v"(r.v[10]), "=&v"(r.v[11])
+      : "v"(c.v[0]), "v"(c.v[1]), "v"(c.v[2]), "v"(c.v[3]), "v"(c.v[4]), "v"(c.v[5]), "v"(c.v[6]), "v"(c.v[7]), "v"(c.v[8]), "v"(c.v[9]), "v"(c.v[10]), "v"(c.v[11]),
+        "v"(b.v[0]), "v"(b.v[1]), "v"(b.v[2]), "v"(b.v[3]), "v"(b.v[4]), "v"(b.v[5]), "v"(b.v[6]), "v"(b.v[7]), "v"(b.v[8]), "v"(b.v[9]), "v"(b.v[10]), "v"(b.v[11])
+      : "vcc");
   return r;
 }
 
 // r = a - b + c where c is a constant multiple of p held in VGPRs and b <= c
 // (so the result is non-negative); the caller guarantees a + c < 2^384.
 __device__ __forceinline__ fe fe_sub_plus(const fe& a, const fe& b, const fe& c) {
-  fe t, r;
-  uint64_t cy, cy2, dummy;
-  // t = c - b (no borrow out since b <= c)
-  MSM_SUB0(t.v[0], cy, c.v[0], b.v[0]);
-#pragma unroll
-  for (int i = 1; i < NL; ++i) {
-    MSM_SUBB(t.v[i], cy2, c.v[i], b.v[i], cy);
-    cy = cy2;
-  }
-  // r = a + t
-  MSM_ADD0(r.v[0], cy, a.v[0], t.v[0]);
-#pragma unroll
-  for (int i = 1; i < NL - 1; ++i) {
-    MSM_ADDC(r.v[i], cy2, a.v[i], t.v[i], cy);
-    cy = cy2;
-  }
-  MSM_ADDC_LAST(r.v[NL - 1], a.v[NL - 1], t.v[NL - 1], cy);
-  (void)dummy;
-  return r;
+  return fe_add(a, fe_sub_nb(c, b));
 }
 
 // r = a - b with the borrow returned as this wave's lane mask (bit set where

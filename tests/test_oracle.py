@@ -10,7 +10,7 @@ import random
 import numpy as np
 import pytest
 
-from oracle import curve, field, msm, points, te
+from oracle import curve, field, glv, msm, points, te
 from oracle.field import P, R_ORDER
 from paper_2502_11660_amd import inputs
 from tests.golden.fixtures import read_kv
@@ -307,6 +307,45 @@ def test_signed_pippenger_equals_definition(c):
         coeff = sum((1 if x > 0 else -1) * k for s, k in zip(sc, ks)
                     for x in [msm.signed_digits(s, c)[w]] if abs(x) == m + 1)
         assert B[w][m] == curve.smul(coeff % R_ORDER, curve.G)
+
+
+def test_endomorphism_constants():
+    # lambda^2 + lambda + 1 equals r as integers (BLS12 family identity)
+    assert glv.LAMBDA ** 2 + glv.LAMBDA + 1 == R_ORDER
+    assert glv.LAMBDA.bit_length() == 127
+    w = glv.OMEGA
+    assert w != 1 and pow(w, 3, P) == 1 and (w * w + w + 1) % P == 0
+
+
+def test_endomorphism_acts_as_lambda_on_g1():
+    for _ in range(3):
+        pt = random_g1_point()
+        ph = glv.phi(pt)
+        assert curve.on_curve(ph)
+        assert ph == curve.smul(glv.LAMBDA, pt)
+        # phi^3 = identity and P + phi(P) + phi^2(P) = O
+        assert glv.phi(glv.phi(ph)) == pt
+        assert curve.add(curve.add(pt, ph), glv.phi(ph)) is curve.INF
+    assert glv.phi(curve.INF) is curve.INF
+
+
+def test_scalar_split_recombines_and_is_short():
+    cases = [0, 1, glv.LAMBDA - 1, glv.LAMBDA, glv.LAMBDA + 1, R_ORDER - 1,
+             (1 << 253) - 1] + [RNG.randrange(1 << 253) for _ in range(200)]
+    for s in cases:
+        s0, s1 = glv.split(s)
+        assert s1 * glv.LAMBDA + s0 == s
+        assert 0 <= s0 < glv.LAMBDA and 0 <= s1 < (1 << glv.SPLIT_BITS)
+
+
+def test_split_msm_equals_naive():
+    n = 4
+    ks = [RNG.randrange(1, R_ORDER) for _ in range(n)]
+    pts = [points.fixed_base_mul(k) for k in ks]
+    sc = [RNG.randrange(R_ORDER) for _ in range(n - 1)] + [(1 << 253) - 1]
+    sc2, pts2 = glv.msm_split(sc, pts)
+    assert len(pts2) == 2 * n and max(sc2).bit_length() <= glv.SPLIT_BITS
+    assert msm.msm_naive(sc2, pts2) == msm.msm_naive(sc, pts) == msm.closed_form(sc, ks)
 
 
 # --------------------------------------------------------------------------
