@@ -74,6 +74,17 @@ extern "C" {
  *    Requires c >= 2. */
 #define MSM_DIGITS_SIGNED 0
 #define MSM_DIGITS_UNSIGNED 1
+/*  MSM_DIGITS_GLV: the endomorphism split (not in the paper; the same MSM
+ *    with half-length scalars).  phi(x, y) = (omega x, y) multiplies G1 by
+ *    lambda = x0^2 - 1, and lambda^2 + lambda + 1 = r, so each scalar splits
+ *    as s = s1 lambda + s0 with s0, s1 < 2^127 and s P = s0 P + s1 phi(P).
+ *    The prepared points must come from msm_points_prepare_endo (2n records:
+ *    the n points, then their images); the 2n half-scalars use signed digits
+ *    with W = ceil(128 / c) windows and 2^(c-1) buckets per window, bucket
+ *    entries indexed by record (point i: s0 of scalar i; record n + i: s1 of
+ *    scalar i).  Requires c >= 2; scalars are given as for the other
+ *    encodings. */
+#define MSM_DIGITS_GLV 2
 
 /* Batched point addition out_i = a_i + b_i (Sec. II-D; the paper's "task").
  * a_xytz: SoA, 4 coordinates x 12 words x count.  b: SoA, 4 coordinates
@@ -145,6 +156,14 @@ int msm_fe_mul_chain(const uint32_t* a, const uint32_t* b, uint32_t* out, size_t
  * are never exceptional.  Errors: MSM_EINVAL for null pointers or n = 0. */
 int msm_points_prepare(const uint32_t* xy_std, const uint32_t* inf, uint32_t* xyu, size_t n,
                        uint32_t* status, void* stream);
+
+/* As msm_points_prepare, and also the images phi(P_i) = (omega x_i, y_i)
+ * of the points under the curve's order-3 automorphism (for
+ * MSM_DIGITS_GLV): xyu receives 2n AoS records, record i = P_i and record
+ * n + i = phi(P_i).  Errors: MSM_EINVAL for null pointers, n = 0 or
+ * n >= 2^30. */
+int msm_points_prepare_endo(const uint32_t* xy_std, const uint32_t* inf, uint32_t* xyu, size_t n,
+                            uint32_t* status, void* stream);
 
 /* Synthetic-workload generator: P_i = k_i G for the conventional generator G
  * of BLS12-377 G1, written as Weierstrass affine points.  k: 8 words per

@@ -85,12 +85,13 @@ def num_signed_windows(c, bits=SCALAR_BITS):
     return -(-(bits + 1) // c)
 
 
-def signed_digits(s, c):
-    """Digits d_0..d_{W-1} with s = sum_w d_w 2^(w c), written from the
-    definition: walking up from the lowest window, v = slice + carry; when
-    v >= 2^(c-1) (and this is not the top window) the digit is v - 2^c and a
-    carry of one moves up, otherwise the digit is v and no carry moves."""
-    W = num_signed_windows(c)
+def signed_digits(s, c, bits=SCALAR_BITS):
+    """Digits d_0..d_{W-1} with s = sum_w d_w 2^(w c) for s < 2^bits, written
+    from the definition: walking up from the lowest window, v = slice +
+    carry; when v >= 2^(c-1) (and this is not the top window) the digit is
+    v - 2^c and a carry of one moves up, otherwise the digit is v and no
+    carry moves."""
+    W = num_signed_windows(c, bits)
     half, full = 1 << (c - 1), 1 << c
     out, carry = [], 0
     for w in range(W):
@@ -104,12 +105,12 @@ def signed_digits(s, c):
     return out
 
 
-def signed_buckets(scalars, points, c):
+def signed_buckets(scalars, points, c, bits=SCALAR_BITS):
     """B[w][m] = sum over i with |d_w(s_i)| = m + 1 of sign(d_w(s_i)) P_i."""
-    W = num_signed_windows(c)
+    W = num_signed_windows(c, bits)
     B = [[INF] * (1 << (c - 1)) for _ in range(W)]
     for s, pt in zip(scalars, points):
-        for w, d in enumerate(signed_digits(s, c)):
+        for w, d in enumerate(signed_digits(s, c, bits)):
             if d > 0:
                 B[w][d - 1] = add(B[w][d - 1], pt)
             elif d < 0:

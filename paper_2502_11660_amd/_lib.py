@@ -30,6 +30,7 @@ MSM_MB_MAD64_DEP = 4
 MSM_MB_FEMUL_DEP = 5
 MSM_DIGITS_SIGNED = 0
 MSM_DIGITS_UNSIGNED = 1
+MSM_DIGITS_GLV = 2
 MSM_UNIT_QUAD = 0
 MSM_UNIT_LANE = 1
 MSM_MUL_MONT = 0
@@ -50,6 +51,7 @@ SIGNATURES = {
     "msm_padd_batch": (_I, [_P, _P, _P, _SZ, _I, _P]),
     "msm_fe_mul_batch": (_I, [_P, _P, _P, _SZ, _I, _P]),
     "msm_points_prepare": (_I, [_P, _P, _P, _SZ, _P, _P]),
+    "msm_points_prepare_endo": (_I, [_P, _P, _P, _SZ, _P, _P]),
     "msm_gen_points": (_I, [_P, _SZ, _P, _P, _P]),
     "msm_num_windows": (_I, [_I, _I]),
     "msm_workspace_bytes": (_SZ, [_SZ, _I, _I]),

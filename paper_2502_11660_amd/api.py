@@ -12,7 +12,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (MSM_DIGITS_SIGNED, MSM_DIGITS_UNSIGNED, MSM_FLAG_EXCEPT,  # noqa: F401
+from ._lib import (MSM_DIGITS_GLV, MSM_DIGITS_SIGNED, MSM_DIGITS_UNSIGNED,  # noqa: F401
+                   MSM_FLAG_EXCEPT,
                    MSM_FLAG_OFFCURVE, MSM_FLAG_RANGE, MSM_FORM_XYTZ, MSM_FORM_XYU,
                    MSM_MUL_BARRETT, MSM_MUL_KARATSUBA, MSM_MUL_MONT, MSM_RESULT_WORDS,
                    MSM_UNIT_LANE, MSM_UNIT_QUAD, MSMError, MsmJob)
@@ -118,18 +119,20 @@ def fe_mul_chain(a, b, count, variant=MSM_MUL_MONT, rounds=1, out=None):
     return out
 
 
-def points_prepare(xy_std, n, inf=None, out=None, status=None):
-    """Weierstrass affine (SoA) -> prepared Edwards XYU records (AoS)."""
+def points_prepare(xy_std, n, inf=None, out=None, status=None, endo=False):
+    """Weierstrass affine (SoA) -> prepared Edwards XYU records (AoS); with
+    endo, 2n records: the points, then their endomorphism images."""
     _dev(xy_std, "xy_std")
     if xy_std.numel() != 2 * WORDS * n:
         raise ValueError("xy_std size does not match n")
     if inf is not None:
         _dev(inf, "inf")
     if out is None:
-        out = words(XYU_WORDS * n, xy_std.device)
+        out = words(XYU_WORDS * n * (2 if endo else 1), xy_std.device)
     if status is None:
         status = torch.zeros(1, dtype=torch.int32, device=xy_std.device)
-    _lib.check("msm_points_prepare", _lib.lib().msm_points_prepare(
+    fn = "msm_points_prepare_endo" if endo else "msm_points_prepare"
+    _lib.check(fn, getattr(_lib.lib(), fn)(
         _ptr(xy_std), _ptr(inf), _ptr(out), n, _ptr(status), _stream()))
     return out, status
 
@@ -153,7 +156,7 @@ def num_windows(c, encoding=MSM_DIGITS_SIGNED):
 
 
 def buckets_per_window(c, encoding=MSM_DIGITS_SIGNED):
-    return 1 << (c - 1 if encoding == MSM_DIGITS_SIGNED else c)
+    return 1 << (c if encoding == MSM_DIGITS_UNSIGNED else c - 1)
 
 
 def default_window(n):
@@ -174,7 +177,7 @@ def workspace(n, c, encoding=MSM_DIGITS_SIGNED, device="cuda"):
 def bucket_accumulate(xyu, scalars, n, c, encoding=MSM_DIGITS_SIGNED, buckets=None, ws=None):
     _dev(xyu, "xyu")
     _dev(scalars, "scalars")
-    if xyu.numel() != XYU_WORDS * n or scalars.numel() != SCALAR_WORDS * n:
+    if xyu.numel() != XYU_WORDS * _records(n, encoding) or scalars.numel() != SCALAR_WORDS * n:
         raise ValueError("input sizes do not match n")
     W = num_windows(c, encoding)
     if buckets is None:
@@ -187,10 +190,14 @@ def bucket_accumulate(xyu, scalars, n, c, encoding=MSM_DIGITS_SIGNED, buckets=No
     return buckets, ws
 
 
+def _records(n, encoding):
+    return 2 * n if encoding == MSM_DIGITS_GLV else n
+
+
 def msm_run(xyu, scalars, n, c=0, encoding=MSM_DIGITS_SIGNED, result=None, ws=None):
     _dev(xyu, "xyu")
     _dev(scalars, "scalars")
-    if xyu.numel() != XYU_WORDS * n or scalars.numel() != SCALAR_WORDS * n:
+    if xyu.numel() != XYU_WORDS * _records(n, encoding) or scalars.numel() != SCALAR_WORDS * n:
         raise ValueError("input sizes do not match n")
     if result is None:
         result = words(MSM_RESULT_WORDS, xyu.device)
@@ -202,12 +209,12 @@ def msm_run(xyu, scalars, n, c=0, encoding=MSM_DIGITS_SIGNED, result=None, ws=No
     return result
 
 
-def _job_array(jobs):
+def _job_array(jobs, encoding=MSM_DIGITS_SIGNED):
     arr = (MsmJob * len(jobs))()
     for a, (xyu, scalars, result, n, c) in zip(arr, jobs):
         for t, name in ((xyu, "xyu"), (scalars, "scalars"), (result, "result")):
             _dev(t, name)
-        if xyu.numel() < XYU_WORDS * n or scalars.numel() < SCALAR_WORDS * n:
+        if xyu.numel() < XYU_WORDS * _records(n, encoding) or scalars.numel() < SCALAR_WORDS * n:
             raise ValueError("job inputs smaller than n")
         if result.numel() < MSM_RESULT_WORDS:
             raise ValueError("job result buffer too small")
@@ -218,7 +225,7 @@ def _job_array(jobs):
 
 def batch_workspace_bytes(jobs, encoding=MSM_DIGITS_SIGNED):
     """jobs: list of (xyu, scalars, result, n, c) tuples (c = 0: default width)."""
-    arr = _job_array(jobs)
+    arr = _job_array(jobs, encoding)
     return _lib.lib().msm_batch_workspace_bytes(arr, len(jobs), encoding)
 
 
@@ -230,7 +237,7 @@ class Batch:
     """
 
     def __init__(self, jobs, encoding=MSM_DIGITS_SIGNED, use_graph=False):
-        arr = _job_array(jobs)
+        arr = _job_array(jobs, encoding)
         nbytes = _lib.lib().msm_batch_workspace_bytes(arr, len(jobs), encoding)
         if nbytes == 0:
             raise ValueError("invalid batch jobs")
@@ -304,11 +311,12 @@ class Server:
         _lib.check("msm_server_create", _lib.lib().msm_server_create(
             int(budget_bytes), int(streams), int(encoding), ctypes.byref(h)))
         self._h = h
+        self.encoding = encoding
         self._live = {}
         self._buf = (ctypes.c_uint64 * 1024)()
 
     def submit(self, xyu, scalars, result, n, c=0):
-        arr = _job_array([(xyu, scalars, result, n, c)])
+        arr = _job_array([(xyu, scalars, result, n, c)], self.encoding)
         t = ctypes.c_uint64(0)
         _lib.check("msm_server_submit", _lib.lib().msm_server_submit(
             self._h, arr, ctypes.byref(t)))

@@ -28,6 +28,11 @@ constexpr uint32_t kBetaOverAlpha[NL] = {0xead605e4u, 0xfb7c0ab8u, 0xe2752c7au, 
 constexpr uint32_t kR3[NL] = {0x8815de20u, 0x581f532fu, 0xbe329585u, 0xe50f4148u,
                               0x0449f513u, 0x2be8b118u, 0xc804a20eu, 0x6a2a9516u,
                               0x13590cb9u, 0x3f725407u, 0xc0e7dda5u, 0x01065ab4u};
+// omega (Montgomery form): the cube root of unity for which
+// (x, y) -> (omega x, y) is multiplication by lambda = x0^2 - 1 on G1
+constexpr uint32_t kOmega[NL] = {0xa5847973u, 0xdacd106du, 0xbac2a79au, 0xd8fe2454u,
+                                 0xfd832edcu, 0x1ada4fd6u, 0x9d150908u, 0xfb986844u,
+                                 0xea32285eu, 0xd63eb8aeu, 0x6f873fd0u, 0x0167d6a3u};
 // conventional generator G of BLS12-377 G1, Weierstrass affine (Montgomery form)
 constexpr uint32_t kGx[NL] = {0x772451f4u, 0x260f33b9u, 0x169d5658u, 0xc54dd773u,
                               0x69a510ddu, 0x5c1551c4u, 0x425e1698u, 0x761662e4u,
@@ -47,6 +52,7 @@ constexpr uint32_t kGteU[NL] = {0x4f3f8d58u, 0x719243efu, 0x4a7b9d48u, 0xf744d1f
                                 0xef3f9f1bu, 0x24125ab8u, 0xfb63f6d1u, 0x01959f77u};
 
 constexpr int SCALAR_BITS = 253;  // scalars are below 2^253
+constexpr int GLV_BITS = 127;     // halves of the endomorphism split are below 2^127
 constexpr int SCALAR_WORDS = 8;
 
 inline unsigned grid_for(size_t n, unsigned block) { return (unsigned)((n + block - 1) / block); }
@@ -168,7 +174,7 @@ int launch_fe_mul(const uint32_t* a, const uint32_t* b, uint32_t* out, uint32_t 
 int launch_padd(const uint32_t* a, const uint32_t* b, uint32_t* out, uint32_t count, int form,
                 hipStream_t st);
 int launch_prepare(const uint32_t* xy, const uint32_t* inf, uint32_t* xyu, uint32_t n,
-                   uint32_t* status, hipStream_t st);
+                   uint32_t* status, bool endo, hipStream_t st);
 int launch_gen_points(const uint32_t* k, uint32_t* xy, uint32_t* inf, uint32_t n, hipStream_t st);
 int launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
 

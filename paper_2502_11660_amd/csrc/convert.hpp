@@ -241,6 +241,78 @@ __device__ __forceinline__ scalar256 ld_scalar(const uint32_t* __restrict__ s, u
 }
 
 // c-bit digit starting at bit position pos (c <= 20, pos < 253)
+// Endomorphism split (optional, not in the paper): lambda = x0^2 - 1 with
+// lambda^2 + lambda + 1 = r; s = s1 lambda + s0 with 0 <= s0 < lambda and
+// s1 < 2^127 for every s < 2^253.  q = floor(s mu / 2^380) with
+// mu = floor(2^380 / lambda) is the quotient or one below it (the error
+// s (2^380 / lambda - mu) / 2^380 is below 2^-127), fixed by one compare.
+constexpr uint32_t kGlvLambda[4] = {0x00000000u, 0x0a118000u, 0x90000001u, 0x452217ccu};
+constexpr uint32_t kGlvMu[8] = {0xb7b820d2u, 0x55cc5a03u, 0x76f25c6bu, 0xc3366fc8u,
+                                0x2af90182u, 0x07f72ed3u, 0x69fd3716u, 0x3b3f7aa9u};
+
+__device__ __forceinline__ void glv_split(const scalar256& s, scalar256& s0, scalar256& s1) {
+  uint32_t prod[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) prod[k] = 0u;
+#pragma unroll
+  for (int i = 0; i < SCALAR_WORDS; ++i) {
+    uint64_t c = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      c = (uint64_t)s.w[i] * kGlvMu[j] + prod[i + j] + (c >> 32);
+      prod[i + j] = (uint32_t)c;
+    }
+    prod[i + 8] = (uint32_t)(c >> 32);
+  }
+  uint32_t q[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) q[k] = __builtin_amdgcn_alignbit(prod[12 + k], prod[11 + k], 28);
+  // r = s - q lambda (fits in 5 words: r < 2 lambda)
+  uint32_t ql[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) ql[k] = 0u;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    uint64_t c = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      c = (uint64_t)q[i] * kGlvLambda[j] + ql[i + j] + (c >> 32);
+      ql[i + j] = (uint32_t)c;
+    }
+    ql[i + 4] = (uint32_t)(c >> 32);
+  }
+  uint32_t r[SCALAR_WORDS];
+  uint32_t borrow = 0;
+#pragma unroll
+  for (int k = 0; k < SCALAR_WORDS; ++k) {
+    const uint64_t d = (uint64_t)s.w[k] - ql[k] - borrow;
+    r[k] = (uint32_t)d;
+    borrow = (uint32_t)(d >> 63);
+  }
+  // r >= lambda: subtract once more and bump the quotient
+  uint32_t t[SCALAR_WORDS];
+  borrow = 0;
+#pragma unroll
+  for (int k = 0; k < SCALAR_WORDS; ++k) {
+    const uint64_t d = (uint64_t)r[k] - (k < 4 ? kGlvLambda[k] : 0u) - borrow;
+    t[k] = (uint32_t)d;
+    borrow = (uint32_t)(d >> 63);
+  }
+  const bool ge = borrow == 0;
+  uint64_t inc = ge ? 1u : 0u;
+#pragma unroll
+  for (int k = 0; k < SCALAR_WORDS; ++k) {
+    s0.w[k] = ge ? t[k] : r[k];
+    if (k < 4) {
+      inc += q[k];
+      s1.w[k] = (uint32_t)inc;
+      inc >>= 32;
+    } else {
+      s1.w[k] = 0u;
+    }
+  }
+}
+
 __device__ __forceinline__ uint32_t digit_at(const scalar256& s, int pos, int c) {
   int wi = pos >> 5, sh = pos & 31;
   uint32_t lo = 0, hi = 0;

@@ -166,7 +166,7 @@ int launch_aggregate(const Plan& pl, const uint32_t* buckets, void* ws, hipStrea
     nodes >>= 1;
   }
   k_window_combine<<<grid_for(4 * (size_t)S, 64), 64, 0, st>>>(
-      in, bb, S, pl.encoding == MSM_DIGITS_SIGNED ? 1 : 0, wsum);
+      in, bb, S, pl.encoding == MSM_DIGITS_UNSIGNED ? 0 : 1, wsum);
   HIPCHK(hipGetLastError());
   return MSM_OK;
 }

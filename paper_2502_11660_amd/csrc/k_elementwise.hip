@@ -56,22 +56,10 @@ __global__ void __launch_bounds__(256) k_padd(const uint32_t* __restrict__ a,
 // Weierstrass affine (ordinary form) -> prepared (X, Y, U = k x y), Z = 1:
 //   w = x + 1,  x_e = (beta/alpha) w / y,  y_e = (w - alpha) / (w + alpha)
 // with one inversion of y (w + alpha) per point.
-__global__ void __launch_bounds__(256) k_prepare(const uint32_t* __restrict__ xy,
-                                                 const uint32_t* __restrict__ inf,
-                                                 uint32_t* __restrict__ out, uint32_t n,
-                                                 uint32_t* __restrict__ status) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  uint32_t* rec = out + (size_t)i * XYU_WORDS;
-  if (inf && inf[i]) {
-    st_aos(rec, 0, fe_zero());
-    st_aos(rec, 1, fe_const(kOne));
-    st_aos(rec, 2, fe_zero());
-    return;
-  }
+// prepared record (x_e, y_e, k x_e y_e) of the affine point (x, y), both in
+// Montgomery form; flags for off-curve / map-exceptional inputs
+__device__ __forceinline__ uint32_t prepare_one(const fe& x, const fe& y, uint32_t* rec) {
   const fe p2 = fe_const(kP2);
-  fe x = fe_to_mont(ld_soa(xy, n, 0, i));
-  fe y = fe_to_mont(ld_soa(xy, n, 1, i));
   uint32_t flags = 0;
   fe lhs = fe_canon(fe_sqr(y));
   fe rhs = fe_canon(fe_add(fe_mul(fe_sqr(x), x), fe_const(kOne)));
@@ -88,6 +76,34 @@ __global__ void __launch_bounds__(256) k_prepare(const uint32_t* __restrict__ xy
   st_aos(rec, 0, fe_canon(xe));
   st_aos(rec, 1, fe_canon(ye));
   st_aos(rec, 2, fe_canon(u));
+  return flags;
+}
+
+__device__ __forceinline__ void prepare_identity(uint32_t* rec) {
+  st_aos(rec, 0, fe_zero());
+  st_aos(rec, 1, fe_const(kOne));
+  st_aos(rec, 2, fe_zero());
+}
+
+// ENDO: also write the image (omega x, y) of every point at record n + i
+template <bool ENDO>
+__global__ void __launch_bounds__(256) k_prepare(const uint32_t* __restrict__ xy,
+                                                 const uint32_t* __restrict__ inf,
+                                                 uint32_t* __restrict__ out, uint32_t n,
+                                                 uint32_t* __restrict__ status) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t* rec = out + (size_t)i * XYU_WORDS;
+  uint32_t* rec2 = out + (size_t)(n + i) * XYU_WORDS;
+  if (inf && inf[i]) {
+    prepare_identity(rec);
+    if (ENDO) prepare_identity(rec2);
+    return;
+  }
+  const fe x = fe_to_mont(ld_soa(xy, n, 0, i));
+  const fe y = fe_to_mont(ld_soa(xy, n, 1, i));
+  uint32_t flags = prepare_one(x, y, rec);
+  if (ENDO) flags |= prepare_one(fe_mul(x, fe_const(kOmega)), y, rec2);
   if (flags) atomicOr(status, flags);
 }
 
@@ -147,8 +163,11 @@ int launch_padd(const uint32_t* a, const uint32_t* b, uint32_t* out, uint32_t co
 }
 
 int launch_prepare(const uint32_t* xy, const uint32_t* inf, uint32_t* xyu, uint32_t n,
-                   uint32_t* status, hipStream_t st) {
-  k_prepare<<<grid_for(n, 256), 256, 0, st>>>(xy, inf, xyu, n, status);
+                   uint32_t* status, bool endo, hipStream_t st) {
+  if (endo)
+    k_prepare<true><<<grid_for(n, 256), 256, 0, st>>>(xy, inf, xyu, n, status);
+  else
+    k_prepare<false><<<grid_for(n, 256), 256, 0, st>>>(xy, inf, xyu, n, status);
   HIPCHK(hipGetLastError());
   return MSM_OK;
 }

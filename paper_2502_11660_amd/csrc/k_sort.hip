@@ -80,7 +80,10 @@ __device__ __forceinline__ size_t count_index(const SortGeom& g, const JobDesc& 
 // Digits of every window of every job.  Word (segment s = j W + w, point i)
 // at W pt_off + w n + i holds q | sign << 31, where q = 0 drops the entry and
 // otherwise bucket m = q - 1 (signed digits, q = |d|) or m = q (unsigned
-// digits, q = d, so unsigned bucket 0 never receives points).
+// digits, q = d, so unsigned bucket 0 never receives points).  With the
+// endomorphism split a job's n points are its n / 2 input points followed by
+// their images: point i < n / 2 takes the digits of s0 of scalar i, point
+// n / 2 + i those of s1.
 __global__ void __launch_bounds__(256) k_slice(JobView jv, uint32_t N, int c, int W, int encoding,
                                                uint32_t* __restrict__ digits,
                                                uint32_t* __restrict__ flags) {
@@ -89,8 +92,17 @@ __global__ void __launch_bounds__(256) k_slice(JobView jv, uint32_t N, int c, in
   const uint32_t j = jv.tab ? find_job(jv.J, gi, [&](uint32_t k) { return jv.tab[k].pt_off; }) : 0u;
   const JobDesc d = jv.get(j);
   const uint32_t i = gi - d.pt_off;
-  const scalar256 s = ld_scalar(d.scalars, i, flags + j);
   uint32_t* out = digits + (size_t)W * d.pt_off + i;
+  scalar256 s;
+  if (encoding == MSM_DIGITS_GLV) {
+    const uint32_t half = d.n >> 1;
+    const bool image = i >= half;
+    scalar256 s0, s1;
+    glv_split(ld_scalar(d.scalars, image ? i - half : i, flags + j), s0, s1);
+    s = image ? s1 : s0;
+  } else {
+    s = ld_scalar(d.scalars, i, flags + j);
+  }
   if (encoding == MSM_DIGITS_UNSIGNED) {
     for (int w = 0; w < W; ++w) out[(size_t)w * d.n] = digit_at(s, w * c, c);
     return;
@@ -342,7 +354,7 @@ int launch_sort(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t st) {
   g.bb = (uint32_t)pl.bb;
   g.lo_bits = pl.lo_bits;
   g.hi_bits = pl.hi_bits;
-  const uint32_t off = pl.encoding == MSM_DIGITS_SIGNED ? 1u : 0u;
+  const uint32_t off = pl.encoding == MSM_DIGITS_UNSIGNED ? 0u : 1u;
 
   int rc;
   if ((rc = launch_fill_u32(flags, pl.J, 0u, st)) != MSM_OK) return rc;

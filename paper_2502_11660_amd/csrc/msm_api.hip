@@ -65,6 +65,7 @@ ProfScope::~ProfScope() {
 
 int num_windows(int c, int encoding) {
   if (encoding == MSM_DIGITS_SIGNED) return (c >= 2 && c <= 20) ? (SCALAR_BITS + c) / c : 0;
+  if (encoding == MSM_DIGITS_GLV) return (c >= 2 && c <= 20) ? (GLV_BITS + c) / c : 0;
   if (encoding == MSM_DIGITS_UNSIGNED) return (c >= 1 && c <= 20) ? (SCALAR_BITS + c - 1) / c : 0;
   return 0;
 }
@@ -92,14 +93,17 @@ bool make_plan(const size_t* ns, uint32_t J, int c, int encoding, Plan& pl) {
   pl.c = c;
   pl.W = W;
   pl.encoding = encoding;
-  pl.bb = encoding == MSM_DIGITS_SIGNED ? c - 1 : c;
+  pl.bb = encoding == MSM_DIGITS_UNSIGNED ? c : c - 1;
   pl.J = J;
+  // with the endomorphism split every input point contributes two points
+  const size_t mult = encoding == MSM_DIGITS_GLV ? 2 : 1;
   size_t tps_sum = 0;
   for (uint32_t j = 0; j < J; ++j) {
     if (ns[j] == 0 || ns[j] >= ((size_t)1 << 26)) return false;
-    pl.N += ns[j];
-    pl.max_n = std::max(pl.max_n, ns[j]);
-    tps_sum += (ns[j] + SORT_TILE - 1) / SORT_TILE;
+    const size_t nv = mult * ns[j];
+    pl.N += nv;
+    pl.max_n = std::max(pl.max_n, nv);
+    tps_sum += (nv + SORT_TILE - 1) / SORT_TILE;
   }
   pl.S = (size_t)J * W;
   pl.M = pl.S << pl.bb;
@@ -112,8 +116,8 @@ bool make_plan(const size_t* ns, uint32_t J, int c, int encoding, Plan& pl) {
   sort_geometry(pl);
   if (pl.lo_bits > 8 || pl.nb > 4096) return false;
   if (J == 1) {
-    pl.one.n = (uint32_t)ns[0];
-    pl.one.tps = (uint32_t)((ns[0] + SORT_TILE - 1) / SORT_TILE);
+    pl.one.n = (uint32_t)(mult * ns[0]);
+    pl.one.tps = (uint32_t)((mult * ns[0] + SORT_TILE - 1) / SORT_TILE);
   }
   // accumulation chunk: the launch keeps about 2 waves per SIMD busy
   // (256 CUs x 4 SIMDs x 2 waves x 64 lanes = 131072 lanes), K in [16, 64]
@@ -210,7 +214,13 @@ int msm_padd_batch(const uint32_t* a_xytz, const uint32_t* b, uint32_t* out_xytz
 int msm_points_prepare(const uint32_t* xy_std, const uint32_t* inf, uint32_t* xyu, size_t n,
                        uint32_t* status, void* stream) {
   if (!xy_std || !xyu || !status || n == 0 || n >= (1u << 31)) return MSM_EINVAL;
-  return launch_prepare(xy_std, inf, xyu, (uint32_t)n, status, (hipStream_t)stream);
+  return launch_prepare(xy_std, inf, xyu, (uint32_t)n, status, false, (hipStream_t)stream);
+}
+
+int msm_points_prepare_endo(const uint32_t* xy_std, const uint32_t* inf, uint32_t* xyu, size_t n,
+                            uint32_t* status, void* stream) {
+  if (!xy_std || !xyu || !status || n == 0 || n >= (1u << 30)) return MSM_EINVAL;
+  return launch_prepare(xy_std, inf, xyu, (uint32_t)n, status, true, (hipStream_t)stream);
 }
 
 int msm_gen_points(const uint32_t* k, size_t n, uint32_t* xy_std, uint32_t* inf, void* stream) {

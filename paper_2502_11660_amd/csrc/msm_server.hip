@@ -184,7 +184,9 @@ int msm_server_create(size_t hbm_budget_bytes, int streams, int encoding, msm_se
   if (!out) return MSM_EINVAL;
   *out = nullptr;
   if (hbm_budget_bytes < 4096 || streams < 1 || streams > 16) return MSM_EINVAL;
-  if (encoding != MSM_DIGITS_SIGNED && encoding != MSM_DIGITS_UNSIGNED) return MSM_EINVAL;
+  if (encoding != MSM_DIGITS_SIGNED && encoding != MSM_DIGITS_UNSIGNED &&
+      encoding != MSM_DIGITS_GLV)
+    return MSM_EINVAL;
   msm_server* s = new msm_server();
   const int rc = create(hbm_budget_bytes, streams, encoding, s);
   if (rc != MSM_OK) {
