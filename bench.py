@@ -30,7 +30,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 N_POINTS = 1 << 20
-C_SWEEP = list(range(13, 18))
+# (encoding, window width) candidates of the n = 2^20 sweep
+SWEEP = [("signed", c) for c in (15, 16, 17)] + [("glv", c) for c in (13, 15, 16, 19)]
+ENCODINGS = {"signed": 0, "unsigned": 1, "glv": 2}
 MAD_PER_MUL = 276          # 144 a*b + 132 m*p word products per Montgomery multiply
 MULS_MIXED = 7             # mixed PADD (Z2 = 1, U2 = k T2)
 MULS_COMPLETE = 9          # complete PADD with k T2 formed on the fly
@@ -44,12 +46,18 @@ def padd_count_formula(n, c):
     return n * W + 2 * ((1 << c) - 1) * W + W * c + W - 1
 
 
-def padd_count_executed(entries, c, signed=True, jobs=1):
+def num_windows(c, encoding):
+    bits = {"signed": 254, "unsigned": 253, "glv": 128}[encoding]
+    return -(-bits // c)
+
+
+def padd_count_executed(entries, c, encoding="signed", jobs=1):
     """Additions and doublings the implementation executes for one MSM:
     accumulation (one mixed addition per non-zero digit), the aggregation
     tree (2^(bb+1) - bb - 2 per window), the window Horner steps and the
     group Horner steps (c doublings and one addition per window but the top)."""
-    W = -(-(254 if signed else 253) // c)
+    signed = encoding != "unsigned"
+    W = num_windows(c, encoding)
     bb = c - 1 if signed else c
     S = W * jobs
     tree = S * ((1 << (bb + 1)) - bb - 2)
@@ -120,11 +128,26 @@ def timed(fn, reps, torch):
     return s.elapsed_time(e) / reps
 
 
-def nonzero_digit_entries(sw_np, c, signed=True):
+def glv_halves(sw_np):
+    """Scalar words -> words of the endomorphism halves (s0, s1) per scalar."""
+    import numpy as np
+    from paper_2502_11660_amd import inputs
+    lam = 0x8508C00000000001 ** 2 - 1
+    ints = [inputs.words_to_int(r) for r in sw_np.reshape(-1, 8)]
+    halves = []
+    for v in ints:
+        halves += [v % lam, v // lam]
+    return np.asarray(inputs.ints_to_words(halves, 8), dtype=np.uint32)
+
+
+def nonzero_digit_entries(sw_np, c, encoding="signed"):
     """Number of (point, window) pairs with a non-zero digit: the mixed PADDs
     bucket accumulation performs."""
     import numpy as np
-    W = -(-(254 if signed else 253) // c)
+    signed = encoding != "unsigned"
+    W = num_windows(c, encoding)
+    if encoding == "glv":
+        sw_np = glv_halves(sw_np)
     words = sw_np.reshape(-1, 8).astype(np.uint64)
     carry = np.zeros(words.shape[0], dtype=np.uint64)
     total = 0
@@ -271,7 +294,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--c", type=int, default=0, help="window width (0: sweep 10..16, take the best)")
+    ap.add_argument("--c", type=int, default=0,
+                    help="window width (0: sweep the encodings and widths, take the best)")
+    ap.add_argument("--encoding", default="glv", choices=sorted(ENCODINGS),
+                    help="digit encoding used with --c")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-padd-kernel", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
@@ -323,23 +349,33 @@ def main():
 
     prep()
     prepare_ms = timed(prep, 3, torch)
+    xyu_endo = None
 
-    # window sweep
+    def prep_endo():
+        nonlocal xyu_endo
+        xyu_endo, _ = api.points_prepare(xy, n, inf=inf, out=xyu_endo, endo=True)
+
+    prep_endo()
+    prepare_endo_ms = timed(prep_endo, 3, torch)
+    pts_for = {"signed": xyu, "unsigned": xyu, "glv": xyu_endo}
+
+    # (encoding, window) sweep
     sweep = {}
-    cs = [args.c] if args.c else C_SWEEP
-    for c in cs:
-        ws = api.workspace(n, c, device=dev)
+    cands = [(args.encoding, args.c)] if args.c else SWEEP
+    for enc, c in cands:
+        ws = api.workspace(n, c, ENCODINGS[enc], device=dev)
         res = api.words(api.MSM_RESULT_WORDS, dev)
-        fn = lambda: api.msm_run(xyu, s_dev, n, c, result=res, ws=ws)
+        fn = lambda: api.msm_run(pts_for[enc], s_dev, n, c, ENCODINGS[enc], result=res, ws=ws)
         fn()
-        sweep[c] = timed(fn, 2, torch)
+        sweep[(enc, c)] = timed(fn, 2, torch)
         del ws
-        print("[bench] c=%d: %.3f ms" % (c, sweep[c]), file=sys.stderr, flush=True)
-    best_c = min(sweep, key=sweep.get)
+        print("[bench] %s c=%d: %.3f ms" % (enc, c, sweep[(enc, c)]), file=sys.stderr, flush=True)
+    best_enc, best_c = min(sweep, key=sweep.get)
 
-    ws = api.workspace(n, best_c, device=dev)
+    ws = api.workspace(n, best_c, ENCODINGS[best_enc], device=dev)
     res = api.words(api.MSM_RESULT_WORDS, dev)
-    step = lambda: api.msm_run(xyu, s_dev, n, best_c, result=res, ws=ws)
+    step = lambda: api.msm_run(pts_for[best_enc], s_dev, n, best_c, ENCODINGS[best_enc],
+                               result=res, ws=ws)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -360,9 +396,14 @@ def main():
         tot, cnt = api.profile_read(ph)
         phases[ph] = tot / max(cnt, 1)
     accum_tot_ms = phases["accum"]
+    # the result of the timed runs, against the closed form
+    from oracle import msm as msm_oracle
+    ok_result = api.decode_result(api.to_host(res)) == (
+        msm_oracle.closed_form([inputs.words_to_int(r) for r in sw],
+                               [inputs.words_to_int(r) for r in kw]), 0)
 
-    entries = nonzero_digit_entries(sw, best_c)
-    padds = padd_count_executed(entries, best_c)
+    entries = nonzero_digit_entries(sw, best_c, best_enc)
+    padds = padd_count_executed(entries, best_c, best_enc)
     value = padds / (ms_per_step * 1e-3)
     accum_mads = entries * MULS_MIXED * MAD_PER_MUL
     achieved = accum_mads / (accum_tot_ms * 1e-3)
@@ -383,10 +424,10 @@ def main():
     ks_pool = [inputs.words_to_int(r) for r in kw[:N_CHECK_POOL]]
     batched = None
     if not args.no_batch:
-        batched = batched_bench(torch, api, inputs, xyu, ks_pool, args)
+        batched = batched_bench(torch, api, inputs, pts_for, ks_pool, args)
     served = None
     if not args.no_serve:
-        served = served_bench(torch, api, inputs, xyu, ks_pool, args)
+        served = served_bench(torch, api, inputs, pts_for, ks_pool, args)
 
     out = {
         "metric": "PADDs/s and MSM latency (ms) at n=2^20; batched/served MSMs/s + p99 vs plain",
@@ -402,13 +443,15 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": "BLS12-377 G1 MSM, n=2^20 points k_i*G, uniform scalars mod r",
-                   "n": n, "c": best_c, "digits": "signed",
-                   "windows": -(-254 // best_c), "seed": seed,
+                   "n": n, "c": best_c, "digits": best_enc,
+                   "windows": num_windows(best_c, best_enc), "seed": seed,
                    "padds_per_msm": padds,
                    "padds_per_msm_unsigned_formula": padd_count_formula(n, best_c)},
         "msm_ms": ms_per_step,
+        "result_matches_closed_form": bool(ok_result),
         "prepare_ms": prepare_ms,
-        "c_sweep_ms": {str(k): v for k, v in sweep.items()},
+        "prepare_endo_ms": prepare_endo_ms,
+        "sweep_ms": {"%s_c%d" % k: v for k, v in sweep.items()},
         "phase_ms": phases,
         "roofline": {
             "kernel": "k_accum (bucket accumulation, mixed PADD)",
@@ -442,9 +485,11 @@ def _closed_form_ok(msm_oracle, api, inputs, res_words, sc_words, ks):
     return api.decode_result(res_words) == (msm_oracle.closed_form(ss, ks), 0)
 
 
-def batched_bench(torch, api, inputs, xyu_pool, ks_pool, args):
+def batched_bench(torch, api, inputs, pools, ks_pool, args):
     """64 MSMs, n_j = floor(2^u), u ~ U[10, 18]: one graph-replayed batch with
-    autotuned widths, against 64 sequential msm_run calls."""
+    autotuned widths (signed digits and the endomorphism split), against 64
+    sequential msm_run calls with the static width."""
+    xyu_pool = pools["signed"]
     import numpy as np
     from oracle import msm as msm_oracle
     from paper_2502_11660_amd import autotune
@@ -458,72 +503,83 @@ def batched_bench(torch, api, inputs, xyu_pool, ks_pool, args):
     rng = np.random.Generator(np.random.PCG64([seed, 3]))
     offs = [int(rng.integers(0, N_CHECK_POOL - n + 1)) if n <= N_CHECK_POOL // 2
             else int(rng.integers(0, npool - n + 1)) for n in sizes]
-    tuner = autotune.Autotuner(context="batch")
+    bu = sorted({autotune.n_bucket(n) for n in sizes})
+    tuners = {}
     t0 = time.perf_counter()
-    for u in sorted({autotune.n_bucket(n) for n in sizes}):
-        tuner.tune(u, xyu_pool, s_dev)
+    for enc in ("signed", "glv"):
+        tuners[enc] = autotune.Autotuner(encoding=ENCODINGS[enc], context="batch")
+        for u in bu:
+            tuners[enc].tune(u, pools[enc], s_dev)
     tune_s = time.perf_counter() - t0
-    print("[bench] autotuned %d size classes in %.1f s" % (len(tuner.table), tune_s),
+    print("[bench] autotuned %d size classes x 2 encodings in %.1f s" % (len(bu), tune_s),
           file=sys.stderr, flush=True)
-    tuned = {"u%d" % u: tuner.choose(1 << u) for u in sorted({autotune.n_bucket(n) for n in sizes})}
 
-    def jobs_with(cfun, results):
+    def jobs_with(enc, cfun, results):
+        rec = 2 if enc == "glv" else 1
         jobs, so = [], 0
         for j, n in enumerate(sizes):
             o = offs[j]
-            jobs.append((xyu_pool[o * 36:(o + n) * 36], s_dev[so * 8:(so + n) * 8], results[j], n,
-                         cfun(n)))
+            jobs.append((pools[enc][rec * o * 36:rec * (o + n) * 36], s_dev[so * 8:(so + n) * 8],
+                         results[j], n, cfun(n)))
             so += n
         return jobs
 
     reps = 5
     out = {"jobs": 64, "points": ntot, "sizes_log2_range": [10, 18], "seed": seed,
-           "autotune_s": tune_s, "tuned_c": tuned}
-    res_b = [api.words(api.MSM_RESULT_WORDS) for _ in sizes]
-    for name, graph in (("batched_graph", True), ("batched_nograph", False)):
-        b = api.Batch(jobs_with(tuner.choose, res_b), use_graph=graph)
-        b.run()
-        ms = timed(b.run, reps, torch)
-        out[name] = {"ms": ms, "msms_per_s": 64 / (ms * 1e-3), "classes": len(
-            {tuner.choose(n) for n in sizes})}
-        b.destroy()
-    maxws = max(api.workspace_bytes(n, c) for n in sizes for c in
-                (api.default_window(n), tuner.choose(n)))
+           "autotune_s": tune_s,
+           "tuned_c": {enc: {"u%d" % u: t.choose(1 << u) for u in bu} for enc, t in tuners.items()}}
+    res_b = {enc: [api.words(api.MSM_RESULT_WORDS) for _ in sizes] for enc in tuners}
+    for enc, t in tuners.items():
+        for graph in (True, False):
+            b = api.Batch(jobs_with(enc, t.choose, res_b[enc]), ENCODINGS[enc], use_graph=graph)
+            b.run()
+            ms = timed(b.run, reps, torch)
+            out["batched_%s_%s" % (enc, "graph" if graph else "nograph")] = {
+                "ms": ms, "msms_per_s": 64 / (ms * 1e-3),
+                "classes": len({t.choose(n) for n in sizes})}
+            b.destroy()
+    best = min((k for k in out if k.startswith("batched_")), key=lambda k: out[k]["ms"])
+    out["batched_best"] = best
+    maxws = max(api.workspace_bytes(n, api.default_window(n)) for n in sizes)
     ws = torch.empty((maxws + 3) // 4, dtype=torch.int32, device=xyu_pool.device)
     res_p = [api.words(api.MSM_RESULT_WORDS) for _ in sizes]
-    for name, cfun in (("plain_static_c", api.default_window), ("plain_tuned_c", tuner.choose)):
-        jobs = jobs_with(cfun, res_p)
+    jobs = jobs_with("signed", api.default_window, res_p)
 
-        def seq():
-            for (x, sc, r, n, c) in jobs:
-                api.msm_run(x, sc, n, c, result=r, ws=ws)
-        seq()
-        ms = timed(seq, reps, torch)
-        out[name] = {"ms": ms, "msms_per_s": 64 / (ms * 1e-3)}
+    def seq():
+        for (x, sc, r, n, c) in jobs:
+            api.msm_run(x, sc, n, c, result=r, ws=ws)
+    seq()
+    ms = timed(seq, reps, torch)
+    out["plain_static_c"] = {"ms": ms, "msms_per_s": 64 / (ms * 1e-3),
+                             "what": "64 sequential msm_run, signed digits, msm_default_window"}
     torch.cuda.synchronize()
-    same = all(np.array_equal(api.to_host(a), api.to_host(b)) for a, b in zip(res_b, res_p))
+    same = all(np.array_equal(api.to_host(a), api.to_host(b))
+               for enc in res_b for a, b in zip(res_b[enc], res_p))
     checked = 0
     so = 0
     ok = True
     for j, n in enumerate(sizes):
         if offs[j] + n <= len(ks_pool) and checked < 8:
-            ok &= _closed_form_ok(msm_oracle, api, inputs, api.to_host(res_b[j]),
+            ok &= _closed_form_ok(msm_oracle, api, inputs, api.to_host(res_p[j]),
                                   sw[so:so + n], ks_pool[offs[j]:offs[j] + n])
             checked += 1
         so += n
     out["results_equal_plain_vs_batched"] = bool(same)
     out["closed_form_checked_jobs"] = checked
     out["closed_form_ok"] = bool(ok)
-    out["speedup_vs_plain_static"] = out["plain_static_c"]["ms"] / out["batched_graph"]["ms"]
-    print("[bench] batched %.2f ms vs plain %.2f ms" % (out["batched_graph"]["ms"],
-                                                      out["plain_static_c"]["ms"]),
+    out["speedup_vs_plain_static"] = out["plain_static_c"]["ms"] / out[best]["ms"]
+    print("[bench] batched (%s) %.2f ms vs plain %.2f ms" % (best, out[best]["ms"],
+                                                           out["plain_static_c"]["ms"]),
           file=sys.stderr, flush=True)
     return out
 
 
-def served_bench(torch, api, inputs, xyu_pool, ks_pool, args):
+def served_bench(torch, api, inputs, pools, ks_pool, args):
     """Poisson arrivals at 200/s, n = floor(2^u), u ~ U[12, 20], replayed
-    through the MSM server and through the plain path one at a time."""
+    through the MSM server (endomorphism split, solo-tuned widths) and
+    through the plain path one at a time (msm_run, signed digits, static
+    width)."""
+    xyu_pool = pools["signed"]
     import numpy as np
     from oracle import msm as msm_oracle
     from paper_2502_11660_amd import autotune, serve
@@ -540,15 +596,17 @@ def served_bench(torch, api, inputs, xyu_pool, ks_pool, args):
     rng = np.random.Generator(np.random.PCG64([seed, 3]))
     poffs = [int(rng.integers(0, npool - n + 1)) for n in sizes]
     soffs = [int(rng.integers(0, spool_n - n + 1)) for n in sizes]
-    tuner = autotune.Autotuner(context="solo")
+    tuner = autotune.Autotuner(encoding=ENCODINGS["glv"], context="solo")
     for u in range(12, 21):
         if not tuner.tuned(u):
-            tuner.tune(u, xyu_pool, s_dev)
+            tuner.tune(u, pools["glv"], s_dev)
     out_tuned = {"u%d" % u: tuner.choose(1 << u) for u in range(12, 21)}
     results = torch.zeros(nreq, api.MSM_RESULT_WORDS, dtype=torch.int32, device=xyu_pool.device)
 
-    def jobs_for(cfun):
-        return [(xyu_pool[po * 36:(po + n) * 36], s_dev[so * 8:(so + n) * 8], results[i], n, cfun(n))
+    def jobs_for(enc, cfun):
+        rec = 2 if enc == "glv" else 1
+        return [(pools[enc][rec * po * 36:rec * (po + n) * 36], s_dev[so * 8:(so + n) * 8],
+                 results[i], n, cfun(n))
                 for i, (n, po, so) in enumerate(zip(sizes, poffs, soffs))]
 
     measured = np.asarray(arrivals) >= warm
@@ -561,10 +619,11 @@ def served_bench(torch, api, inputs, xyu_pool, ks_pool, args):
         budgets.append(("2GB", 2 << 30))
     served_words = None
     for name, budget in budgets:
-        srv = api.Server(budget, streams=4)
+        srv = api.Server(budget, streams=4, encoding=ENCODINGS["glv"])
         print("[bench] serving %d requests, budget %.1f GB ..." % (nreq, budget / 1e9),
               file=sys.stderr, flush=True)
-        lat, wall = serve.replay_served(srv, arrivals, jobs_for(tuner.choose), progress_every=5.0)
+        lat, wall = serve.replay_served(srv, arrivals, jobs_for("glv", tuner.choose),
+                                        progress_every=5.0)
         srv.destroy()
         out[name] = serve.summarize(lat, wall, measured)
         out[name]["budget_bytes"] = budget
@@ -575,7 +634,7 @@ def served_bench(torch, api, inputs, xyu_pool, ks_pool, args):
     maxws = max(api.workspace_bytes(n, 0) for n in set(sizes))
     ws = torch.empty((maxws + 3) // 4, dtype=torch.int32, device=xyu_pool.device)
     print("[bench] plain replay ...", file=sys.stderr, flush=True)
-    lat_p, wall_p = serve.replay_plain(arrivals, jobs_for(lambda n: 0),
+    lat_p, wall_p = serve.replay_plain(arrivals, jobs_for("signed", lambda n: 0),
                                        workspaces=lambda n, c: ws, progress_every=5.0)
     out["plain_fifo"] = serve.summarize(lat_p, wall_p, measured)
     plain_words = results.cpu().numpy()
@@ -602,350 +661,6 @@ def accum_traffic():
     except (OSError, ValueError):
         return None
     if rec.get("sources_sha256") != profsum.sources_sha256(rec.get("sources", [])):
-        return None
-    return rec.get("bytes_per_launch")
-
-
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--c", type=int, default=0, help="window width (0: sweep 10..16, take the best)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-padd-kernel", action="store_true")
-    ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
-    ap.add_argument("--no-serve", action="store_true", help="skip the served workload")
-    ap.add_argument("--serve-seconds", type=float, default=6.0,
-                    help="measured seconds of the served trace (after 1 s of warm-up)")
-    ap.add_argument("--serve-full", action="store_true",
-                    help="served trace of 5 s warm-up + 30 s, plus a run with a 2 GB budget")
-    ap.add_argument("--microbench", action="store_true",
-                    help="only measure the VALU mad / carry-add issue rates and HBM copy bandwidth")
-    args = ap.parse_args()
-
-    if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X and has no "
-              "multi-GPU path (requested --gpus %d)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
-
-    if args.microbench:
-        print(json.dumps(microbench()))
-        return
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(16)
-
-    import numpy as np
-    import torch
-
-    from paper_2502_11660_amd import api, inputs
-
-    torch.cuda.set_device(0)
-    dev = torch.device("cuda", 0)
-    n = N_POINTS
-    seed = inputs.config_seed(3)
-    kw = inputs.nonzero_scalars_mod_r(seed, n, stream=1)
-    sw = inputs.scalars_mod_r(seed, n, stream=2)
-    k_dev = api.to_device(kw, dev)
-    s_dev = api.to_device(sw, dev)
-
-    print("[bench] generating %d points on the GPU ..." % n, file=sys.stderr, flush=True)
-    xy, inf = api.gen_points(k_dev, n)
-    torch.cuda.synchronize()
-    xyu = None
-
-    def prep():
-        nonlocal xyu
-        xyu, _ = api.points_prepare(xy, n, inf=inf, out=xyu)
-
-    prep()
-    prepare_ms = timed(prep, 3, torch)
-
-    # window sweep
-    sweep = {}
-    cs = [args.c] if args.c else C_SWEEP
-    for c in cs:
-        ws = api.workspace(n, c, device=dev)
-        res = api.words(api.MSM_RESULT_WORDS, dev)
-        fn = lambda: api.msm_run(xyu, s_dev, n, c, result=res, ws=ws)
-        fn()
-        sweep[c] = timed(fn, 2, torch)
-        del ws
-        print("[bench] c=%d: %.3f ms" % (c, sweep[c]), file=sys.stderr, flush=True)
-    best_c = min(sweep, key=sweep.get)
-
-    ws = api.workspace(n, best_c, device=dev)
-    res = api.words(api.MSM_RESULT_WORDS, dev)
-    step = lambda: api.msm_run(xyu, s_dev, n, best_c, result=res, ws=ws)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    for ph in ("sort", "accum", "merge", "agg", "horner"):
-        api.profile_read(ph)
-    api.profile_enable(True)
-    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0.record()
-    for _ in range(args.steps):
-        step()
-    t1.record()
-    torch.cuda.synchronize()
-    api.profile_enable(False)
-    ms_per_step = t0.elapsed_time(t1) / args.steps
-    phases = {}
-    for ph in ("sort", "accum", "merge", "agg", "horner"):
-        tot, cnt = api.profile_read(ph)
-        phases[ph] = tot / max(cnt, 1)
-    accum_tot_ms = phases["accum"]
-
-    entries = nonzero_digit_entries(sw, best_c)
-    padds = padd_count_executed(entries, best_c)
-    value = padds / (ms_per_step * 1e-3)
-    accum_mads = entries * MULS_MIXED * MAD_PER_MUL
-    achieved = accum_mads / (accum_tot_ms * 1e-3)
-
-    padd_k = None
-    chain_stream = None
-    if not args.no_padd_kernel:
-        pool_n = 8192
-        padd_k = padd_kernel_bench(torch, api, xyu[:pool_n * 36], pool_n, 1 << 22, 5)
-        chain_stream = chain_and_stream_bench(torch, api, xyu, padd_k.pop("_a_pool"), pool_n)
-        chain_stream["field_cores"] = field_core_bench(torch, api, inputs)
-
-    if cpu is not None:
-        cpu["msm_ms_extrapolated"] = padds / cpu["value"] * 1e3
-        cpu["sample"] = cpu["sample"].replace("c=16", "c=%d" % best_c)
-
-    del ws
-    ks_pool = [inputs.words_to_int(r) for r in kw[:N_CHECK_POOL]]
-    batched = None
-    if not args.no_batch:
-        batched = batched_bench(torch, api, inputs, xyu, ks_pool, args)
-    served = None
-    if not args.no_serve:
-        served = served_bench(torch, api, inputs, xyu, ks_pool, args)
-
-    out = {
-        "metric": "PADDs/s and MSM latency (ms) at n=2^20; batched/served MSMs/s + p99 vs plain",
-        "value": value,
-        "unit": "PADD/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic",
-        "config": {"workload": "BLS12-377 G1 MSM, n=2^20 points k_i*G, uniform scalars mod r",
-                   "n": n, "c": best_c, "digits": "signed",
-                   "windows": -(-254 // best_c), "seed": seed,
-                   "padds_per_msm": padds,
-                   "padds_per_msm_unsigned_formula": padd_count_formula(n, best_c)},
-        "msm_ms": ms_per_step,
-        "prepare_ms": prepare_ms,
-        "c_sweep_ms": {str(k): v for k, v in sweep.items()},
-        "phase_ms": phases,
-        "roofline": {
-            "kernel": "k_accum (bucket accumulation, mixed PADD)",
-            "bound": "alu",
-            "achieved": achieved / 1e12,
-            "peak": PEAK_MAD_PER_S / 1e12,
-            "unit": "Tmad/s (32x32->64 multiply-adds)",
-            "frac": achieved / PEAK_MAD_PER_S,
-            "traffic": accum_traffic(),
-            "work_per_launch": {"mixed_padds": entries, "mad_per_padd": MULS_MIXED * MAD_PER_MUL},
-            "launch_ms": accum_tot_ms,
-        },
-        "padd_kernel": padd_k,
-        "padd_workloads": chain_stream,
-        "batched": batched,
-        "served": served,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out))
-
-
-# ---------------------------------------------------------------------------
-# batched and served workloads
-# ---------------------------------------------------------------------------
-
-N_CHECK_POOL = 1 << 18   # pool points whose discrete logs the checks use
-
-
-def _closed_form_ok(msm_oracle, api, inputs, res_words, sc_words, ks):
-    ss = [inputs.words_to_int(r) for r in sc_words]
-    return api.decode_result(res_words) == (msm_oracle.closed_form(ss, ks), 0)
-
-
-def batched_bench(torch, api, inputs, xyu_pool, ks_pool, args):
-    """64 MSMs, n_j = floor(2^u), u ~ U[10, 18]: one graph-replayed batch with
-    autotuned widths, against 64 sequential msm_run calls."""
-    import numpy as np
-    from oracle import msm as msm_oracle
-    from paper_2502_11660_amd import autotune
-
-    seed = inputs.config_seed(4)
-    sizes = [int(x) for x in inputs.log_uniform_sizes(seed, 64, 10, 18)]
-    npool = xyu_pool.numel() // 36
-    ntot = sum(sizes)
-    sw = inputs.scalars_mod_r(seed, ntot, stream=2)
-    s_dev = api.to_device(sw)
-    rng = np.random.Generator(np.random.PCG64([seed, 3]))
-    offs = [int(rng.integers(0, N_CHECK_POOL - n + 1)) if n <= N_CHECK_POOL // 2
-            else int(rng.integers(0, npool - n + 1)) for n in sizes]
-    tuner = autotune.Autotuner(context="batch")
-    t0 = time.perf_counter()
-    for u in sorted({autotune.n_bucket(n) for n in sizes}):
-        tuner.tune(u, xyu_pool, s_dev)
-    tune_s = time.perf_counter() - t0
-    print("[bench] autotuned %d size classes in %.1f s" % (len(tuner.table), tune_s),
-          file=sys.stderr, flush=True)
-    tuned = {"u%d" % u: tuner.choose(1 << u) for u in sorted({autotune.n_bucket(n) for n in sizes})}
-
-    def jobs_with(cfun, results):
-        jobs, so = [], 0
-        for j, n in enumerate(sizes):
-            o = offs[j]
-            jobs.append((xyu_pool[o * 36:(o + n) * 36], s_dev[so * 8:(so + n) * 8], results[j], n,
-                         cfun(n)))
-            so += n
-        return jobs
-
-    reps = 5
-    out = {"jobs": 64, "points": ntot, "sizes_log2_range": [10, 18], "seed": seed,
-           "autotune_s": tune_s, "tuned_c": tuned}
-    res_b = [api.words(api.MSM_RESULT_WORDS) for _ in sizes]
-    for name, graph in (("batched_graph", True), ("batched_nograph", False)):
-        b = api.Batch(jobs_with(tuner.choose, res_b), use_graph=graph)
-        b.run()
-        ms = timed(b.run, reps, torch)
-        out[name] = {"ms": ms, "msms_per_s": 64 / (ms * 1e-3), "classes": len(
-            {tuner.choose(n) for n in sizes})}
-        b.destroy()
-    maxws = max(api.workspace_bytes(n, c) for n in sizes for c in
-                (api.default_window(n), tuner.choose(n)))
-    ws = torch.empty((maxws + 3) // 4, dtype=torch.int32, device=xyu_pool.device)
-    res_p = [api.words(api.MSM_RESULT_WORDS) for _ in sizes]
-    for name, cfun in (("plain_static_c", api.default_window), ("plain_tuned_c", tuner.choose)):
-        jobs = jobs_with(cfun, res_p)
-
-        def seq():
-            for (x, sc, r, n, c) in jobs:
-                api.msm_run(x, sc, n, c, result=r, ws=ws)
-        seq()
-        ms = timed(seq, reps, torch)
-        out[name] = {"ms": ms, "msms_per_s": 64 / (ms * 1e-3)}
-    torch.cuda.synchronize()
-    same = all(np.array_equal(api.to_host(a), api.to_host(b)) for a, b in zip(res_b, res_p))
-    checked = 0
-    so = 0
-    ok = True
-    for j, n in enumerate(sizes):
-        if offs[j] + n <= len(ks_pool) and checked < 8:
-            ok &= _closed_form_ok(msm_oracle, api, inputs, api.to_host(res_b[j]),
-                                  sw[so:so + n], ks_pool[offs[j]:offs[j] + n])
-            checked += 1
-        so += n
-    out["results_equal_plain_vs_batched"] = bool(same)
-    out["closed_form_checked_jobs"] = checked
-    out["closed_form_ok"] = bool(ok)
-    out["speedup_vs_plain_static"] = out["plain_static_c"]["ms"] / out["batched_graph"]["ms"]
-    print("[bench] batched %.2f ms vs plain %.2f ms" % (out["batched_graph"]["ms"],
-                                                      out["plain_static_c"]["ms"]),
-          file=sys.stderr, flush=True)
-    return out
-
-
-def served_bench(torch, api, inputs, xyu_pool, ks_pool, args):
-    """Poisson arrivals at 200/s, n = floor(2^u), u ~ U[12, 20], replayed
-    through the MSM server and through the plain path one at a time."""
-    import numpy as np
-    from oracle import msm as msm_oracle
-    from paper_2502_11660_amd import autotune, serve
-
-    seed = inputs.config_seed(5)
-    warm, meas = (5.0, 30.0) if args.serve_full else (1.0, args.serve_seconds)
-    arrivals = inputs.poisson_arrivals(seed, 200.0, warm + meas)
-    nreq = len(arrivals)
-    sizes = [int(x) for x in inputs.log_uniform_sizes(seed, nreq, 12, 20, stream=1)]
-    npool = xyu_pool.numel() // 36
-    spool_n = 1 << 21
-    sw = inputs.scalars_mod_r(seed, spool_n, stream=2)
-    s_dev = api.to_device(sw)
-    rng = np.random.Generator(np.random.PCG64([seed, 3]))
-    poffs = [int(rng.integers(0, npool - n + 1)) for n in sizes]
-    soffs = [int(rng.integers(0, spool_n - n + 1)) for n in sizes]
-    tuner = autotune.Autotuner(context="solo")
-    for u in range(12, 21):
-        if not tuner.tuned(u):
-            tuner.tune(u, xyu_pool, s_dev)
-    out_tuned = {"u%d" % u: tuner.choose(1 << u) for u in range(12, 21)}
-    results = torch.zeros(nreq, api.MSM_RESULT_WORDS, dtype=torch.int32, device=xyu_pool.device)
-
-    def jobs_for(cfun):
-        return [(xyu_pool[po * 36:(po + n) * 36], s_dev[so * 8:(so + n) * 8], results[i], n, cfun(n))
-                for i, (n, po, so) in enumerate(zip(sizes, poffs, soffs))]
-
-    measured = np.asarray(arrivals) >= warm
-    free, _ = torch.cuda.mem_get_info()
-    out = {"rate_per_s": 200.0, "warmup_s": warm, "measured_s": meas, "requests": nreq,
-           "sizes_log2_range": [12, 20], "seed": seed, "streams": 4,
-           "tuned_c_solo": out_tuned}
-    budgets = [("half_free_hbm", int(free * 0.5))]
-    if args.serve_full:
-        budgets.append(("2GB", 2 << 30))
-    served_words = None
-    for name, budget in budgets:
-        srv = api.Server(budget, streams=4)
-        print("[bench] serving %d requests, budget %.1f GB ..." % (nreq, budget / 1e9),
-              file=sys.stderr, flush=True)
-        lat, wall = serve.replay_served(srv, arrivals, jobs_for(tuner.choose), progress_every=5.0)
-        srv.destroy()
-        out[name] = serve.summarize(lat, wall, measured)
-        out[name]["budget_bytes"] = budget
-        if served_words is None:
-            torch.cuda.synchronize()
-            served_words = results.cpu().numpy().copy()
-    results.zero_()
-    maxws = max(api.workspace_bytes(n, 0) for n in set(sizes))
-    ws = torch.empty((maxws + 3) // 4, dtype=torch.int32, device=xyu_pool.device)
-    print("[bench] plain replay ...", file=sys.stderr, flush=True)
-    lat_p, wall_p = serve.replay_plain(arrivals, jobs_for(lambda n: 0),
-                                       workspaces=lambda n, c: ws, progress_every=5.0)
-    out["plain_fifo"] = serve.summarize(lat_p, wall_p, measured)
-    plain_words = results.cpu().numpy()
-    out["results_equal_served_vs_plain"] = bool(np.array_equal(served_words, plain_words))
-    ok, checked = True, 0
-    for i, n in enumerate(sizes):
-        if poffs[i] + n <= len(ks_pool) and checked < 6:
-            ok &= _closed_form_ok(msm_oracle, api, inputs, plain_words[i].view(np.uint32),
-                                  sw[soffs[i]:soffs[i] + n], ks_pool[poffs[i]:poffs[i] + n])
-            checked += 1
-    out["closed_form_checked_requests"] = checked
-    out["closed_form_ok"] = bool(ok)
-    return out
-
-
-def accum_traffic():
-    """HBM bytes per accumulation launch from the committed rocprofv3 counter
-    summary, if it was taken on the current accumulation kernel sources."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "k_accum_traffic.json")
-    try:
-        with open(path) as f:
-            rec = json.load(f)
-    except (OSError, ValueError):
-        return None
-    h = hashlib.sha256()
-    for src in rec.get("sources", []):
-        with open(os.path.join(ROOT, src), "rb") as f:
-            h.update(f.read())
-    if h.hexdigest() != rec.get("sources_sha256"):
         return None
     return rec.get("bytes_per_launch")
 

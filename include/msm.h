@@ -79,11 +79,11 @@ extern "C" {
  *    lambda = x0^2 - 1, and lambda^2 + lambda + 1 = r, so each scalar splits
  *    as s = s1 lambda + s0 with s0, s1 < 2^127 and s P = s0 P + s1 phi(P).
  *    The prepared points must come from msm_points_prepare_endo (2n records:
- *    the n points, then their images); the 2n half-scalars use signed digits
- *    with W = ceil(128 / c) windows and 2^(c-1) buckets per window, bucket
- *    entries indexed by record (point i: s0 of scalar i; record n + i: s1 of
- *    scalar i).  Requires c >= 2; scalars are given as for the other
- *    encodings. */
+ *    each point followed by its image); the 2n half-scalars use signed
+ *    digits with W = ceil(128 / c) windows and 2^(c-1) buckets per window,
+ *    bucket entries indexed by record (record 2i: s0 of scalar i; record
+ *    2i + 1: s1 of scalar i).  Requires c >= 2; scalars are given as for
+ *    the other encodings. */
 #define MSM_DIGITS_GLV 2
 
 /* Batched point addition out_i = a_i + b_i (Sec. II-D; the paper's "task").
@@ -159,8 +159,9 @@ int msm_points_prepare(const uint32_t* xy_std, const uint32_t* inf, uint32_t* xy
 
 /* As msm_points_prepare, and also the images phi(P_i) = (omega x_i, y_i)
  * of the points under the curve's order-3 automorphism (for
- * MSM_DIGITS_GLV): xyu receives 2n AoS records, record i = P_i and record
- * n + i = phi(P_i).  Errors: MSM_EINVAL for null pointers, n = 0 or
+ * MSM_DIGITS_GLV): xyu receives 2n AoS records, record 2i = P_i and
+ * record 2i + 1 = phi(P_i), so the records of a slice of the points are a
+ * slice of the records.  Errors: MSM_EINVAL for null pointers, n = 0 or
  * n >= 2^30. */
 int msm_points_prepare_endo(const uint32_t* xy_std, const uint32_t* inf, uint32_t* xyu, size_t n,
                             uint32_t* status, void* stream);
@@ -176,6 +177,15 @@ int msm_gen_points(const uint32_t* k, size_t n, uint32_t* xy_std, uint32_t* inf,
  * out of range for the encoding). */
 int msm_num_windows(int c, int encoding);
 
+/* Bits per window for a requested width c: the windows keep their count
+ * W = msm_num_windows(c, encoding), and the width is lowered to the smallest
+ * one that still covers the digit bits (253 unsigned, 254 signed, 128 for the
+ * endomorphism halves) with W windows, so that the top window is not left
+ * with a few bits whose digits would crowd a handful of buckets.  Bucket
+ * arrays have 2^c' (unsigned) or 2^(c'-1) buckets per window for this c'.
+ * Returns 0 when c is out of range for the encoding. */
+int msm_window_bits(int c, int encoding);
+
 /* Workspace (device bytes) needed by msm_bucket_accumulate / msm_run for n
  * points, window width c (c = 0: the width msm_run would pick) and a digit
  * encoding.  Returns 0 for invalid arguments. */
@@ -184,10 +194,11 @@ size_t msm_workspace_bytes(size_t n, int c, int encoding);
 /* Window width msm_run picks for n points when called with c = 0. */
 int msm_default_window(size_t n);
 
-/* Bucket accumulation (Sec. II-C).  With unsigned digits B[w][b] = sum of
- * the P_i whose w-th digit d_w(s_i) equals b, 0 <= b < 2^c (bucket 0 holds
- * the identity); with signed digits B[w][m] = sum of sign(d_w(s_i)) P_i over
- * the i with |d_w(s_i)| = m + 1, 0 <= m < 2^(c-1).  xyu: AoS prepared points
+/* Bucket accumulation (Sec. II-C), digits of c' = msm_window_bits(c,
+ * encoding) bits.  With unsigned digits B[w][b] = sum of the P_i whose w-th
+ * digit d_w(s_i) equals b, 0 <= b < 2^c' (bucket 0 holds the identity); with
+ * signed digits B[w][m] = sum of sign(d_w(s_i)) P_i over the i with
+ * |d_w(s_i)| = m + 1, 0 <= m < 2^(c'-1).  xyu: AoS prepared points
  * (msm_points_prepare).  scalars: 8 words per scalar.  buckets: AoS XYTZ
  * records, record index w * (buckets per window) + bucket, Montgomery form,
  * lazily reduced (< 2p; compare after normalisation -- any projective

@@ -56,6 +56,7 @@ SIGNATURES = {
     "msm_num_windows": (_I, [_I, _I]),
     "msm_workspace_bytes": (_SZ, [_SZ, _I, _I]),
     "msm_default_window": (_I, [_SZ]),
+    "msm_window_bits": (_I, [_I, _I]),
     "msm_bucket_accumulate": (_I, [_P, _P, _SZ, _I, _I, _P, _P, _SZ, _P]),
     "msm_run": (_I, [_P, _P, _SZ, _I, _I, _P, _P, _SZ, _P]),
     "msm_batch_workspace_bytes": (_SZ, [ctypes.POINTER(MsmJob), _SZ, _I]),

@@ -155,8 +155,13 @@ def num_windows(c, encoding=MSM_DIGITS_SIGNED):
     return _lib.lib().msm_num_windows(c, encoding)
 
 
+def window_bits(c, encoding=MSM_DIGITS_SIGNED):
+    return _lib.lib().msm_window_bits(c, encoding)
+
+
 def buckets_per_window(c, encoding=MSM_DIGITS_SIGNED):
-    return 1 << (c if encoding == MSM_DIGITS_UNSIGNED else c - 1)
+    cb = window_bits(c, encoding)
+    return 1 << (cb if encoding == MSM_DIGITS_UNSIGNED else cb - 1)
 
 
 def default_window(n):

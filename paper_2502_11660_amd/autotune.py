@@ -64,9 +64,11 @@ class Autotuner:
     def tune(self, u, xyu_pool, scalar_pool, span=(-3, 2), reps=3, batch_points=1 << 20):
         """Time jobs of size 2^u over pool slices -- batches of about
         batch_points points (at most 64 jobs) in context "batch", single jobs
-        in context "solo" -- and store and return the best width."""
+        in context "solo" -- and store and return the best width.  With the
+        endomorphism encoding the pool holds two records per point."""
         n = 1 << u
-        npool = xyu_pool.numel() // api.XYU_WORDS
+        rec = 2 if self.encoding == api.MSM_DIGITS_GLV else 1  # records per point
+        npool = xyu_pool.numel() // (api.XYU_WORDS * rec)
         if n > npool or n > scalar_pool.numel() // api.SCALAR_WORDS:
             raise ValueError("pool smaller than 2^%d" % u)
         jobs_n = max(1, min(64, batch_points // n)) if self.context == "batch" else 1
@@ -78,7 +80,7 @@ class Autotuner:
             jobs = []
             for j in range(jobs_n):
                 off = (j * 7919) % (npool - n + 1)
-                jobs.append((xyu_pool[off * 36:(off + n) * 36],
+                jobs.append((xyu_pool[rec * off * 36:rec * (off + n) * 36],
                              scalar_pool[off * 8:(off + n) * 8], results[j], n, c))
             b = api.Batch(jobs, self.encoding, use_graph=True)
             b.run()

@@ -135,6 +135,7 @@ struct Plan {
 };
 
 int num_windows(int c, int encoding);
+int window_bits(int c, int encoding);
 int default_window(size_t n);
 // plan of a batch with job sizes ns[0..J); false for invalid sizes or c
 bool make_plan(const size_t* ns, uint32_t J, int c, int encoding, Plan& pl);

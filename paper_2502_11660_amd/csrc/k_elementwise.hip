@@ -85,7 +85,7 @@ __device__ __forceinline__ void prepare_identity(uint32_t* rec) {
   st_aos(rec, 2, fe_zero());
 }
 
-// ENDO: also write the image (omega x, y) of every point at record n + i
+// ENDO: records 2i and 2i + 1 hold point i and its image (omega x, y)
 template <bool ENDO>
 __global__ void __launch_bounds__(256) k_prepare(const uint32_t* __restrict__ xy,
                                                  const uint32_t* __restrict__ inf,
@@ -93,8 +93,8 @@ __global__ void __launch_bounds__(256) k_prepare(const uint32_t* __restrict__ xy
                                                  uint32_t* __restrict__ status) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  uint32_t* rec = out + (size_t)i * XYU_WORDS;
-  uint32_t* rec2 = out + (size_t)(n + i) * XYU_WORDS;
+  uint32_t* rec = out + (size_t)(ENDO ? 2 * i : i) * XYU_WORDS;
+  uint32_t* rec2 = rec + XYU_WORDS;
   if (inf && inf[i]) {
     prepare_identity(rec);
     if (ENDO) prepare_identity(rec2);

@@ -81,9 +81,9 @@ __device__ __forceinline__ size_t count_index(const SortGeom& g, const JobDesc& 
 // at W pt_off + w n + i holds q | sign << 31, where q = 0 drops the entry and
 // otherwise bucket m = q - 1 (signed digits, q = |d|) or m = q (unsigned
 // digits, q = d, so unsigned bucket 0 never receives points).  With the
-// endomorphism split a job's n points are its n / 2 input points followed by
-// their images: point i < n / 2 takes the digits of s0 of scalar i, point
-// n / 2 + i those of s1.
+// endomorphism split a job's n points are its n / 2 input points and their
+// images, interleaved: point 2i takes the digits of s0 of scalar i, point
+// 2i + 1 those of s1.
 __global__ void __launch_bounds__(256) k_slice(JobView jv, uint32_t N, int c, int W, int encoding,
                                                uint32_t* __restrict__ digits,
                                                uint32_t* __restrict__ flags) {
@@ -95,11 +95,9 @@ __global__ void __launch_bounds__(256) k_slice(JobView jv, uint32_t N, int c, in
   uint32_t* out = digits + (size_t)W * d.pt_off + i;
   scalar256 s;
   if (encoding == MSM_DIGITS_GLV) {
-    const uint32_t half = d.n >> 1;
-    const bool image = i >= half;
     scalar256 s0, s1;
-    glv_split(ld_scalar(d.scalars, image ? i - half : i, flags + j), s0, s1);
-    s = image ? s1 : s0;
+    glv_split(ld_scalar(d.scalars, i >> 1, flags + j), s0, s1);
+    s = (i & 1u) ? s1 : s0;
   } else {
     s = ld_scalar(d.scalars, i, flags + j);
   }

@@ -70,6 +70,19 @@ int num_windows(int c, int encoding) {
   return 0;
 }
 
+// Window width actually used for a requested width c: the smallest width
+// that covers the digit bits with the same number of windows, so that no
+// window (in particular the top one) is left with a few bits whose digits
+// would crowd a handful of buckets.
+int window_bits(int c, int encoding) {
+  const int W = num_windows(c, encoding);
+  if (W == 0) return 0;
+  const int bits = encoding == MSM_DIGITS_UNSIGNED ? SCALAR_BITS
+                   : encoding == MSM_DIGITS_GLV    ? GLV_BITS + 1
+                                                   : SCALAR_BITS + 1;
+  return (bits + W - 1) / W;
+}
+
 int default_window(size_t n) {
   // additions ~ n W (accumulation) + ~1.3 * 2^c W (signed-digit aggregation
   // of 2^(c-1) buckets per window, merges included)
@@ -86,10 +99,11 @@ int default_window(size_t n) {
   return best;
 }
 
-bool make_plan(const size_t* ns, uint32_t J, int c, int encoding, Plan& pl) {
+bool make_plan(const size_t* ns, uint32_t J, int c_req, int encoding, Plan& pl) {
   pl = Plan();
-  const int W = num_windows(c, encoding);
+  const int W = num_windows(c_req, encoding);
   if (W == 0 || J == 0 || !ns) return false;
+  const int c = window_bits(c_req, encoding);
   pl.c = c;
   pl.W = W;
   pl.encoding = encoding;
@@ -190,6 +204,8 @@ const char* msm_status_string(int status) {
 int msm_num_windows(int c, int encoding) { return num_windows(c, encoding); }
 
 int msm_default_window(size_t n) { return default_window(n); }
+
+int msm_window_bits(int c, int encoding) { return window_bits(c, encoding); }
 
 size_t msm_workspace_bytes(size_t n, int c, int encoding) {
   if (c == 0) c = default_window(n);

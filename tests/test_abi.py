@@ -128,6 +128,16 @@ def test_window_helpers(lib):
         assert lib.msm_workspace_bytes(n, 0, S) == lib.msm_workspace_bytes(n, c, S)
     # signed digits halve the bucket storage
     assert lib.msm_workspace_bytes(1 << 16, 16, S) < lib.msm_workspace_bytes(1 << 16, 16, U)
+    # window widths are lowered to cover the digit bits with the same windows
+    G = _lib.MSM_DIGITS_GLV
+    for enc, bits in ((U, 253), (S, 254), (G, 128)):
+        for c in range(2, 21):
+            W = lib.msm_num_windows(c, enc)
+            cb = lib.msm_window_bits(c, enc)
+            assert cb <= c and W * cb >= bits and W * (cb - 1) < bits, (enc, c)
+    assert lib.msm_window_bits(17, G) == 16 and lib.msm_window_bits(18, S) == 17
+    assert lib.msm_workspace_bytes(1 << 12, 17, G) == lib.msm_workspace_bytes(1 << 12, 16, G)
+    assert lib.msm_window_bits(1, S) == 0 and lib.msm_window_bits(21, U) == 0
     # a batch of one job needs what a single MSM needs
     Job = _lib.MsmJob
     one = (Job * 1)(Job(16, 16, 16, 5000, 11))

@@ -42,8 +42,8 @@ def test_prepare_endo_records(oracle_pool):
                                                    inf=_dev(np.array([p is None for p in sel],
                                                                      dtype=np.uint32)))[0]), 3, n)
     for i, pt in enumerate(sel):
-        assert recs[i] == plain[i]
-        assert recs[n + i] == H.te_prepared_mont(te.w_to_te(glv.phi(pt))), i
+        assert recs[2 * i] == plain[i]
+        assert recs[2 * i + 1] == H.te_prepared_mont(te.w_to_te(glv.phi(pt))), i
 
 
 @pytest.mark.parametrize("c", [2, 5, 8, 13, 16])
@@ -77,8 +77,7 @@ def test_glv_buckets_match_definition(oracle_pool):
     sc = [inputs.words_to_int(r) for r in inputs.scalars_mod_r(3100, n)]
     xyu = _prepared_endo(pts[:n])
     buckets, ws = api.bucket_accumulate(xyu, _dev(H.scalar_words(sc)), n, c, GLV)
-    sc2 = [glv.split(s)[0] for s in sc] + [glv.split(s)[1] for s in sc]
-    pts2 = list(pts[:n]) + [glv.phi(p) for p in pts[:n]]
+    sc2, pts2 = glv.msm_split(sc, pts[:n])   # interleaved like the records
     W = msm.num_signed_windows(c, glv.SPLIT_BITS)
     B = 1 << (c - 1)
     assert W == api.num_windows(c, GLV)
@@ -92,28 +91,28 @@ def test_glv_buckets_match_definition(oracle_pool):
 def test_glv_batch_and_server(oracle_pool):
     ks, pts = oracle_pool
     sizes = [1, 33, 500, 2000, 700]
+    offs = [5, 0, 1000, 0, 1300]
     pool = _prepared_endo(pts[:2048])
     jobs, meta = [], []
-    for j, n in enumerate(sizes):
-        # a job's records must be its points followed by their images
-        xyu = _prepared_endo(pts[:n])
+    for j, (n, o) in enumerate(zip(sizes, offs)):
+        # slices of the interleaved records are the records of the slice
+        xyu = pool[2 * o * 36:2 * (o + n) * 36]
         sc = [inputs.words_to_int(r) for r in inputs.scalars_mod_r(3200 + j, n)]
         jobs.append((xyu, _dev(H.scalar_words(sc)), api.words(api.MSM_RESULT_WORDS), n, 0))
-        meta.append(sc)
-    del pool
+        meta.append((o, sc))
     b = api.Batch(jobs, api.MSM_DIGITS_GLV, use_graph=True)
     b.run()
     torch.cuda.synchronize()
-    for (x, s, r, n, c), sc in zip(jobs, meta):
-        assert api.decode_result(api.to_host(r)) == (msm.closed_form(sc, ks[:n]), 0), n
+    for (x, s, r, n, c), (o, sc) in zip(jobs, meta):
+        assert api.decode_result(api.to_host(r)) == (msm.closed_form(sc, ks[o:o + n]), 0), n
     b.destroy()
     srv = api.Server(1 << 30, streams=2, encoding=GLV)
     for job in jobs:
         job[2].zero_()
         srv.submit(*job)
     srv.drain()
-    for (x, s, r, n, c), sc in zip(jobs, meta):
-        assert api.decode_result(api.to_host(r)) == (msm.closed_form(sc, ks[:n]), 0), n
+    for (x, s, r, n, c), (o, sc) in zip(jobs, meta):
+        assert api.decode_result(api.to_host(r)) == (msm.closed_form(sc, ks[o:o + n]), 0), n
     srv.destroy()
 
 
