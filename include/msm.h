@@ -137,12 +137,16 @@ int msm_fe_mul_batch(const uint32_t* a, const uint32_t* b, uint32_t* out, size_t
  *    out = a b^rounds mod p.
  *  MSM_MUL_KARATSUBA: Montgomery with one Karatsuba level over 6-word halves
  *    and a separate reduction: same output as MSM_MUL_MONT.
+ *  MSM_MUL_WIDE: the Montgomery product spread over one wave (16 limbs of 24
+ *    bits, one per lane), one wave per element: the latency-oriented form;
+ *    same output as MSM_MUL_MONT.
  * a, b, out: SoA, one coordinate (12 x count words); inputs canonical
  * (< p); output canonical.  Errors: MSM_EINVAL (null pointers, count = 0 or
  * >= 2^31, rounds < 1, unknown variant), MSM_EHIP. */
 #define MSM_MUL_MONT 0
 #define MSM_MUL_BARRETT 1
 #define MSM_MUL_KARATSUBA 2
+#define MSM_MUL_WIDE 3
 int msm_fe_mul_chain(const uint32_t* a, const uint32_t* b, uint32_t* out, size_t count,
                      int variant, int rounds, void* stream);
 

@@ -56,7 +56,8 @@ def split(s):
 
 
 def msm_split(scalars, points):
-    """The 2n-point MSM with half-length scalars that equals the original."""
+    """The 2n-point MSM with half-length scalars that equals the original
+    (point i followed by its image, scalar halves s0, s1 likewise)."""
     pts, sc = [], []
     for s, pt in zip(scalars, points):
         s0, s1 = split(s)

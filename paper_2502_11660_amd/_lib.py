@@ -36,6 +36,7 @@ MSM_UNIT_LANE = 1
 MSM_MUL_MONT = 0
 MSM_MUL_BARRETT = 1
 MSM_MUL_KARATSUBA = 2
+MSM_MUL_WIDE = 3
 
 
 class MsmJob(ctypes.Structure):

@@ -4,6 +4,7 @@
 // throughput and the value pins every product).
 #include "common.hpp"
 #include "field_variants.hpp"
+#include "wide.hpp"
 
 namespace msm {
 namespace {
@@ -28,6 +29,19 @@ __global__ void __launch_bounds__(256) k_fe_mul_chain(const uint32_t* __restrict
   st_soa(out, count, 0, i, fe_canon(x));
 }
 
+// one wave per element: the same chain with the lane-parallel product
+__global__ void __launch_bounds__(64) k_fe_mul_chain_wide(const uint32_t* __restrict__ a,
+                                                          const uint32_t* __restrict__ b,
+                                                          uint32_t* __restrict__ out,
+                                                          uint32_t count, uint32_t rounds) {
+  const uint32_t e = blockIdx.x;
+  wfe x = wfe_from_words(ld_soa(a, count, 0, e));
+  const wfe y = wfe_from_words(ld_soa(b, count, 0, e));
+  for (uint32_t r = 0; r < rounds; ++r) x = wfe_mul(x, y);
+  const fe w = fe_canon(wfe_to_words(x));
+  if (threadIdx.x == 0) st_soa(out, count, 0, e, w);
+}
+
 }  // namespace
 }  // namespace msm
 
@@ -49,6 +63,10 @@ extern "C" int msm_fe_mul_chain(const uint32_t* a, const uint32_t* b, uint32_t* 
     case MSM_MUL_KARATSUBA:
       k_fe_mul_chain<MSM_MUL_KARATSUBA><<<grid, 256, 0, st>>>(a, b, out, (uint32_t)count,
                                                               (uint32_t)rounds);
+      break;
+    case MSM_MUL_WIDE:
+      k_fe_mul_chain_wide<<<(unsigned)count, 64, 0, st>>>(a, b, out, (uint32_t)count,
+                                                           (uint32_t)rounds);
       break;
     default:
       return MSM_EINVAL;

@@ -18,13 +18,13 @@ R_INV = pow(1 << 384, -1, P)
 
 def _expected(variant, a, b, rounds):
     v = a * pow(b, rounds, P) % P
-    if variant in (api.MSM_MUL_MONT, api.MSM_MUL_KARATSUBA):
+    if variant in (api.MSM_MUL_MONT, api.MSM_MUL_KARATSUBA, api.MSM_MUL_WIDE):
         v = v * pow(R_INV, rounds, P) % P
     return v
 
 
 @pytest.mark.parametrize("variant", [api.MSM_MUL_MONT, api.MSM_MUL_BARRETT,
-                                     api.MSM_MUL_KARATSUBA])
+                                     api.MSM_MUL_KARATSUBA, api.MSM_MUL_WIDE])
 @pytest.mark.parametrize("rounds", [1, 7])
 def test_fe_mul_chain_variants(variant, rounds):
     rng = random.Random(100 + variant * 10 + rounds)
