@@ -217,7 +217,8 @@ def chain_and_stream_bench(torch, api, xyu_pool, a_pool_soa, pool_n):
     recs = a_pool_soa.view(48, pool_n).t().contiguous()          # AoS XYTZ
     out = {"paper_latency_us_per_padd": 1.05, "paper_throughput_mtask_per_s": 67.0}
     chain = {}
-    for name, unit, count in (("quad", api.MSM_UNIT_QUAD, 1 << 18), ("lane", api.MSM_UNIT_LANE, 1 << 16)):
+    for name, unit, count in (("wide", api.MSM_UNIT_WIDE, 1 << 18), ("quad", api.MSM_UNIT_QUAD, 1 << 18),
+                              ("lane", api.MSM_UNIT_LANE, 1 << 16)):
         pts = recs.repeat((count + pool_n - 1) // pool_n, 1)[:count].contiguous().view(-1)
         api.padd_chain(pts, 64, unit)
         ms = timed(lambda: api.padd_chain(pts, count, unit), 1, torch)

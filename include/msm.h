@@ -101,9 +101,12 @@ int msm_padd_batch(const uint32_t* a_xytz, const uint32_t* b, uint32_t* out_xytz
  *   after another into a single accumulator (starting at the identity), each
  *   addition waiting for the previous one, with the complete addition.
  *   pts_xytz: AoS XYTZ records (48 words each, Montgomery form, coordinates
- *   < 2p).  unit: MSM_UNIT_QUAD (four lanes share one point: the latency unit
- *   bucket and group aggregation use) or MSM_UNIT_LANE (one lane does the
- *   whole addition).  out_xytz: one AoS XYTZ record, lazily reduced (< 2p).
+ *   < 2p).  unit: MSM_UNIT_WIDE (two waves share one point, each
+ *   coordinate spread over 16 lanes as 24-bit limbs, a third wave preparing
+ *   k T of the next point: the latency unit group aggregation uses),
+ *   MSM_UNIT_QUAD (four lanes share one point: the latency unit of the
+ *   aggregation tree) or MSM_UNIT_LANE (one lane does the whole addition).
+ *   out_xytz: one AoS XYTZ record, lazily reduced (< 2p).
  *   Errors: MSM_EINVAL (null pointers, count = 0 or >= 2^31, unknown unit).
  *
  * msm_accumulate_stream -- throughput: `accumulators` independent running
@@ -114,6 +117,7 @@ int msm_padd_batch(const uint32_t* a_xytz, const uint32_t* b, uint32_t* out_xytz
  *   Errors: MSM_EINVAL (null pointers, n = 0, A = 0, n or A >= 2^31). */
 #define MSM_UNIT_QUAD 0
 #define MSM_UNIT_LANE 1
+#define MSM_UNIT_WIDE 2
 int msm_padd_chain(const uint32_t* pts_xytz, size_t count, int unit, uint32_t* out_xytz,
                    void* stream);
 int msm_accumulate_stream(const uint32_t* xyu, size_t n, size_t accumulators, uint32_t* out_xytz,
@@ -137,9 +141,10 @@ int msm_fe_mul_batch(const uint32_t* a, const uint32_t* b, uint32_t* out, size_t
  *    out = a b^rounds mod p.
  *  MSM_MUL_KARATSUBA: Montgomery with one Karatsuba level over 6-word halves
  *    and a separate reduction: same output as MSM_MUL_MONT.
- *  MSM_MUL_WIDE: the Montgomery product spread over one wave (16 limbs of 24
- *    bits, one per lane), one wave per element: the latency-oriented form;
- *    same output as MSM_MUL_MONT.
+ *  MSM_MUL_WIDE: the Montgomery product spread over lanes (16 limbs of 24
+ *    bits, one per lane, two elements per wave), with the reduction digits
+ *    formed as one product m = (a b mod R)(-p^-1) mod R: the latency-oriented
+ *    form; same output as MSM_MUL_MONT.
  * a, b, out: SoA, one coordinate (12 x count words); inputs canonical
  * (< p); output canonical.  Errors: MSM_EINVAL (null pointers, count = 0 or
  * >= 2^31, rounds < 1, unknown variant), MSM_EHIP. */

@@ -33,6 +33,7 @@ MSM_DIGITS_UNSIGNED = 1
 MSM_DIGITS_GLV = 2
 MSM_UNIT_QUAD = 0
 MSM_UNIT_LANE = 1
+MSM_UNIT_WIDE = 2
 MSM_MUL_MONT = 0
 MSM_MUL_BARRETT = 1
 MSM_MUL_KARATSUBA = 2

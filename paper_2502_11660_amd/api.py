@@ -17,7 +17,7 @@ from ._lib import (MSM_DIGITS_GLV, MSM_DIGITS_SIGNED, MSM_DIGITS_UNSIGNED,  # no
                    MSM_FLAG_OFFCURVE, MSM_FLAG_RANGE, MSM_FORM_XYTZ, MSM_FORM_XYU,
                    MSM_MUL_BARRETT, MSM_MUL_KARATSUBA, MSM_MUL_MONT, MSM_MUL_WIDE,
                    MSM_RESULT_WORDS,
-                   MSM_UNIT_LANE, MSM_UNIT_QUAD, MSMError, MsmJob)
+                   MSM_UNIT_LANE, MSM_UNIT_QUAD, MSM_UNIT_WIDE, MSMError, MsmJob)
 
 WORDS = 12
 XYU_WORDS = 36

@@ -17,12 +17,13 @@
 // Each window then forms S_w by Horner's rule on one quad, and group
 // aggregation Q = sum_w 2^(w c) S_w is Horner's rule over the windows of a job
 // (c doublings per window), the dependent chain the paper assigns to its
-// low-latency unit; one quad per job.  The result is mapped back to
-// Weierstrass affine form.  A "window" below is a segment: one window of one
+// low-latency unit: one wide two-wave unit per job (wide_unit.hpp).  The
+// result is mapped back to Weierstrass affine form.  A "window" below is a segment: one window of one
 // job of the batch.
 #include "common.hpp"
 #include "convert.hpp"
 #include "quad.hpp"
+#include "wide_unit.hpp"
 
 namespace msm {
 namespace {
@@ -105,21 +106,29 @@ __global__ void __launch_bounds__(64) k_window_combine(const uint32_t* __restric
   quad_st(wsum + (size_t)(2 * w + 1) * XYTZ_WORDS, quad_to_u(acc));
 }
 
-// Group aggregation of job j (quad j): Q = sum_w 2^(w c) S_w by Horner's rule
-// over the job's W windows, then the affine Weierstrass result.
-__global__ void __launch_bounds__(64) k_horner(const uint32_t* __restrict__ wsum, JobView jv,
-                                               uint32_t W, uint32_t c,
-                                               uint32_t* __restrict__ qstate) {
-  const uint32_t j = (blockIdx.x * blockDim.x + threadIdx.x) >> 2;
-  if (j >= jv.J) return;
-  const fe p2 = fe_const(kP2);
-  const uint32_t* ws = wsum + (size_t)2 * j * W * XYTZ_WORDS;
-  fe q = quad_ld(ws + (size_t)(2 * (W - 1)) * XYTZ_WORDS);
+// Group aggregation of job j (block j, one wide unit): Q = sum_w 2^(w c) S_w
+// by Horner's rule over the job's W windows.  Each lane loads its limb of the
+// next window sum while the doublings of the current window run.
+__global__ void __launch_bounds__(128) k_horner_wide(const uint32_t* __restrict__ wsum,
+                                                     uint32_t W, uint32_t c,
+                                                     uint32_t* __restrict__ qstate) {
+  __shared__ wunit_lds<2> s;
+  const uint32_t job = blockIdx.x;
+  wunit_init(s);
+  const wslot q = wslot_here();
+  const uint32_t* ws = wsum + (size_t)2 * job * W * XYTZ_WORDS;
+  const uint32_t top = wu_load_limb(ws + (size_t)(2 * (W - 1)) * XYTZ_WORDS, q.k, q.j);
+  uint32_t nxt = W >= 2 ? wu_load_limb(ws + (size_t)(2 * W - 3) * XYTZ_WORDS, q.k, q.j) : 0u;
+  unit_sync();
+  if (q.act) s.acc[16 * q.k + q.j] = top;  // S_{W-1}, XYTZ
+  unit_sync();
   for (int w = (int)W - 2; w >= 0; --w) {
-    for (uint32_t t = 0; t < c; ++t) q = quad_dbl(q, p2);
-    q = quad_add_u(q, quad_ld(ws + (size_t)(2 * w + 1) * XYTZ_WORDS), p2);
+    if (q.act) s.opd[0][16 * q.k + q.j] = nxt;  // S_w, XYUZ (read after the doublings)
+    if (w >= 1) nxt = wu_load_limb(ws + (size_t)(2 * w - 1) * XYTZ_WORDS, q.k, q.j);
+    for (uint32_t t = 0; t < c; ++t) wu_dbl(s, q);
+    wu_add_u(s, s.opd[0], q);
   }
-  quad_st(qstate + (size_t)j * XYTZ_WORDS, q);
+  if (threadIdx.x < 64) wu_store_acc(s, qstate + (size_t)job * XYTZ_WORDS);
 }
 
 // The affine Weierstrass result of each job, one lane per job.
@@ -175,8 +184,8 @@ int launch_horner(const Plan& pl, void* ws, hipStream_t st) {
   ProfScope prof(PT_HORNER, st);
   const JobView jv = job_view(pl, ws);
   uint32_t* qstate = ws_at<uint32_t>(ws, pl.o_qstate);
-  k_horner<<<grid_for(4 * (size_t)pl.J, 64), 64, 0, st>>>(ws_at<uint32_t>(ws, pl.o_wsum), jv,
-                                                          (uint32_t)pl.W, (uint32_t)pl.c, qstate);
+  k_horner_wide<<<(unsigned)pl.J, 128, 0, st>>>(ws_at<uint32_t>(ws, pl.o_wsum), (uint32_t)pl.W,
+                                                 (uint32_t)pl.c, qstate);
   k_finalize<<<grid_for(pl.J, 64), 64, 0, st>>>(qstate, jv, ws_at<uint32_t>(ws, pl.o_flags));
   HIPCHK(hipGetLastError());
   return MSM_OK;

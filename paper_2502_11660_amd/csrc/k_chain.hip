@@ -2,13 +2,14 @@
 //
 //  * latency: one accumulator adds the input points one after another, each
 //    addition waiting for the previous one (the chain bucket and group
-//    aggregation are made of); here on the four-lane latency unit or on one
-//    lane, with the complete addition;
+//    aggregation are made of); here on the wide two-wave unit, the four-lane
+//    unit or one lane, with the complete addition;
 //  * throughput: many independent accumulators, each fed prepared points and
 //    returning its sum once at the end (the shape of bucket accumulation),
 //    with the mixed addition.
 #include "common.hpp"
 #include "quad.hpp"
+#include "wide_unit.hpp"
 
 namespace msm {
 namespace {
@@ -43,6 +44,75 @@ __global__ void __launch_bounds__(64) k_chain_lane(const uint32_t* __restrict__ 
     acc = padd_full(acc, cur, p2);
   }
   st_xytz(out, acc);
+}
+
+// The wide unit: waves 0 and 1 run the additions (two phases of four
+// products); wave 2 prepares the next operand (U = k T, one product) while
+// they add the current one, and loads the point after that.
+__global__ void __launch_bounds__(192) k_chain_wide(const uint32_t* __restrict__ pts,
+                                                    uint32_t count, uint32_t* __restrict__ out) {
+  __shared__ wunit_lds<3> s;
+  wunit_init(s);
+  const wslot q = wslot_here();
+  const bool prep = (threadIdx.x >> 6) == 2;
+  const bool ld = prep && q.k == 4 && q.act;  // the prep wave's first half loads
+  uint32_t cx = 0, cy = 0, ct = 0, cz = 0;    // point to prepare next (limb j)
+  uint32_t nx = 0, ny = 0, nt = 0, nz = 0;    // the point after it
+  const uint32_t kk = limb_of_const(kK, q.j);
+  if (ld) {
+    cx = wu_load_limb(pts, 0, q.j);
+    cy = wu_load_limb(pts, 1, q.j);
+    ct = wu_load_limb(pts, 2, q.j);
+    cz = wu_load_limb(pts, 3, q.j);
+    if (count > 1) {
+      const uint32_t* r1 = pts + XYTZ_WORDS;
+      nx = wu_load_limb(r1, 0, q.j);
+      ny = wu_load_limb(r1, 1, q.j);
+      nt = wu_load_limb(r1, 2, q.j);
+      nz = wu_load_limb(r1, 3, q.j);
+    }
+  }
+  unit_sync();  // scratch padding and constants
+  if (prep) {
+    const uint32_t u = wmul2(ld ? ct : 0u, ld ? kk : 0u, s.mul[2]);
+    if (ld) {
+      s.opd[0][q.j] = cx;
+      s.opd[0][16 + q.j] = cy;
+      s.opd[0][32 + q.j] = u;
+      s.opd[0][48 + q.j] = cz;
+    }
+  }
+  unit_sync();
+  for (uint32_t i = 0; i < count; ++i) {
+    if (!prep) {
+      wu_add_u(s, s.opd[i & 1], q);
+    } else {
+      if (i + 1 < count) {
+        cx = nx;
+        cy = ny;
+        ct = nt;
+        cz = nz;
+        if (ld && i + 2 < count) {
+          const uint32_t* r2 = pts + (size_t)(i + 2) * XYTZ_WORDS;
+          nx = wu_load_limb(r2, 0, q.j);
+          ny = wu_load_limb(r2, 1, q.j);
+          nt = wu_load_limb(r2, 2, q.j);
+          nz = wu_load_limb(r2, 3, q.j);
+        }
+        const uint32_t u = wmul2(ld ? ct : 0u, ld ? kk : 0u, s.mul[2]);
+        uint32_t* o = s.opd[(i + 1) & 1];
+        if (ld) {
+          o[q.j] = cx;
+          o[16 + q.j] = cy;
+          o[32 + q.j] = u;
+          o[48 + q.j] = cz;
+        }
+      }
+      unit_sync();  // the two syncs of wu_add_u
+      unit_sync();
+    }
+  }
+  if (threadIdx.x < 64) wu_store_acc(s, out);
 }
 
 // Accumulator a (one lane) sums the prepared points a, a + A, a + 2A, ...
@@ -81,6 +151,8 @@ int msm_padd_chain(const uint32_t* pts_xytz, size_t count, int unit, uint32_t* o
     k_chain_quad<<<1, 64, 0, st>>>(pts_xytz, (uint32_t)count, out_xytz);
   else if (unit == MSM_UNIT_LANE)
     k_chain_lane<<<1, 64, 0, st>>>(pts_xytz, (uint32_t)count, out_xytz);
+  else if (unit == MSM_UNIT_WIDE)
+    k_chain_wide<<<1, 192, 0, st>>>(pts_xytz, (uint32_t)count, out_xytz);
   else
     return MSM_EINVAL;
   HIPCHK(hipGetLastError());

@@ -29,17 +29,34 @@ __global__ void __launch_bounds__(256) k_fe_mul_chain(const uint32_t* __restrict
   st_soa(out, count, 0, i, fe_canon(x));
 }
 
-// one wave per element: the same chain with the lane-parallel product
+// two elements per wave (one per 32-lane half): the same chain with the
+// lane-parallel product
 __global__ void __launch_bounds__(64) k_fe_mul_chain_wide(const uint32_t* __restrict__ a,
                                                           const uint32_t* __restrict__ b,
                                                           uint32_t* __restrict__ out,
                                                           uint32_t count, uint32_t rounds) {
-  const uint32_t e = blockIdx.x;
-  wfe x = wfe_from_words(ld_soa(a, count, 0, e));
-  const wfe y = wfe_from_words(ld_soa(b, count, 0, e));
-  for (uint32_t r = 0; r < rounds; ++r) x = wfe_mul(x, y);
-  const fe w = fe_canon(wfe_to_words(x));
-  if (threadIdx.x == 0) st_soa(out, count, 0, e, w);
+  __shared__ uint32_t scratch[WMUL2_WORDS];
+  __shared__ uint32_t res[32];
+  wmul2_init(scratch);
+  const uint32_t lane = wlane(), h = lane >> 5, jj = lane & 31;
+  const uint32_t e = 2 * blockIdx.x + h;
+  const bool act = jj < 16 && e < count;
+  uint32_t x = 0, y = 0;
+  if (act) {
+    // limb jj of the SoA element e: bits 24 jj .. 24 jj + 23
+    const uint32_t bit = 24u * jj, wi = bit >> 5, sh = bit & 31u;
+    const uint32_t hi = sh > 8u;
+    const uint64_t wa = ((uint64_t)(hi ? a[(size_t)(wi + 1) * count + e] : 0u) << 32) |
+                        a[(size_t)wi * count + e];
+    const uint64_t wb = ((uint64_t)(hi ? b[(size_t)(wi + 1) * count + e] : 0u) << 32) |
+                        b[(size_t)wi * count + e];
+    x = (uint32_t)(wa >> sh) & kLimbMask;
+    y = (uint32_t)(wb >> sh) & kLimbMask;
+  }
+  for (uint32_t r = 0; r < rounds; ++r) x = wmul2(x, y, scratch);
+  if (jj < 16) res[16 * h + jj] = x;
+  wave_lds_sync();
+  if (jj == 0 && e < count) st_soa(out, count, 0, e, fe_canon(words_of_limbs(res + 16 * h)));
 }
 
 }  // namespace
@@ -65,8 +82,8 @@ extern "C" int msm_fe_mul_chain(const uint32_t* a, const uint32_t* b, uint32_t* 
                                                               (uint32_t)rounds);
       break;
     case MSM_MUL_WIDE:
-      k_fe_mul_chain_wide<<<(unsigned)count, 64, 0, st>>>(a, b, out, (uint32_t)count,
-                                                           (uint32_t)rounds);
+      k_fe_mul_chain_wide<<<(unsigned)((count + 1) / 2), 64, 0, st>>>(a, b, out, (uint32_t)count,
+                                                                       (uint32_t)rounds);
       break;
     default:
       return MSM_EINVAL;

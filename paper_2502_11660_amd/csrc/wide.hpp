@@ -1,15 +1,21 @@
-// Wide field elements for latency-bound chains: one wave holds one element
-// as 16 limbs of 24 bits, limb j in lane j (lanes 16..63 hold zero), the
-// same Montgomery representation (R = 2^384 = 2^(16*24)) as the 12-word
-// form, so every lazy-reduction bound of curve.hpp carries over.
+// Wide field elements for latency-bound chains: one field element spread over
+// 16 lanes as 16 limbs of 24 bits (limb j in lane j of its half-wave), in the
+// same Montgomery representation as the 12-word form (R = 2^384 = 2^(16*24)).
 //
-// A lone wave issues about one VALU instruction per 4-10 cycles whatever the
-// dependencies, so a dependent chain of products is as fast as the
-// instruction count of one product.  Spread over lanes, a product takes 16
-// multiply-adds per lane for a*b (one broadcast factor per step, the other
-// shifted one lane per step) and 16 more for the reduction, whose digits
-// m_k = -t_k mod 2^24 (p = 1 mod 2^46) are formed on the scalar unit from
-// the column value read out of lane k.
+// A lone wave issues one VALU instruction every few cycles whatever the
+// dependencies, so a dependent chain of products runs at the instruction
+// count of one product.  Spread over lanes, a product is 16 multiply-adds per
+// lane for a b, 16 for the reduction digits and 16 for adding m p; a wave
+// computes two products at once, one per 32-lane half (columns 0..31 of the
+// half's product in its 32 lanes).  The reduction is separated from the
+// product (no step waits on the previous digit):
+//
+//   T = a b                 m = (T mod R) q mod R  (q = -p^-1 mod R)
+//   U = T + m p = 0 mod R   result = U / R
+//
+// Limbs are lazily normalised: an operand limb may be up to 2^28, values up
+// to 8p; a product comes back with limbs at most 2^24 + 2^6 + 1 and value
+// below a b / R + 1.001 p.
 #pragma once
 #include "field.hpp"
 
@@ -17,120 +23,147 @@ namespace msm {
 
 constexpr uint32_t kLimbMask = 0xffffffu;
 
-struct wfe {
-  uint32_t v;  // this lane's limb (zero above lane 15)
-};
+// 24-bit limbs of p and of q = -p^-1 mod 2^384
+constexpr uint32_t kP24[16] = {0x000001u, 0xc00000u, 0x008508u, 0x300000u, 0x0b5d44u, 0x480017u,
+                               0x2fba09u, 0x1ef362u, 0xf5138fu, 0xd9f300u, 0x3b1a22u, 0x6ca149u,
+                               0x3b05c0u, 0x10eac6u, 0x4617c5u, 0x01ae3au};
+constexpr uint32_t kQ24[16] = {0xffffffu, 0xbfffffu, 0x008508u, 0xa00000u, 0xe94577u, 0xebffd1u,
+                               0x47970du, 0x35ed13u, 0xed7a13u, 0x5b86ccu, 0xec5b24u, 0x806a3cu,
+                               0xf80141u, 0x2e3d22u, 0x5feec8u, 0xbfa520u};
 
 __device__ __forceinline__ uint32_t wlane() { return __lane_id(); }
 
-// lane k's value (the builtin returns a signed int: keep it unsigned)
-__device__ __forceinline__ uint32_t rlane(uint32_t v, int k) {
-  return (uint32_t)__builtin_amdgcn_readlane((int)v, k);
+// shift by one lane towards higher lanes, lane 0 receiving 0 (bound_ctrl)
+__device__ __forceinline__ uint32_t shr1z(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x138, 0xF, 0xF, true);
 }
 
-// DPP wave shift by one lane towards higher lanes (lane 0 receives 0)
-__device__ __forceinline__ uint32_t wave_shr1(uint32_t x) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x138, 0xF, 0xF, false);
+// one carry pass over 64-bit columns / 32-bit limbs: limb & mask plus the
+// carry of the lane below
+__device__ __forceinline__ uint64_t cpass64(uint64_t x) {
+  const uint64_t c = x >> 24;
+  return (x & kLimbMask) +
+         ((uint64_t)shr1z((uint32_t)c) | ((uint64_t)shr1z((uint32_t)(c >> 32)) << 32));
+}
+__device__ __forceinline__ uint32_t cpass32(uint32_t x) { return (x & kLimbMask) + shr1z(x >> 24); }
+
+// order this wave's LDS accesses (cross-lane exchange inside one wave)
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// limb j of the 12-word value w (all lanes read; lanes >= 16 get 0)
-__device__ __forceinline__ wfe wfe_from_words(const fe& w) {
-  const uint32_t j = wlane();
-  const uint32_t bit = 24 * j, wi = bit >> 5, sh = bit & 31;
+// LDS scratch of one wave for wmul2: words 0..63 hold the broadcast operands,
+// then per half 16 zero words followed by the half's 32 shifted-operand words.
+constexpr int WMUL2_WORDS = 160;
+
+// zero the padding of a wmul2 scratch area (once, before its first use; the
+// first wmul2 call orders it)
+__device__ __forceinline__ void wmul2_init(uint32_t* lds) {
+  const uint32_t lane = wlane();
+  if (lane < 16) {
+    lds[64 + lane] = 0u;
+    lds[112 + lane] = 0u;
+  }
+}
+
+// Two Montgomery products per wave: the half h = lane / 32 multiplies its own
+// a and b, given as limbs in lanes 32h + j (j < 16) and zero in lanes
+// 32h + 16 .. 32h + 31; the result comes back in the same layout.  Column j
+// of a product is sum_i a_i b_{j-i}: a_i is an LDS broadcast, b_{j-i} an LDS
+// read at a lane-shifted address (zero below the half's first lane).
+__device__ __forceinline__ uint32_t wmul2(uint32_t a, uint32_t b, uint32_t* lds) {
+  const uint32_t lane = wlane(), h = lane >> 5, jj = lane & 31;
+  const uint32_t* bc = lds + 16 * h;
+  uint32_t* sh = lds + 80 + 48 * h;  // sh[jj - i] reaches the 16 zero words below
+  wave_lds_sync();
+  lds[16 * h + jj + (jj & 16)] = a;  // a of half h at words 16h .. 16h + 15
+  sh[jj] = b;
+  wave_lds_sync();
+  uint32_t av[16], bv[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    av[i] = bc[i];
+    bv[i] = sh[(int)jj - i];
+  }
+  uint64_t col = (uint64_t)av[0] * bv[0];
+#pragma unroll
+  for (int i = 1; i < 16; ++i) col += (uint64_t)av[i] * bv[i];
+  // two passes: limbs below 2^24 + 2^12 (a column holds at most 2^60)
+  const uint32_t t = (uint32_t)cpass64(cpass64(col));
+  // m = (T mod R) q mod R: product columns 0..15 of the low half with q
+  wave_lds_sync();
+  sh[jj] = jj < 16 ? t : 0u;
+  wave_lds_sync();
+#pragma unroll
+  for (int i = 0; i < 16; ++i) bv[i] = sh[(int)jj - i];
+  uint64_t mc = (uint64_t)kQ24[0] * bv[0];
+#pragma unroll
+  for (int i = 1; i < 16; ++i) mc += (uint64_t)kQ24[i] * bv[i];
+  mc = jj < 16 ? mc : 0u;  // mod R (and no carry into the other half)
+  uint32_t m = cpass32((uint32_t)cpass64(mc));  // limbs below 2^24 + 2^6
+  m = jj < 16 ? m : 0u;                          // m < R (1 + 2^-17)
+  // U = T + m p (p_0 = 1)
+  wave_lds_sync();
+  sh[jj] = m;
+  wave_lds_sync();
+#pragma unroll
+  for (int i = 0; i < 16; ++i) bv[i] = sh[(int)jj - i];
+  uint64_t u = (uint64_t)t + bv[0];
+#pragma unroll
+  for (int i = 1; i < 16; ++i) u += (uint64_t)kP24[i] * bv[i];
+  const uint32_t uv = cpass32((uint32_t)cpass64(u));  // limbs below 2^24 + 2^6
+  // The low 16 limbs are 0 mod R and below 2R: all zero, or exactly R (then
+  // one carry into limb 16).
+  const uint64_t nz = __ballot(jj < 16 && uv != 0u);
+  const bool carry = ((h ? (nz >> 32) : nz) & 0xffffu) != 0u;
+  // limbs 16..31 of the half to its lanes 0..15 (swap of 16-lane groups)
+  const uint32_t r = (uint32_t)__builtin_amdgcn_ds_swizzle((int)uv, 0x401F);
+  return jj < 16 ? r + ((jj == 0 && carry) ? 1u : 0u) : 0u;
+}
+
+// limb j (bits 24j .. 24j + 23, j < 16) of a 12-word little-endian value
+__device__ __forceinline__ uint32_t limb_of_words(const uint32_t* __restrict__ w, uint32_t j) {
+  const uint32_t bit = 24u * j, wi = bit >> 5, sh = bit & 31u;
+  const uint32_t lo = w[wi];
+  const uint32_t hi = (sh > 8u) ? w[wi + 1] : 0u;  // sh > 8 implies wi + 1 < 12
+  return (uint32_t)(((((uint64_t)hi) << 32) | lo) >> sh) & kLimbMask;
+}
+
+// limb j of a compile-time constant (selects, no memory)
+__device__ __forceinline__ uint32_t limb_of_const(const uint32_t (&w)[NL], uint32_t j) {
+  const uint32_t bit = 24u * j, wi = bit >> 5, sh = bit & 31u;
   uint32_t lo = 0, hi = 0;
 #pragma unroll
-  for (int i = 0; i < NL; ++i) {
-    lo = ((uint32_t)i == wi) ? w.v[i] : lo;
-    hi = ((uint32_t)i == wi + 1) ? w.v[i] : hi;
+  for (uint32_t i = 0; i < (uint32_t)NL; ++i) {
+    lo = (i == wi) ? w[i] : lo;
+    hi = (i == wi + 1) ? w[i] : hi;
   }
-  const uint64_t two = ((uint64_t)hi << 32) | lo;
-  wfe r;
-  r.v = j < 16 ? (uint32_t)(two >> sh) & kLimbMask : 0u;
-  return r;
+  return (uint32_t)(((((uint64_t)hi) << 32) | lo) >> sh) & kLimbMask;
 }
 
-// Carry-normalise limbs (each pass moves limb >> 24 one lane up).  With
-// limbs below 2^32 three passes leave every limb below 2^24 + 2^9; the top
-// limb keeps what reaches it (the value is below 2^384).
-__device__ __forceinline__ uint32_t wnorm32(uint32_t x) {
-#pragma unroll
-  for (int pass = 0; pass < 3; ++pass) {
-    const uint32_t c = wave_shr1(x >> 24);
-    x = (wlane() < 15 ? (x & kLimbMask) : x) + (wlane() < 16 ? c : 0u);
-    x = wlane() < 16 ? x : 0u;
-  }
-  return x;
-}
-
-// Fully reduced 12-word form of w (< 2^384) for storing: exact carry
-// propagation on the scalar unit, then packing.
-__device__ __forceinline__ fe wfe_to_words(const wfe& w) {
-  uint64_t carry = 0;
-  uint32_t limb[16];
+// 12-word value of 16 lazily normalised limbs (value below 2^384), by an
+// exact carry chain in one lane
+__device__ __forceinline__ fe words_of_limbs(const uint32_t* limbs) {
+  uint32_t n[16];
+  uint64_t c = 0;
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    const uint64_t t = (uint64_t)rlane(w.v, j) + carry;
-    limb[j] = (uint32_t)t & kLimbMask;
-    carry = t >> 24;
+    const uint64_t t = (uint64_t)limbs[j] + c;
+    n[j] = (uint32_t)t & kLimbMask;
+    c = t >> 24;
   }
   fe r;
 #pragma unroll
   for (int i = 0; i < NL; ++i) {
     const int bit = 32 * i, j = bit / 24, sh = bit % 24;
-    uint64_t v = (uint64_t)limb[j] >> sh;
-    if (j + 1 < 16) v |= (uint64_t)limb[j + 1] << (24 - sh);
-    if (j + 2 < 16 && 48 - sh < 32) v |= (uint64_t)limb[j + 2] << (48 - sh);
+    uint64_t v = (uint64_t)n[j] >> sh;
+    if (j + 1 < 16) v |= (uint64_t)n[j + 1] << (24 - sh);
+    if (j + 2 < 16 && 48 - sh < 32) v |= (uint64_t)n[j + 2] << (48 - sh);
     r.v[i] = (uint32_t)v;
   }
   return r;
-}
-
-// Montgomery product a b R^-1 (R = 2^384), lazily reduced (< 2p when
-// a b < R p); limbs of a and b at most 2^27.
-__device__ __forceinline__ wfe wfe_mul(const wfe& a, const wfe& b) {
-  const uint32_t lane = wlane();
-  // columns 0..31 of a*b, column j in lane j: sum_i a_i b_{j-i}
-  uint64_t col = 0;
-  uint32_t bs = b.v;
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const uint32_t ai = rlane(a.v, i);
-    col += (uint64_t)ai * bs;
-    bs = wave_shr1(bs);
-  }
-  // reduction: m_k = -(column k + carry) mod 2^24; column k + j += m_k p_j
-  uint32_t ps = wfe_from_words(fe_const(kP)).v;  // p_j in lane j
-  uint64_t carry = 0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const uint64_t ck = ((uint64_t)rlane((uint32_t)(col >> 32), k) << 32) | rlane((uint32_t)col, k);
-    const uint64_t t = ck + carry;
-    uint32_t m = (0u - (uint32_t)t) & kLimbMask;
-    // opaque to the optimiser: otherwise it treats the product as a 24-bit
-    // multiply, drops the mask, and then emits a full 32-bit multiply-add
-    asm volatile("" : "+s"(m));
-    carry = (t + m) >> 24;
-    col += (uint64_t)m * ps;  // lane k + j gets m p_j (lane k itself is retired)
-    ps = wave_shr1(ps);
-  }
-  // result limbs: columns 16..31 (+ carry into column 16), moved to lanes 0..15
-  const uint32_t lo = (uint32_t)col, hi = (uint32_t)(col >> 32);
-  const uint32_t lo_d = (uint32_t)__builtin_amdgcn_ds_swizzle((int)lo, 0x401F);
-  const uint32_t hi_d = (uint32_t)__builtin_amdgcn_ds_swizzle((int)hi, 0x401F);
-  uint64_t r = lane < 16 ? (((uint64_t)hi_d << 32) | lo_d) : 0u;
-  r += lane == 0 ? carry : 0u;
-  // carry normalisation: two 64-bit passes bring the limbs below 2^32 (the
-  // top limb keeps its carries: the value is below 2^384), then three more
-  uint64_t x = r;
-#pragma unroll
-  for (int pass = 0; pass < 2; ++pass) {
-    const uint64_t c = (uint64_t)wave_shr1((uint32_t)(x >> 24)) |
-                       ((uint64_t)wave_shr1((uint32_t)(x >> 56)) << 32);
-    x = (lane < 15 ? (x & kLimbMask) : x) + (lane < 16 ? c : 0u);
-  }
-  wfe out;
-  out.v = wnorm32(lane < 16 ? (uint32_t)x : 0u);
-  return out;
 }
 
 }  // namespace msm

@@ -29,7 +29,7 @@ def _sum_w(points):
     return acc
 
 
-@pytest.mark.parametrize("unit", [api.MSM_UNIT_QUAD, api.MSM_UNIT_LANE])
+@pytest.mark.parametrize("unit", [api.MSM_UNIT_WIDE, api.MSM_UNIT_QUAD, api.MSM_UNIT_LANE])
 def test_padd_chain_sum_and_edge_chains(oracle_pool, unit):
     ks, pts = oracle_pool
     n = 257
