@@ -14,7 +14,7 @@
 // its dependent depth is only c additions.  Large levels run one addition per
 // lane; small ones use the four-lane quad unit (quad.hpp) to cut latency.
 //
-// Each window then forms S_w by Horner's rule on one quad, and group
+// Each window then forms S_w by Horner's rule on one wide unit, and group
 // aggregation Q = sum_w 2^(w c) S_w is Horner's rule over the windows of a job
 // (c doublings per window), the dependent chain the paper assigns to its
 // low-latency unit: one wide two-wave unit per job (wide_unit.hpp).  The
@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(256) k_tree_level(const uint32_t* __restrict__
     const uint32_t src = (s < h) ? s : h;
     r = padd_full(ld_xytz(L + (size_t)src * XYTZ_WORDS), ld_xytz(R + (size_t)src * XYTZ_WORDS), p2);
   }
-  if (to_u && s <= h) r.T = fe_mul(r.T, fe_const(kK));
+  if (to_u) r.T = fe_mul(r.T, fe_const(kK));
   st_xytz(out + rec_index(w, nodes_out, n, slots_out, s) * XYTZ_WORDS, r);
 }
 
@@ -81,29 +81,49 @@ __global__ void __launch_bounds__(256) k_tree_level_quad(const uint32_t* __restr
     const uint32_t src = (s < h) ? s : h;
     r = quad_add(quad_ld(L + (size_t)src * XYTZ_WORDS), quad_ld(R + (size_t)src * XYTZ_WORDS), p2);
   }
-  if (to_u && s <= h) r = quad_to_u(r);
+  if (to_u) r = quad_to_u(r);
   quad_st(out + rec_index(w, nodes_out, n, slots_out, s) * XYTZ_WORDS, r);
 }
 
-// Per window: S_w = sum_t 2^t X_t (+ S for signed digits), X_t in XYUZ form
-// (slot t < bb of the tree's root), S in XYTZ form (slot bb), by Horner's rule
-// on one quad.  Writes S_w as XYTZ (record 2w) and XYUZ (record 2w + 1).
-__global__ void __launch_bounds__(64) k_window_combine(const uint32_t* __restrict__ root,
-                                                       uint32_t bb, uint32_t w_cnt,
-                                                       int add_total,
-                                                       uint32_t* __restrict__ wsum) {
-  const uint32_t w = (blockIdx.x * blockDim.x + threadIdx.x) >> 2;
-  if (w >= w_cnt) return;
-  const fe p2 = fe_const(kP2);
+// Per window (block w, one wide unit): S_w = sum_t 2^t X_t (+ S for signed
+// digits) by Horner's rule over the bits t, with X_t (slot t < bb of the
+// tree's root) and S (slot bb) in XYUZ form.  Writes S_w as XYTZ (record 2w)
+// and XYUZ (record 2w + 1).  Each lane fetches its limb of the next slot
+// while the current step runs.
+__global__ void __launch_bounds__(128) k_window_combine(const uint32_t* __restrict__ root,
+                                                        uint32_t bb, int add_total,
+                                                        uint32_t* __restrict__ wsum) {
+  __shared__ wunit_lds<2> s;
+  const uint32_t w = blockIdx.x;
+  wunit_init(s);  // accumulator = identity
+  const wslot q = wslot_here();
   const uint32_t* V = root + (size_t)w * (bb + 1) * XYTZ_WORDS;
-  fe acc = quad_identity();
-  for (int t = (int)bb - 1; t >= 0; --t) {
-    if (t + 1 < (int)bb) acc = quad_dbl(acc, p2);
-    acc = quad_add_u(acc, quad_ld(V + (size_t)t * XYTZ_WORDS), p2);
+  limb_src nxt = wu_fetch(V + (size_t)(bb - 1) * XYTZ_WORDS, q.k, q.j);
+  const int steps = (int)bb + (add_total ? 1 : 0);
+  for (int i = 0; i < steps; ++i) {
+    // step i adds slot bb - 1 - i (i < bb) or the total (slot bb)
+    const uint32_t* opd = s.opd[i & 1];
+    if (q.act) s.opd[i & 1][16 * q.k + q.j] = limb_extract(nxt, q.j);
+    const int following = i + 1 < (int)bb ? (int)bb - 2 - i : (int)bb;  // clamped
+    nxt = wu_fetch(V + (size_t)following * XYTZ_WORDS, q.k, q.j);
+    unit_sync();
+    if (i >= 1 && i < (int)bb) wu_dbl(s, q);
+    wu_add_u(s, opd, q);
   }
-  if (add_total) acc = quad_add(acc, quad_ld(V + (size_t)bb * XYTZ_WORDS), p2);
-  quad_st(wsum + (size_t)(2 * w) * XYTZ_WORDS, acc);
-  quad_st(wsum + (size_t)(2 * w + 1) * XYTZ_WORDS, quad_to_u(acc));
+  if (threadIdx.x < 64) {
+    // record 2w: XYTZ; record 2w + 1: XYUZ with U = k T (one more product,
+    // in the first half of wave 0)
+    wu_store_acc(s, wsum + (size_t)(2 * w) * XYTZ_WORDS);
+    const bool h0 = q.k == 0 && q.act;
+    const uint32_t u = wmul2(h0 ? s.acc[32 + q.j] : 0u, h0 ? limb_of_const(kK, q.j) : 0u, s.mul[0]);
+    if (h0) s.prod[32 + q.j] = u;
+    wave_lds_sync();
+    const uint32_t lane = wlane();
+    if (lane < 4) {
+      const uint32_t* src = lane == 2 ? s.prod + 32 : s.acc + 16 * lane;
+      st_aos(wsum + (size_t)(2 * w + 1) * XYTZ_WORDS, (int)lane, words_of_limbs(src));
+    }
+  }
 }
 
 // Group aggregation of job j (block j, one wide unit): Q = sum_w 2^(w c) S_w
@@ -117,14 +137,16 @@ __global__ void __launch_bounds__(128) k_horner_wide(const uint32_t* __restrict_
   wunit_init(s);
   const wslot q = wslot_here();
   const uint32_t* ws = wsum + (size_t)2 * job * W * XYTZ_WORDS;
-  const uint32_t top = wu_load_limb(ws + (size_t)(2 * (W - 1)) * XYTZ_WORDS, q.k, q.j);
-  uint32_t nxt = W >= 2 ? wu_load_limb(ws + (size_t)(2 * W - 3) * XYTZ_WORDS, q.k, q.j) : 0u;
+  const limb_src top = wu_fetch(ws + (size_t)(2 * (W - 1)) * XYTZ_WORDS, q.k, q.j);
+  limb_src nxt = {0u, 0u};
+  if (W >= 2) nxt = wu_fetch(ws + (size_t)(2 * W - 3) * XYTZ_WORDS, q.k, q.j);
   unit_sync();
-  if (q.act) s.acc[16 * q.k + q.j] = top;  // S_{W-1}, XYTZ
+  if (q.act) s.acc[16 * q.k + q.j] = limb_extract(top, q.j);  // S_{W-1}, XYTZ
   unit_sync();
   for (int w = (int)W - 2; w >= 0; --w) {
-    if (q.act) s.opd[0][16 * q.k + q.j] = nxt;  // S_w, XYUZ (read after the doublings)
-    if (w >= 1) nxt = wu_load_limb(ws + (size_t)(2 * w - 1) * XYTZ_WORDS, q.k, q.j);
+    // S_w, XYUZ (read after the doublings); then fetch S_{w-1}
+    if (q.act) s.opd[0][16 * q.k + q.j] = limb_extract(nxt, q.j);
+    if (w >= 1) nxt = wu_fetch(ws + (size_t)(2 * w - 1) * XYTZ_WORDS, q.k, q.j);
     for (uint32_t t = 0; t < c; ++t) wu_dbl(s, q);
     wu_add_u(s, s.opd[0], q);
   }
@@ -174,8 +196,7 @@ int launch_aggregate(const Plan& pl, const uint32_t* buckets, void* ws, hipStrea
     in = out;
     nodes >>= 1;
   }
-  k_window_combine<<<grid_for(4 * (size_t)S, 64), 64, 0, st>>>(
-      in, bb, S, pl.encoding == MSM_DIGITS_UNSIGNED ? 0 : 1, wsum);
+  k_window_combine<<<S, 128, 0, st>>>(in, bb, pl.encoding == MSM_DIGITS_UNSIGNED ? 0 : 1, wsum);
   HIPCHK(hipGetLastError());
   return MSM_OK;
 }

@@ -48,38 +48,30 @@ __global__ void __launch_bounds__(64) k_chain_lane(const uint32_t* __restrict__ 
 
 // The wide unit: waves 0 and 1 run the additions (two phases of four
 // products); wave 2 prepares the next operand (U = k T, one product) while
-// they add the current one, and loads the point after that.
+// they add the current one, and fetches the point after that.
 __global__ void __launch_bounds__(192) k_chain_wide(const uint32_t* __restrict__ pts,
                                                     uint32_t count, uint32_t* __restrict__ out) {
   __shared__ wunit_lds<3> s;
   wunit_init(s);
   const wslot q = wslot_here();
   const bool prep = (threadIdx.x >> 6) == 2;
-  const bool ld = prep && q.k == 4 && q.act;  // the prep wave's first half loads
-  uint32_t cx = 0, cy = 0, ct = 0, cz = 0;    // point to prepare next (limb j)
-  uint32_t nx = 0, ny = 0, nt = 0, nz = 0;    // the point after it
+  const bool ld = prep && q.k == 4 && q.act;  // the prep wave's first half fetches
   const uint32_t kk = limb_of_const(kK, q.j);
-  if (ld) {
-    cx = wu_load_limb(pts, 0, q.j);
-    cy = wu_load_limb(pts, 1, q.j);
-    ct = wu_load_limb(pts, 2, q.j);
-    cz = wu_load_limb(pts, 3, q.j);
-    if (count > 1) {
-      const uint32_t* r1 = pts + XYTZ_WORDS;
-      nx = wu_load_limb(r1, 0, q.j);
-      ny = wu_load_limb(r1, 1, q.j);
-      nt = wu_load_limb(r1, 2, q.j);
-      nz = wu_load_limb(r1, 3, q.j);
-    }
+  limb_src f[4];  // raw words of the point after the one being prepared
+  uint32_t c[4];  // limbs of the point being prepared
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    c[k] = limb_extract(wu_fetch(pts, k, q.j), q.j);
+    f[k] = wu_fetch(pts + (count > 1 ? XYTZ_WORDS : 0), k, q.j);
   }
   unit_sync();  // scratch padding and constants
   if (prep) {
-    const uint32_t u = wmul2(ld ? ct : 0u, ld ? kk : 0u, s.mul[2]);
+    const uint32_t u = wmul2(ld ? c[2] : 0u, ld ? kk : 0u, s.mul[2]);
     if (ld) {
-      s.opd[0][q.j] = cx;
-      s.opd[0][16 + q.j] = cy;
+      s.opd[0][q.j] = c[0];
+      s.opd[0][16 + q.j] = c[1];
       s.opd[0][32 + q.j] = u;
-      s.opd[0][48 + q.j] = cz;
+      s.opd[0][48 + q.j] = c[3];
     }
   }
   unit_sync();
@@ -87,26 +79,21 @@ __global__ void __launch_bounds__(192) k_chain_wide(const uint32_t* __restrict__
     if (!prep) {
       wu_add_u(s, s.opd[i & 1], q);
     } else {
-      if (i + 1 < count) {
-        cx = nx;
-        cy = ny;
-        ct = nt;
-        cz = nz;
-        if (ld && i + 2 < count) {
-          const uint32_t* r2 = pts + (size_t)(i + 2) * XYTZ_WORDS;
-          nx = wu_load_limb(r2, 0, q.j);
-          ny = wu_load_limb(r2, 1, q.j);
-          nt = wu_load_limb(r2, 2, q.j);
-          nz = wu_load_limb(r2, 3, q.j);
-        }
-        const uint32_t u = wmul2(ld ? ct : 0u, ld ? kk : 0u, s.mul[2]);
-        uint32_t* o = s.opd[(i + 1) & 1];
-        if (ld) {
-          o[q.j] = cx;
-          o[16 + q.j] = cy;
-          o[32 + q.j] = u;
-          o[48 + q.j] = cz;
-        }
+      // Unconditional and clamped (past the end it prepares a slot nobody
+      // reads): a conditional fetch would make the compiler copy the fresh
+      // registers at the merge and wait for the loads there.
+#pragma unroll
+      for (int k = 0; k < 4; ++k) c[k] = limb_extract(f[k], q.j);  // point i + 1
+      const uint32_t nx = i + 2 < count ? i + 2 : count - 1;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) f[k] = wu_fetch(pts + (size_t)nx * XYTZ_WORDS, k, q.j);
+      const uint32_t u = wmul2(ld ? c[2] : 0u, ld ? kk : 0u, s.mul[2]);
+      uint32_t* o = s.opd[(i + 1) & 1];
+      if (ld) {
+        o[q.j] = c[0];
+        o[16 + q.j] = c[1];
+        o[32 + q.j] = u;
+        o[48 + q.j] = c[3];
       }
       unit_sync();  // the two syncs of wu_add_u
       unit_sync();

@@ -70,10 +70,11 @@ __device__ __forceinline__ void wmul2_init(uint32_t* lds) {
 
 // Two Montgomery products per wave: the half h = lane / 32 multiplies its own
 // a and b, given as limbs in lanes 32h + j (j < 16) and zero in lanes
-// 32h + 16 .. 32h + 31; the result comes back in the same layout.  Column j
-// of a product is sum_i a_i b_{j-i}: a_i is an LDS broadcast, b_{j-i} an LDS
-// read at a lane-shifted address (zero below the half's first lane).
-__device__ __forceinline__ uint32_t wmul2(uint32_t a, uint32_t b, uint32_t* lds) {
+// 32h + 16 .. 32h + 31.  Limb j of the result comes back in lane 32h + 16 + j
+// (zero in the half's lower 16 lanes).  Column j of a product is
+// sum_i a_i b_{j-i}: a_i is an LDS broadcast, b_{j-i} an LDS read at a
+// lane-shifted address (zero below the half's first lane).
+__device__ __forceinline__ uint32_t wmul2_hi(uint32_t a, uint32_t b, uint32_t* lds) {
   const uint32_t lane = wlane(), h = lane >> 5, jj = lane & 31;
   const uint32_t* bc = lds + 16 * h;
   uint32_t* sh = lds + 80 + 48 * h;  // sh[jj - i] reaches the 16 zero words below
@@ -118,17 +119,34 @@ __device__ __forceinline__ uint32_t wmul2(uint32_t a, uint32_t b, uint32_t* lds)
   // one carry into limb 16).
   const uint64_t nz = __ballot(jj < 16 && uv != 0u);
   const bool carry = ((h ? (nz >> 32) : nz) & 0xffffu) != 0u;
-  // limbs 16..31 of the half to its lanes 0..15 (swap of 16-lane groups)
-  const uint32_t r = (uint32_t)__builtin_amdgcn_ds_swizzle((int)uv, 0x401F);
-  return jj < 16 ? r + ((jj == 0 && carry) ? 1u : 0u) : 0u;
+  return jj >= 16 ? uv + ((jj == 16 && carry) ? 1u : 0u) : 0u;
 }
 
-// limb j (bits 24j .. 24j + 23, j < 16) of a 12-word little-endian value
-__device__ __forceinline__ uint32_t limb_of_words(const uint32_t* __restrict__ w, uint32_t j) {
-  const uint32_t bit = 24u * j, wi = bit >> 5, sh = bit & 31u;
-  const uint32_t lo = w[wi];
-  const uint32_t hi = (sh > 8u) ? w[wi + 1] : 0u;  // sh > 8 implies wi + 1 < 12
-  return (uint32_t)(((((uint64_t)hi) << 32) | lo) >> sh) & kLimbMask;
+// wmul2_hi with the result moved to the operand layout (lanes 32h + j)
+__device__ __forceinline__ uint32_t wmul2(uint32_t a, uint32_t b, uint32_t* lds) {
+  const uint32_t v = wmul2_hi(a, b, lds);
+  // swap of the 16-lane groups within each 32 lanes
+  const uint32_t r = (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);
+  return (wlane() & 31u) < 16u ? r : 0u;
+}
+
+// The two words that hold limb j (bits 24j .. 24j + 23, j < 16) of a
+// 12-word little-endian value, fetched without using them (so that a
+// prefetch is not waited for until limb_extract); both loads stay inside the
+// 12 words.
+struct limb_src {
+  uint32_t lo, hi;
+};
+__device__ __forceinline__ limb_src limb_fetch(const uint32_t* __restrict__ w, uint32_t j) {
+  const uint32_t wi = (24u * j) >> 5;
+  limb_src r;
+  r.lo = w[wi];
+  r.hi = w[wi + 1 < (uint32_t)NL ? wi + 1 : (uint32_t)NL - 1];  // unused when the limb fits in lo
+  return r;
+}
+__device__ __forceinline__ uint32_t limb_extract(const limb_src& s, uint32_t j) {
+  const uint32_t sh = (24u * j) & 31u;
+  return (uint32_t)(((((uint64_t)s.hi) << 32) | s.lo) >> sh) & kLimbMask;
 }
 
 // limb j of a compile-time constant (selects, no memory)

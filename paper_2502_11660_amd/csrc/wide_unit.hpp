@@ -39,7 +39,8 @@ struct wunit_lds {
 // this lane's place in the unit: product k = 2 wave + half, limb j
 struct wslot {
   uint32_t k, j;
-  bool act;  // limb lanes (the upper 16 lanes of each half carry zeros)
+  bool act;  // operand limb lanes (the lower 16 of each half; the upper 16
+             // carry zero operands and receive the product's limbs)
 };
 
 __device__ __forceinline__ wslot wslot_here() {
@@ -84,8 +85,8 @@ __device__ __forceinline__ void wu_products_out(wunit_lds<WAVES>& s, const wslot
   uint32_t r = q.k == 0 ? F : (q.k == 3 ? G : H);
   l = q.act ? l : 0u;
   r = q.act ? r : 0u;
-  const uint32_t v = wmul2(l, r, s.mul[threadIdx.x >> 6]);
-  if (q.act) s.acc[16 * q.k + q.j] = v;
+  const uint32_t v = wmul2_hi(l, r, s.mul[threadIdx.x >> 6]);
+  if (!q.act) s.acc[16 * q.k + q.j] = v;  // result limb j sits in lane 16 + j
 }
 
 // acc + opd (X2, Y2, U2 = k T2, Z2; coordinates below 2p): two phases.
@@ -101,9 +102,9 @@ __device__ __forceinline__ void wu_add_u(wunit_lds<WAVES>& s, const uint32_t* op
     uint32_t r = q.k == 0 ? (y2 + c) - x2 : (q.k == 1 ? y2 + x2 : o2);
     l = q.act ? l : 0u;
     r = q.act ? r : 0u;
-    uint32_t v = wmul2(l, r, s.mul[threadIdx.x >> 6]);  // A, B, C = T1 U2, Z1 Z2
-    if (q.k == 3) v <<= 1;                             // D = 2 Z1 Z2
-    if (q.act) s.prod[16 * q.k + q.j] = v;
+    uint32_t v = wmul2_hi(l, r, s.mul[threadIdx.x >> 6]);  // A, B, C = T1 U2, Z1 Z2
+    if (q.k == 3) v <<= 1;                                // D = 2 Z1 Z2
+    if (!q.act) s.prod[16 * q.k + q.j] = v;
   }
   unit_sync();
   {
@@ -121,9 +122,9 @@ __device__ __forceinline__ void wu_dbl(wunit_lds<WAVES>& s, const wslot& q) {
     const uint32_t x = s.acc[q.j], y = s.acc[16 + q.j], o = s.acc[16 * q.k + q.j];
     uint32_t l = q.k == 2 ? x + y : o;  // X, Y, X + Y, Z
     l = q.act ? l : 0u;
-    uint32_t v = wmul2(l, l, s.mul[threadIdx.x >> 6]);  // A, B, S, Z^2
-    if (q.k == 3) v <<= 1;                             // 2 Z^2
-    if (q.act) s.prod[16 * q.k + q.j] = v;
+    uint32_t v = wmul2_hi(l, l, s.mul[threadIdx.x >> 6]);  // A, B, S, Z^2
+    if (q.k == 3) v <<= 1;                                // 2 Z^2
+    if (!q.act) s.prod[16 * q.k + q.j] = v;
   }
   unit_sync();
   {
@@ -136,11 +137,11 @@ __device__ __forceinline__ void wu_dbl(wunit_lds<WAVES>& s, const wslot& q) {
   unit_sync();
 }
 
-// this lane's limb of coordinate `coord` of an AoS record (12 words per
-// coordinate)
-__device__ __forceinline__ uint32_t wu_load_limb(const uint32_t* __restrict__ rec, uint32_t coord,
-                                                 uint32_t j) {
-  return limb_of_words(rec + coord * NL, j);
+// the words of this lane's limb of coordinate `coord` of an AoS record (12
+// words per coordinate)
+__device__ __forceinline__ limb_src wu_fetch(const uint32_t* __restrict__ rec, uint32_t coord,
+                                             uint32_t j) {
+  return limb_fetch(rec + coord * NL, j);
 }
 
 // store the accumulator as one AoS XYTZ record (lanes 0..3 of the calling
