@@ -146,30 +146,6 @@ __global__ void __launch_bounds__(SORT_THREADS) k_part_count(SortGeom g, uint32_
     counts[count_index(g, t.d, t.w, b, t.tile)] = hist[b];
 }
 
-// pass 1b: scatter into (partition, tile) ranges; tmp entry = {idx | sign, key}
-__global__ void __launch_bounds__(SORT_THREADS) k_part_scatter(SortGeom g, uint32_t off,
-                                                               const uint32_t* __restrict__ digits,
-                                                               const uint32_t* __restrict__ scanned,
-                                                               uint2* __restrict__ tmp) {
-  __shared__ uint32_t cur[1u << 12];
-  const TileRef t = tile_ref(g, blockIdx.x);
-  const uint32_t H = 1u << g.hi_bits;
-  for (uint32_t b = threadIdx.x; b < H; b += SORT_THREADS)
-    cur[b] = scanned[count_index(g, t.d, t.w, b, t.tile)];
-  __syncthreads();
-  const uint32_t e0 = t.tile * TILE, e1 = min(e0 + TILE, t.d.n);
-  const uint32_t* dg = digits + (size_t)g.W * t.d.pt_off + (size_t)t.w * t.d.n;
-  const uint32_t keybase = (t.j * g.W + t.w) << g.bb;
-  for (uint32_t e = e0 + threadIdx.x; e < e1; e += SORT_THREADS) {
-    const uint32_t q = dg[e];
-    if (q) {
-      const uint32_t m = bucket_of(q, off);
-      const uint32_t pos = atomicAdd(&cur[m >> g.lo_bits], 1u);
-      tmp[pos] = make_uint2(e | (q & 0x80000000u), keybase + m);
-    }
-  }
-}
-
 // block-wide exclusive scan of the first L (<= 256) entries of v, in place;
 // all SORT_THREADS threads must call it
 __device__ void lds_exclusive_scan256(uint32_t* v, uint32_t L) {
@@ -188,12 +164,89 @@ __device__ void lds_exclusive_scan256(uint32_t* v, uint32_t L) {
   __syncthreads();
 }
 
-// pass 2: one block per partition (segment s, high bits hi)
+// block-wide exclusive scan of v[0..n) (n <= 16 SORT_THREADS) in place;
+// returns the total; all SORT_THREADS threads must call it
+__device__ uint32_t lds_exclusive_scan(uint32_t* v, uint32_t n) {
+  __shared__ uint32_t sums[SORT_THREADS];
+  __shared__ uint32_t total;
+  const uint32_t per = (n + SORT_THREADS - 1) / SORT_THREADS;
+  const uint32_t b0 = min(threadIdx.x * per, n), b1 = min(b0 + per, n);
+  uint32_t sum = 0;
+  for (uint32_t i = b0; i < b1; ++i) sum += v[i];
+  sums[threadIdx.x] = sum;
+  __syncthreads();
+  lds_exclusive_scan256(sums, SORT_THREADS);
+  uint32_t run = sums[threadIdx.x];
+  if (threadIdx.x == SORT_THREADS - 1) total = run + sum;
+  for (uint32_t i = b0; i < b1; ++i) {
+    const uint32_t x = v[i];
+    v[i] = run;
+    run += x;
+  }
+  __syncthreads();
+  return total;
+}
+
+// pass 1b: scatter into (partition, tile) ranges; tmp entry = {idx | sign, key}.
+// The tile is first ordered by partition in LDS, so that consecutive threads
+// write consecutive entries of each partition's range.
+constexpr uint32_t PER_THREAD = TILE / SORT_THREADS;
+__global__ void __launch_bounds__(SORT_THREADS) k_part_scatter(SortGeom g, uint32_t off,
+                                                               const uint32_t* __restrict__ digits,
+                                                               const uint32_t* __restrict__ scanned,
+                                                               uint2* __restrict__ tmp) {
+  __shared__ uint32_t gstart[1u << 12];  // global start of (partition, this tile)
+  __shared__ uint32_t lstart[1u << 12];  // counts, then local starts in the tile
+  __shared__ uint2 stage[TILE];
+  const TileRef t = tile_ref(g, blockIdx.x);
+  const uint32_t H = 1u << g.hi_bits;
+  for (uint32_t b = threadIdx.x; b < H; b += SORT_THREADS) {
+    gstart[b] = scanned[count_index(g, t.d, t.w, b, t.tile)];
+    lstart[b] = 0;
+  }
+  __syncthreads();
+  const uint32_t e0 = t.tile * TILE, e1 = min(e0 + TILE, t.d.n);
+  const uint32_t* dg = digits + (size_t)g.W * t.d.pt_off + (size_t)t.w * t.d.n;
+  const uint32_t keybase = (t.j * g.W + t.w) << g.bb;
+  uint32_t part[PER_THREAD], rank[PER_THREAD];
+  uint2 ent[PER_THREAD];
+#pragma unroll
+  for (uint32_t r = 0; r < PER_THREAD; ++r) {
+    const uint32_t e = e0 + r * SORT_THREADS + threadIdx.x;
+    const uint32_t q = e < e1 ? dg[e] : 0u;
+    part[r] = H;  // no entry
+    rank[r] = 0;
+    ent[r] = make_uint2(0u, 0u);
+    if (q) {
+      const uint32_t m = bucket_of(q, off);
+      part[r] = m >> g.lo_bits;
+      rank[r] = atomicAdd(&lstart[part[r]], 1u);
+      ent[r] = make_uint2(e | (q & 0x80000000u), keybase + m);
+    }
+  }
+  __syncthreads();
+  const uint32_t count = lds_exclusive_scan(lstart, H);
+#pragma unroll
+  for (uint32_t r = 0; r < PER_THREAD; ++r)
+    if (part[r] < H) stage[lstart[part[r]] + rank[r]] = ent[r];
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < count; k += SORT_THREADS) {
+    const uint2 en = stage[k];
+    const uint32_t pr = (en.y - keybase) >> g.lo_bits;
+    tmp[gstart[pr] + (k - lstart[pr])] = en;
+  }
+}
+
+// pass 2: one block per partition (segment s, high bits hi).  A staged
+// partition is ranked in LDS (a permutation into bucket order) and written
+// out linearly; a larger one is streamed from tmp twice.
 __global__ void __launch_bounds__(SORT_THREADS) k_part_sort(
     SortGeom g, const uint32_t* __restrict__ scanned, const uint32_t* __restrict__ total_p,
     size_t ncounts, const uint2* __restrict__ tmp, uint32_t* __restrict__ key,
     uint32_t* __restrict__ idx, uint32_t* __restrict__ offsets, uint32_t* __restrict__ buckets) {
-  __shared__ uint2 ent[PART_CAP];
+  __shared__ uint32_t ent_idx[PART_CAP];  // index words of the staged entries
+  __shared__ uint8_t ent_lo[PART_CAP];    // their low bucket bits
+  __shared__ uint16_t perm[PART_CAP];     // position in bucket order -> entry
   __shared__ uint32_t hist[256], cur[256];
   const uint32_t H = 1u << g.hi_bits, L = 1u << g.lo_bits;
   const uint32_t p = blockIdx.x, s = p >> g.hi_bits, hi = p & (H - 1);
@@ -210,9 +263,13 @@ __global__ void __launch_bounds__(SORT_THREADS) k_part_sort(
   if (threadIdx.x < 256) hist[threadIdx.x] = 0;
   __syncthreads();
   for (uint32_t k = threadIdx.x; k < size; k += SORT_THREADS) {
-    uint2 e = tmp[start + k];
-    if (staged) ent[k] = e;
-    atomicAdd(&hist[e.y & (L - 1)], 1u);
+    const uint2 e = tmp[start + k];
+    const uint32_t lo = e.y & (L - 1);
+    if (staged) {
+      ent_idx[k] = e.x;
+      ent_lo[k] = (uint8_t)lo;
+    }
+    atomicAdd(&hist[lo], 1u);
   }
   __syncthreads();
   for (uint32_t lo = threadIdx.x; lo < L; lo += SORT_THREADS) cur[lo] = hist[lo];
@@ -227,11 +284,22 @@ __global__ void __launch_bounds__(SORT_THREADS) k_part_sort(
   }
   if (p == 0 && threadIdx.x == 0) offsets[g.S << g.bb] = total;
   __syncthreads();
-  for (uint32_t k = threadIdx.x; k < size; k += SORT_THREADS) {
-    uint2 e = staged ? ent[k] : tmp[start + k];
-    uint32_t pos = start + atomicAdd(&cur[e.y & (L - 1)], 1u);
-    key[pos] = e.y;
-    idx[pos] = e.x;
+  if (staged) {
+    for (uint32_t k = threadIdx.x; k < size; k += SORT_THREADS)
+      perm[atomicAdd(&cur[ent_lo[k]], 1u)] = (uint16_t)k;
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < size; q += SORT_THREADS) {
+      const uint32_t k = perm[q];
+      key[start + q] = bucket0 + ent_lo[k];
+      idx[start + q] = ent_idx[k];
+    }
+  } else {
+    for (uint32_t k = threadIdx.x; k < size; k += SORT_THREADS) {
+      const uint2 e = tmp[start + k];
+      const uint32_t pos = start + atomicAdd(&cur[e.y & (L - 1)], 1u);
+      key[pos] = e.y;
+      idx[pos] = e.x;
+    }
   }
 }
 
