@@ -100,7 +100,9 @@ __device__ __forceinline__ bool tail_of(const uint32_t* __restrict__ key,
 
 // Split buckets: one lane sums tail + heads when the span is at most
 // SMALL_SPAN chunks; longer spans (skewed inputs) are appended to a work list
-// for k_merge_long.
+// for k_merge_long.  The block's tasks are packed in LDS first (span 1 at
+// the front, longer spans at the back), so that a wave runs one kind and
+// wholly idle waves leave at once.
 __global__ void __launch_bounds__(256) k_merge_small(const uint32_t* __restrict__ key,
                                                      const uint32_t* __restrict__ offsets,
                                                      uint32_t M, uint32_t K,
@@ -108,21 +110,35 @@ __global__ void __launch_bounds__(256) k_merge_small(const uint32_t* __restrict_
                                                      const uint32_t* __restrict__ tail,
                                                      uint32_t* __restrict__ buckets,
                                                      uint32_t* __restrict__ longlist) {
+  __shared__ uint32_t task[256];
+  __shared__ uint32_t cnt[2];
+  const uint32_t tid = threadIdx.x;
+  if (tid < 2) cnt[tid] = 0;
+  __syncthreads();
   const uint32_t E1 = offsets[M];
-  const uint32_t ch = blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t b, c1;
-  if (!tail_of(key, offsets, E1, K, ch, b, c1)) return;
-  const uint32_t span = c1 - ch;
-  if (span > SMALL_SPAN) {
+  const uint32_t ch = blockIdx.x * blockDim.x + tid;
+  uint32_t b = 0, c1 = 0;
+  const bool has = tail_of(key, offsets, E1, K, ch, b, c1);
+  const uint32_t span = has ? c1 - ch : 0u;
+  if (has && span > SMALL_SPAN) {
     const uint32_t slot = atomicAdd(&longlist[0], 1u);
     longlist[1 + slot] = ch;
-    return;
+  } else if (has && span == 1) {
+    task[atomicAdd(&cnt[0], 1u)] = ch;
+  } else if (has) {
+    task[255 - atomicAdd(&cnt[1], 1u)] = ch;
   }
+  __syncthreads();
+  const uint32_t n1 = cnt[0], n2 = cnt[1];
+  if (!(tid < n1 || tid >= 256 - n2)) return;
+  const uint32_t c = task[tid];
+  const uint32_t bk = key[(c + 1) * K - 1];  // the tail's bucket ends after chunk c
+  const uint32_t sp = (offsets[bk + 1] - 1) / K - c;
   const fe p2 = fe_const(kP2);
-  xytz acc = ld_xytz(tail + (size_t)ch * XYTZ_WORDS);
-  for (uint32_t j = 1; j <= span; ++j)
-    acc = padd_full(acc, ld_xytz(head + (size_t)(ch + j) * XYTZ_WORDS), p2);
-  st_xytz(buckets + (size_t)b * XYTZ_WORDS, acc);
+  xytz acc = ld_xytz(tail + (size_t)c * XYTZ_WORDS);
+  for (uint32_t j = 1; j <= sp; ++j)
+    acc = padd_full(acc, ld_xytz(head + (size_t)(c + j) * XYTZ_WORDS), p2);
+  st_xytz(buckets + (size_t)bk * XYTZ_WORDS, acc);
 }
 
 // Long split buckets, one block each: the block's threads sum strided heads

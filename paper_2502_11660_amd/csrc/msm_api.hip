@@ -99,6 +99,19 @@ int default_window(size_t n) {
   return best;
 }
 
+// compute units of the current device (256 on MI355X; also the answer when
+// no device is visible, e.g. for workspace queries on a host without GPU)
+static int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0) {
+    (void)hipGetLastError();
+    return 256;
+  }
+  return cus;
+}
+
 bool make_plan(const size_t* ns, uint32_t J, int c_req, int encoding, Plan& pl) {
   pl = Plan();
   const int W = num_windows(c_req, encoding);
@@ -133,10 +146,12 @@ bool make_plan(const size_t* ns, uint32_t J, int c_req, int encoding, Plan& pl) 
     pl.one.n = (uint32_t)(mult * ns[0]);
     pl.one.tps = (uint32_t)((mult * ns[0] + SORT_TILE - 1) / SORT_TILE);
   }
-  // accumulation chunk: the launch keeps about 2 waves per SIMD busy
-  // (256 CUs x 4 SIMDs x 2 waves x 64 lanes = 131072 lanes), K in [16, 64]
-  pl.K = 16;
-  while (pl.K < 64 && pl.NW / (2 * pl.K) >= 131072) pl.K *= 2;
+  // accumulation chunk: as many lanes as k_accum keeps resident in one
+  // round (CUs x 4 SIMDs x 3 waves x 64 lanes; its register use allows 3
+  // waves per SIMD), so that every lane runs exactly once and no second,
+  // mostly idle round follows; at least 16 entries per chunk
+  const size_t lanes = (size_t)device_cus() * 4 * 3 * 64;
+  pl.K = (uint32_t)std::max<size_t>(16, (pl.NW + lanes - 1) / lanes);
   pl.chunks = (pl.NW + pl.K - 1) / pl.K;
   size_t o = 0;
   auto take = [&](size_t bytes) {
