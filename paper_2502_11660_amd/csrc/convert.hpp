@@ -145,7 +145,16 @@ __device__ __forceinline__ fe comb_shift_mod(const fe& x, const fe& y, int64_t f
   return borrow ? q : d;
 }
 
-// Plain modular inverse y^-1 mod p of a canonical y (0 for y = 0).
+// lane 0's value of x (for values that are the same in every lane)
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+  return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(x >> 32)) << 32) |
+         (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+}
+
+// Plain modular inverse y^-1 mod p of a canonical y (0 for y = 0).  UNIFORM:
+// y is the same in every lane of the wave, and the 31 divsteps of each round
+// then run on the scalar unit.
+template <bool UNIFORM = false>
 __device__ __noinline__ fe fe_inv_plain(const fe& y) {
   fe a = y, b = fe_const(kP), u = fe_zero(), v = fe_zero();
   u.v[0] = 1u;
@@ -155,6 +164,10 @@ __device__ __noinline__ fe fe_inv_plain(const fe& y) {
     const uint64_t lo31 = 0x7fffffffull;
     uint64_t ab = (a.v[0] & lo31) | ((bits_at(a, n - 33) & 0x1ffffffffull) << 31);
     uint64_t bb = (b.v[0] & lo31) | ((bits_at(b, n - 33) & 0x1ffffffffull) << 31);
+    if constexpr (UNIFORM) {
+      ab = uniform64(ab);
+      bb = uniform64(bb);
+    }
     int64_t f0 = 1, g0 = 0, f1 = 0, g1 = 1;
     for (int j = 0; j < 31; ++j) {
       const bool odd = (ab & 1u) != 0;
@@ -192,13 +205,15 @@ __device__ __noinline__ fe fe_inv_plain(const fe& y) {
 
 // Inverse in Montgomery form: (aR)^-1 R^3 R^-1 = a^-1 R.  Input any value < 2p
 // representing aR; output canonical.
+template <bool UNIFORM = false>
 __device__ __forceinline__ fe fe_inv_mont(const fe& am) {
-  fe inv = fe_inv_plain(fe_canon(am));
+  fe inv = fe_inv_plain<UNIFORM>(fe_canon(am));
   return fe_canon(fe_mul(inv, fe_const(kR3)));
 }
 
 // Twisted-Edwards extended (Montgomery form) -> Weierstrass affine, ordinary
 // form, canonical.  Returns false for the identity (x = y = 0 written).
+template <bool UNIFORM = false>
 __device__ __forceinline__ bool te_to_weierstrass(const xytz& q, fe& xw, fe& yw) {
   fe X = fe_canon(q.X);
   if (fe_is_zero_canon(X)) {
@@ -209,7 +224,7 @@ __device__ __forceinline__ bool te_to_weierstrass(const xytz& q, fe& xw, fe& yw)
   const fe p2 = fe_const(kP2);
   fe zpy = fe_add(q.Z, q.Y);           // Z + Y
   fe zmy = fe_sub_plus(q.Z, q.Y, p2);  // Z - Y
-  fe inv = fe_inv_mont(fe_mul(zmy, q.X));
+  fe inv = fe_inv_mont<UNIFORM>(fe_mul(zmy, q.X));
   fe u = fe_mul(fe_mul(zpy, q.X), inv);  // (Z + Y) / (Z - Y)
   fe v = fe_mul(fe_mul(zpy, q.Z), inv);  // u / x_e
   fe au = fe_mul(u, fe_const(kAlpha));

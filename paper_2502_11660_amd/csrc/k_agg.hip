@@ -34,29 +34,32 @@ __device__ __forceinline__ size_t rec_index(uint32_t w, uint32_t nodes, uint32_t
   return ((size_t)w * nodes + n) * slots + s;
 }
 
-// One level h -> h+1, one output record per lane.
+// One level h -> h+1, one addition per lane: addition a < h forms slot a,
+// addition h the total (slot h + 1); the lane of addition 0 also copies
+// slot h (= R.S), so that no lane of a wave idles through another's addition.
 __global__ void __launch_bounds__(256) k_tree_level(const uint32_t* __restrict__ in, uint32_t h,
                                                     uint32_t nodes_in, uint32_t w_lo,
                                                     uint32_t w_cnt, uint32_t* __restrict__ out,
                                                     int to_u) {
   const uint32_t nodes_out = nodes_in >> 1, slots_in = h + 1, slots_out = h + 2;
   const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= (uint64_t)w_cnt * nodes_out * slots_out) return;
-  const uint32_t s = (uint32_t)(g % slots_out);
-  const uint32_t t = (uint32_t)(g / slots_out);
+  if (g >= (uint64_t)w_cnt * nodes_out * slots_in) return;
+  const uint32_t a = (uint32_t)(g % slots_in);
+  const uint32_t t = (uint32_t)(g / slots_in);
   const uint32_t n = t % nodes_out, w = w_lo + t / nodes_out;
   const uint32_t* L = in + rec_index(w, nodes_in, 2 * n, slots_in, 0) * XYTZ_WORDS;
   const uint32_t* R = L + (size_t)slots_in * XYTZ_WORDS;
+  uint32_t* O = out + rec_index(w, nodes_out, n, slots_out, 0) * XYTZ_WORDS;
   const fe p2 = fe_const(kP2);
-  xytz r;
-  if (s == h) {
-    r = ld_xytz(R + (size_t)h * XYTZ_WORDS);
-  } else {
-    const uint32_t src = (s < h) ? s : h;
-    r = padd_full(ld_xytz(L + (size_t)src * XYTZ_WORDS), ld_xytz(R + (size_t)src * XYTZ_WORDS), p2);
+  if (a == 0) {
+    xytz c = ld_xytz(R + (size_t)h * XYTZ_WORDS);
+    if (to_u) c.T = fe_mul(c.T, fe_const(kK));
+    st_xytz(O + (size_t)h * XYTZ_WORDS, c);
   }
+  const uint32_t s = a < h ? a : h + 1;  // output slot
+  xytz r = padd_full(ld_xytz(L + (size_t)a * XYTZ_WORDS), ld_xytz(R + (size_t)a * XYTZ_WORDS), p2);
   if (to_u) r.T = fe_mul(r.T, fe_const(kK));
-  st_xytz(out + rec_index(w, nodes_out, n, slots_out, s) * XYTZ_WORDS, r);
+  st_xytz(O + (size_t)s * XYTZ_WORDS, r);
 }
 
 // Same level, four lanes per output record.
@@ -153,15 +156,17 @@ __global__ void __launch_bounds__(128) k_horner_wide(const uint32_t* __restrict_
   if (threadIdx.x < 64) wu_store_acc(s, qstate + (size_t)job * XYTZ_WORDS);
 }
 
-// The affine Weierstrass result of each job, one lane per job.
+// The affine Weierstrass result of each job, one wave per job (all lanes
+// compute the same values, so the inversion's divsteps run on the scalar
+// unit; lane 0 writes).
 __global__ void __launch_bounds__(64) k_finalize(const uint32_t* __restrict__ qstate, JobView jv,
                                                  const uint32_t* __restrict__ flags) {
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= jv.J) return;
+  const uint32_t j = blockIdx.x;
   uint32_t* result = jv.get(j).result;
   xytz Q = ld_xytz(qstate + (size_t)j * XYTZ_WORDS);
   fe xw, yw;
-  bool fin = te_to_weierstrass(Q, xw, yw);
+  bool fin = te_to_weierstrass<true>(Q, xw, yw);
+  if (threadIdx.x != 0) return;
 #pragma unroll
   for (int l = 0; l < NL; ++l) {
     result[l] = xw.v[l];
@@ -188,8 +193,9 @@ int launch_aggregate(const Plan& pl, const uint32_t* buckets, void* ws, hipStrea
     uint32_t* out = lv[h & 1];
     const uint64_t outs = (uint64_t)S * (nodes >> 1) * (h + 2);
     const int to_u = (h + 1 == bb) ? 1 : 0;
+    const uint64_t adds = (uint64_t)S * (nodes >> 1) * (h + 1);
     if (outs >= QUAD_BELOW)
-      k_tree_level<<<(unsigned)((outs + 255) / 256), 256, 0, st>>>(in, h, nodes, 0, S, out, to_u);
+      k_tree_level<<<(unsigned)((adds + 255) / 256), 256, 0, st>>>(in, h, nodes, 0, S, out, to_u);
     else
       k_tree_level_quad<<<(unsigned)((4 * outs + 255) / 256), 256, 0, st>>>(in, h, nodes, 0, S,
                                                                            out, to_u);
@@ -207,7 +213,7 @@ int launch_horner(const Plan& pl, void* ws, hipStream_t st) {
   uint32_t* qstate = ws_at<uint32_t>(ws, pl.o_qstate);
   k_horner_wide<<<(unsigned)pl.J, 128, 0, st>>>(ws_at<uint32_t>(ws, pl.o_wsum), (uint32_t)pl.W,
                                                  (uint32_t)pl.c, qstate);
-  k_finalize<<<grid_for(pl.J, 64), 64, 0, st>>>(qstate, jv, ws_at<uint32_t>(ws, pl.o_flags));
+  k_finalize<<<(unsigned)pl.J, 64, 0, st>>>(qstate, jv, ws_at<uint32_t>(ws, pl.o_flags));
   HIPCHK(hipGetLastError());
   return MSM_OK;
 }
