@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(64) k_finalize(const uint32_t* __restrict__ qs
 }
 
 // below this many outputs a tree level runs on quads
-constexpr uint64_t QUAD_BELOW = 16384;
+constexpr uint64_t QUAD_BELOW = 65536;
 
 }  // namespace
 
