@@ -38,6 +38,13 @@ MULS_MIXED = 7             # mixed PADD (Z2 = 1, U2 = k T2)
 MULS_COMPLETE = 9          # complete PADD with k T2 formed on the fly
 # gfx950 VALU: 256 CUs x 4 SIMDs x 16 lanes, v_mad_u64_u32 at full rate, 2.4 GHz
 PEAK_MAD_PER_S = 256 * 64 * 2.4e9
+# Chip-wide issue rates measured by --microbench (profiles/valu_rates.md), as
+# fractions of PEAK_MAD_PER_S: independent v_mad_u64_u32 and v_addc_co_u32.
+# The field multiply issues one carry add per multiply-add, so its mads can
+# reach at most 1 / (1/MAD_RATE + 1/ADDC_RATE) of the peak.
+MAD_RATE = 0.71
+ADDC_RATE = 0.80
+MAD_WITH_CARRY_CEILING = 1.0 / (1.0 / MAD_RATE + 1.0 / ADDC_RATE)
 
 
 def padd_count_formula(n, c):
@@ -461,6 +468,8 @@ def main():
             "peak": PEAK_MAD_PER_S / 1e12,
             "unit": "Tmad/s (32x32->64 multiply-adds)",
             "frac": achieved / PEAK_MAD_PER_S,
+            "mad_with_carry_ceiling_frac": MAD_WITH_CARRY_CEILING,
+            "frac_of_that_ceiling": achieved / PEAK_MAD_PER_S / MAD_WITH_CARRY_CEILING,
             "traffic": accum_traffic(),
             "work_per_launch": {"mixed_padds": entries, "mad_per_padd": MULS_MIXED * MAD_PER_MUL},
             "launch_ms": accum_tot_ms,
