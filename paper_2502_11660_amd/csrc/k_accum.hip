@@ -142,9 +142,12 @@ __global__ void __launch_bounds__(256) k_merge_small(const uint32_t* __restrict_
 }
 
 // Long split buckets, one block each: the block's threads sum strided heads
-// of the span, then fold their partial sums pairwise through LDS, and thread
-// 0 adds the tail.  Blocks take list entries in turn; an empty list costs one
-// read.
+// of the span, then fold their partial sums pairwise through LDS (as many
+// levels as the span needs), and thread 0 adds the tail.  The grid holds a
+// block for every possible list entry (a long span covers more than
+// SMALL_SPAN chunks of its own, so there are at most chunks / SMALL_SPAN, and
+// up to 2048 blocks), so the entries run side by side; blocks past the list's
+// count leave at once.
 constexpr int LONG_THREADS = 128;
 __global__ void __launch_bounds__(LONG_THREADS) k_merge_long(const uint32_t* __restrict__ key,
                                                              const uint32_t* __restrict__ offsets,
@@ -161,18 +164,25 @@ __global__ void __launch_bounds__(LONG_THREADS) k_merge_long(const uint32_t* __r
     const uint32_t e_last = (ch + 1) * K - 1;  // the tail's bucket ends after this chunk
     const uint32_t b = key[e_last];
     const uint32_t c1 = (offsets[b + 1] - 1) / K;
-    xytz acc = pt_identity();
-    for (uint32_t j = ch + 1 + threadIdx.x; j <= c1; j += LONG_THREADS)
-      acc = padd_full(acc, ld_xytz(head + (size_t)j * XYTZ_WORDS), p2);
-    st_xytz(part[threadIdx.x], acc);
+    const uint32_t span = c1 - ch;
+    const uint32_t nact = span < (uint32_t)LONG_THREADS ? span : (uint32_t)LONG_THREADS;
+    if (threadIdx.x < nact) {
+      xytz acc = pt_identity();
+      for (uint32_t j = ch + 1 + threadIdx.x; j <= c1; j += LONG_THREADS)
+        acc = padd_full(acc, ld_xytz(head + (size_t)j * XYTZ_WORDS), p2);
+      st_xytz(part[threadIdx.x], acc);
+    }
     __syncthreads();
-    for (uint32_t half = LONG_THREADS / 2; half >= 1; half >>= 1) {
-      if (threadIdx.x < half) {
+    // fold partials [0, n) into [0, ceil(n / 2)) until one is left
+    for (uint32_t n = nact; n > 1;) {
+      const uint32_t half = (n + 1) >> 1;
+      if (threadIdx.x + half < n) {
         xytz a = ld_xytz(part[threadIdx.x]);
         xytz o = ld_xytz(part[threadIdx.x + half]);
         st_xytz(part[threadIdx.x], padd_full(a, o, p2));
       }
       __syncthreads();
+      n = half;
     }
     if (threadIdx.x == 0) {
       xytz t = ld_xytz(tail + (size_t)ch * XYTZ_WORDS);
@@ -203,7 +213,11 @@ int launch_accumulate(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t s
   }
   ProfScope prof(PT_MERGE, st);
   k_merge_small<<<grid, 256, 0, st>>>(key, offsets, M, K, head, tail, buckets, longlist);
-  k_merge_long<<<64, LONG_THREADS, 0, st>>>(key, offsets, K, head, tail, buckets, longlist);
+  // a block per possible entry (at most chunks / SMALL_SPAN), capped: the
+  // common empty list then costs one short wave per block
+  const unsigned long_grid =
+      (unsigned)std::min<size_t>(2048, std::max<size_t>(1, pl.chunks / SMALL_SPAN));
+  k_merge_long<<<long_grid, LONG_THREADS, 0, st>>>(key, offsets, K, head, tail, buckets, longlist);
   HIPCHK(hipGetLastError());
   return MSM_OK;
 }
