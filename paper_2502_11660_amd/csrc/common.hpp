@@ -131,7 +131,7 @@ struct Plan {
   // byte offsets into the workspace
   size_t o_flags = 0, o_total = 0, o_offsets = 0, o_counts = 0, o_blocksums = 0, o_digits = 0,
          o_tmp = 0, o_key = 0, o_idx = 0, o_head = 0, o_tail = 0, o_buckets = 0, o_lvl0 = 0,
-         o_lvl1 = 0, o_wsum = 0, o_qstate = 0, o_longlist = 0, o_jobs = 0, o_segoff = 0, bytes = 0;
+         o_lvl1 = 0, o_wsum = 0, o_qstate = 0, o_longlist = 0, o_big = 0, o_bigdesc = 0, o_bigcnt = 0, o_jobs = 0, o_segoff = 0, bytes = 0;
 };
 
 int num_windows(int c, int encoding);

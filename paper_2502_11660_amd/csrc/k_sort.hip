@@ -34,6 +34,7 @@ namespace {
 constexpr int SORT_THREADS = 256;
 constexpr uint32_t TILE = SORT_TILE;  // entries per pass-1 tile
 constexpr uint32_t PART_CAP = 8192;   // entries staged in LDS by pass 2
+constexpr unsigned BIG_GRID = 512;    // blocks of the large-partition kernels
 
 struct SortGeom {
   JobView jv;
@@ -237,69 +238,206 @@ __global__ void __launch_bounds__(SORT_THREADS) k_part_scatter(SortGeom g, uint3
   }
 }
 
-// pass 2: one block per partition (segment s, high bits hi).  A staged
-// partition is ranked in LDS (a permutation into bucket order) and written
-// out linearly; a larger one is streamed from tmp twice.
+// partition p's range [start, start + size) in tmp; partitions are contiguous
+// in the count matrix, the next one starting tps entries later
+__device__ __forceinline__ void part_range(const SortGeom& g, const uint32_t* __restrict__ scanned,
+                                           uint32_t total, size_t ncounts, uint32_t p,
+                                           uint32_t& start, uint32_t& size) {
+  const uint32_t s = p >> g.hi_bits, hi = p & ((1u << g.hi_bits) - 1);
+  const JobDesc d = g.jv.get(s / g.W);
+  const size_t ci = count_index(g, d, s % g.W, hi, 0);
+  start = scanned[ci];
+  const uint32_t end = (ci + d.tps < ncounts) ? scanned[ci + d.tps] : total;
+  size = end - start;
+}
+
+// first bucket of partition p
+__device__ __forceinline__ uint32_t part_bucket0(const SortGeom& g, uint32_t p) {
+  const uint32_t s = p >> g.hi_bits, hi = p & ((1u << g.hi_bits) - 1);
+  return (s << g.bb) + (hi << g.lo_bits);
+}
+
+// pass 2: one block per partition (segment s, high bits hi).  The partition
+// is ranked in LDS (a permutation into bucket order) and written out
+// linearly.  A partition of more than PART_CAP entries (skewed digits) is only
+// listed in big[] here; the k_big_* kernels sort it with many blocks.
 __global__ void __launch_bounds__(SORT_THREADS) k_part_sort(
     SortGeom g, const uint32_t* __restrict__ scanned, const uint32_t* __restrict__ total_p,
     size_t ncounts, const uint2* __restrict__ tmp, uint32_t* __restrict__ key,
-    uint32_t* __restrict__ idx, uint32_t* __restrict__ offsets, uint32_t* __restrict__ buckets) {
+    uint32_t* __restrict__ idx, uint32_t* __restrict__ offsets, uint32_t* __restrict__ buckets,
+    uint32_t* __restrict__ big) {
   __shared__ uint32_t ent_idx[PART_CAP];  // index words of the staged entries
   __shared__ uint8_t ent_lo[PART_CAP];    // their low bucket bits
   __shared__ uint16_t perm[PART_CAP];     // position in bucket order -> entry
   __shared__ uint32_t hist[256], cur[256];
-  const uint32_t H = 1u << g.hi_bits, L = 1u << g.lo_bits;
-  const uint32_t p = blockIdx.x, s = p >> g.hi_bits, hi = p & (H - 1);
-  const uint32_t j = s / g.W, w = s % g.W;
-  const JobDesc d = g.jv.get(j);
+  const uint32_t L = 1u << g.lo_bits;
+  const uint32_t p = blockIdx.x;
   const uint32_t total = *total_p;
-  // partitions are contiguous in the count matrix: the next one starts tps
-  // entries later
-  const size_t ci = count_index(g, d, w, hi, 0);
-  const uint32_t start = scanned[ci];
-  const uint32_t end = (ci + d.tps < ncounts) ? scanned[ci + d.tps] : total;
-  const uint32_t size = end - start;
-  const bool staged = size <= PART_CAP;
+  uint32_t start, size;
+  part_range(g, scanned, total, ncounts, p, start, size);
+  if (p == 0 && threadIdx.x == 0) offsets[g.S << g.bb] = total;
+  if (size > PART_CAP) {
+    if (threadIdx.x == 0) big[1 + atomicAdd(&big[0], 1u)] = p;
+    return;
+  }
   if (threadIdx.x < 256) hist[threadIdx.x] = 0;
   __syncthreads();
   for (uint32_t k = threadIdx.x; k < size; k += SORT_THREADS) {
     const uint2 e = tmp[start + k];
     const uint32_t lo = e.y & (L - 1);
-    if (staged) {
-      ent_idx[k] = e.x;
-      ent_lo[k] = (uint8_t)lo;
-    }
+    ent_idx[k] = e.x;
+    ent_lo[k] = (uint8_t)lo;
     atomicAdd(&hist[lo], 1u);
   }
   __syncthreads();
   for (uint32_t lo = threadIdx.x; lo < L; lo += SORT_THREADS) cur[lo] = hist[lo];
   __syncthreads();
   lds_exclusive_scan256(cur, L);  // cur[lo] = local start of bucket lo
-  const uint32_t bucket0 = (s << g.bb) + hi * L;
+  const uint32_t bucket0 = part_bucket0(g, p);
   if (threadIdx.x < L) {
     const uint32_t lo = threadIdx.x;
     offsets[bucket0 + lo] = start + cur[lo];
     if (hist[lo] == 0 && buckets)
       st_xytz(buckets + (size_t)(bucket0 + lo) * XYTZ_WORDS, pt_identity());
   }
-  if (p == 0 && threadIdx.x == 0) offsets[g.S << g.bb] = total;
   __syncthreads();
-  if (staged) {
-    for (uint32_t k = threadIdx.x; k < size; k += SORT_THREADS)
-      perm[atomicAdd(&cur[ent_lo[k]], 1u)] = (uint16_t)k;
-    __syncthreads();
-    for (uint32_t q = threadIdx.x; q < size; q += SORT_THREADS) {
-      const uint32_t k = perm[q];
-      key[start + q] = bucket0 + ent_lo[k];
-      idx[start + q] = ent_idx[k];
+  for (uint32_t k = threadIdx.x; k < size; k += SORT_THREADS)
+    perm[atomicAdd(&cur[ent_lo[k]], 1u)] = (uint16_t)k;
+  __syncthreads();
+  for (uint32_t q = threadIdx.x; q < size; q += SORT_THREADS) {
+    const uint32_t k = perm[q];
+    key[start + q] = bucket0 + ent_lo[k];
+    idx[start + q] = ent_idx[k];
+  }
+}
+
+// Large partitions, sorted by many blocks.  big[0] = their count n, big[1..n]
+// their ids.  desc[4b .. 4b + 3] = id, start, size and first item of large
+// partition b, desc[4n] = the item count; an item is BIG_CH consecutive
+// entries of one large partition.  cnt[item * 256 + lo] holds the item's count
+// of bucket lo, then its cursor (the bucket's start plus the entries of
+// earlier items).
+constexpr uint32_t BIG_CH = 4096;
+
+__device__ __forceinline__ uint32_t big_of_item(const uint32_t* __restrict__ desc, uint32_t nbig,
+                                                uint32_t item) {
+  return find_job(nbig, item, [&](uint32_t b) { return desc[4 * b + 3]; });
+}
+
+// numbering of the items (one block)
+__global__ void __launch_bounds__(SORT_THREADS) k_big_plan(
+    SortGeom g, const uint32_t* __restrict__ scanned, const uint32_t* __restrict__ total_p,
+    size_t ncounts, const uint32_t* __restrict__ big, uint32_t* __restrict__ desc) {
+  __shared__ uint32_t chunks[16 * SORT_THREADS];
+  const uint32_t nbig = big[0], total = *total_p;
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < nbig; base += 16 * SORT_THREADS) {
+    const uint32_t n = min(16u * SORT_THREADS, nbig - base);
+    for (uint32_t i = threadIdx.x; i < n; i += SORT_THREADS) {
+      const uint32_t p = big[1 + base + i];
+      uint32_t start, size;
+      part_range(g, scanned, total, ncounts, p, start, size);
+      desc[4 * (base + i) + 0] = p;
+      desc[4 * (base + i) + 1] = start;
+      desc[4 * (base + i) + 2] = size;
+      chunks[i] = (size + BIG_CH - 1) / BIG_CH;
     }
-  } else {
-    for (uint32_t k = threadIdx.x; k < size; k += SORT_THREADS) {
+    __syncthreads();
+    const uint32_t tot = lds_exclusive_scan(chunks, n);
+    for (uint32_t i = threadIdx.x; i < n; i += SORT_THREADS) desc[4 * (base + i) + 3] = carry + chunks[i];
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) desc[4 * nbig] = carry;
+}
+
+// per item: histogram of the low bucket bits
+__global__ void __launch_bounds__(SORT_THREADS) k_big_count(SortGeom g,
+                                                            const uint32_t* __restrict__ big,
+                                                            const uint32_t* __restrict__ desc,
+                                                            const uint2* __restrict__ tmp,
+                                                            uint32_t* __restrict__ cnt) {
+  __shared__ uint32_t hist[256];
+  const uint32_t nbig = big[0];
+  if (nbig == 0) return;
+  const uint32_t items = desc[4 * nbig], L = 1u << g.lo_bits;
+  for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
+    const uint32_t b = big_of_item(desc, nbig, item);
+    const uint32_t start = desc[4 * b + 1], size = desc[4 * b + 2];
+    const uint32_t e0 = (item - desc[4 * b + 3]) * BIG_CH, e1 = min(e0 + BIG_CH, size);
+    if (threadIdx.x < 256) hist[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t k = e0 + threadIdx.x; k < e1; k += SORT_THREADS)
+      atomicAdd(&hist[tmp[start + k].y & (L - 1)], 1u);
+    __syncthreads();
+    for (uint32_t lo = threadIdx.x; lo < L; lo += SORT_THREADS)
+      cnt[(size_t)item * 256 + lo] = hist[lo];
+    __syncthreads();
+  }
+}
+
+// per large partition: counts -> cursors, bucket offsets, identities
+__global__ void __launch_bounds__(SORT_THREADS) k_big_scan(SortGeom g,
+                                                           const uint32_t* __restrict__ big,
+                                                           const uint32_t* __restrict__ desc,
+                                                           uint32_t* __restrict__ cnt,
+                                                           uint32_t* __restrict__ offsets,
+                                                           uint32_t* __restrict__ buckets) {
+  __shared__ uint32_t bstart[256];
+  const uint32_t nbig = big[0], L = 1u << g.lo_bits, lo = threadIdx.x;
+  for (uint32_t b = blockIdx.x; b < nbig; b += gridDim.x) {
+    const uint32_t p = desc[4 * b], start = desc[4 * b + 1], size = desc[4 * b + 2];
+    const uint32_t it0 = desc[4 * b + 3], nit = (size + BIG_CH - 1) / BIG_CH;
+    uint32_t run = 0;
+    if (lo < L) {
+      for (uint32_t it = 0; it < nit; ++it) {
+        uint32_t* c = cnt + (size_t)(it0 + it) * 256 + lo;
+        const uint32_t v = *c;
+        *c = run;
+        run += v;
+      }
+    }
+    if (lo < 256) bstart[lo] = run;
+    __syncthreads();
+    lds_exclusive_scan256(bstart, L);
+    const uint32_t bucket0 = part_bucket0(g, p);
+    if (lo < L) {
+      offsets[bucket0 + lo] = start + bstart[lo];
+      if (run == 0 && buckets)
+        st_xytz(buckets + (size_t)(bucket0 + lo) * XYTZ_WORDS, pt_identity());
+      for (uint32_t it = 0; it < nit; ++it) cnt[(size_t)(it0 + it) * 256 + lo] += bstart[lo];
+    }
+    __syncthreads();
+  }
+}
+
+// per item: place its entries at the cursors
+__global__ void __launch_bounds__(SORT_THREADS) k_big_scatter(SortGeom g,
+                                                              const uint32_t* __restrict__ big,
+                                                              const uint32_t* __restrict__ desc,
+                                                              const uint32_t* __restrict__ cnt,
+                                                              const uint2* __restrict__ tmp,
+                                                              uint32_t* __restrict__ key,
+                                                              uint32_t* __restrict__ idx) {
+  __shared__ uint32_t cur[256];
+  const uint32_t nbig = big[0];
+  if (nbig == 0) return;
+  const uint32_t items = desc[4 * nbig], L = 1u << g.lo_bits;
+  for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
+    const uint32_t b = big_of_item(desc, nbig, item);
+    const uint32_t p = desc[4 * b], start = desc[4 * b + 1], size = desc[4 * b + 2];
+    const uint32_t e0 = (item - desc[4 * b + 3]) * BIG_CH, e1 = min(e0 + BIG_CH, size);
+    const uint32_t bucket0 = part_bucket0(g, p);
+    for (uint32_t lo = threadIdx.x; lo < L; lo += SORT_THREADS) cur[lo] = cnt[(size_t)item * 256 + lo];
+    __syncthreads();
+    for (uint32_t k = e0 + threadIdx.x; k < e1; k += SORT_THREADS) {
       const uint2 e = tmp[start + k];
-      const uint32_t pos = start + atomicAdd(&cur[e.y & (L - 1)], 1u);
-      key[pos] = e.y;
+      const uint32_t lo = e.y & (L - 1);
+      const uint32_t pos = start + atomicAdd(&cur[lo], 1u);
+      key[pos] = bucket0 + lo;
       idx[pos] = e.x;
     }
+    __syncthreads();
   }
 }
 
@@ -431,8 +569,17 @@ int launch_sort(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t st) {
   k_scan_top<<<1, SCAN_THREADS, 0, st>>>(blocksums, (uint32_t)pl.nb, total);
   k_scan_add<<<(unsigned)pl.nb, SCAN_THREADS, 0, st>>>(counts, pl.ncounts, blocksums);
   k_part_scatter<<<(unsigned)pl.tiles, SORT_THREADS, 0, st>>>(g, off, digits, counts, tmp);
+  uint32_t* big = ws_at<uint32_t>(ws, pl.o_big);
+  uint32_t* bigdesc = ws_at<uint32_t>(ws, pl.o_bigdesc);
+  uint32_t* bigcnt = ws_at<uint32_t>(ws, pl.o_bigcnt);
+  if ((rc = launch_fill_u32(big, 1, 0u, st)) != MSM_OK) return rc;
   k_part_sort<<<(unsigned)(pl.S << pl.hi_bits), SORT_THREADS, 0, st>>>(
-      g, counts, total, pl.ncounts, tmp, key, idx, offsets, buckets);
+      g, counts, total, pl.ncounts, tmp, key, idx, offsets, buckets, big);
+  // large partitions (none for evenly spread digits: these return at once)
+  k_big_plan<<<1, SORT_THREADS, 0, st>>>(g, counts, total, pl.ncounts, big, bigdesc);
+  k_big_count<<<BIG_GRID, SORT_THREADS, 0, st>>>(g, big, bigdesc, tmp, bigcnt);
+  k_big_scan<<<BIG_GRID, SORT_THREADS, 0, st>>>(g, big, bigdesc, bigcnt, offsets, buckets);
+  k_big_scatter<<<BIG_GRID, SORT_THREADS, 0, st>>>(g, big, bigdesc, bigcnt, tmp, key, idx);
   HIPCHK(hipGetLastError());
   return MSM_OK;
 }

@@ -130,3 +130,22 @@ def test_glv_full_size_closed_form(c):
     ks = [inputs.words_to_int(r) for r in kw]
     ss = [inputs.words_to_int(r) for r in sw]
     assert got == msm.closed_form(ss, ks)
+
+
+def test_glv_sparse_top_window_large_partitions():
+    """n = 2^15 with c = 10: the top window keeps 8 digit bits, so its 2^16
+    entries crowd about 120 of 512 buckets and each of its first sort
+    partitions (32 buckets) holds ~16k entries, above the 8192-entry LDS stage:
+    the many-block path (several items per partition, many buckets) runs."""
+    n = 1 << 15
+    seed = inputs.config_seed(4)
+    kw = inputs.nonzero_scalars_mod_r(seed, n, stream=5)
+    sw = inputs.scalars_mod_r(seed, n, stream=6)
+    xy, inf = api.gen_points(_dev(kw), n)
+    xyu, status = api.points_prepare(xy, n, inf=inf, endo=True)
+    res = api.msm_run(xyu, _dev(sw), n, 10, GLV)
+    got, flags = api.decode_result(api.to_host(res))
+    assert flags == 0 and int(api.to_host(status)[0]) == 0
+    ks = [inputs.words_to_int(r) for r in kw]
+    ss = [inputs.words_to_int(r) for r in sw]
+    assert got == msm.closed_form(ss, ks)
