@@ -111,26 +111,6 @@ __device__ __forceinline__ xytz padd_full(const xytz& a, const xytz& b, const fe
   return r;
 }
 
-// a + b with b given as (X, Y, U = k T, Z): 8 multiplications.
-__device__ __forceinline__ xytz padd_xyuz(const xytz& a, const fe& bX, const fe& bY, const fe& bU,
-                                         const fe& bZ, const fe& p2) {
-  fe A = fe_mul(fe_sub_plus(a.Y, a.X, p2), fe_sub_plus(bY, bX, p2));
-  fe B = fe_mul(fe_add(a.Y, a.X), fe_add(bY, bX));
-  fe C = fe_mul(a.T, bU);
-  fe Z = fe_mul(a.Z, bZ);
-  fe D = fe_add(Z, Z);
-  fe E = fe_sub_plus(B, A, p2);
-  fe F = fe_sub_plus(D, C, p2);
-  fe G = fe_add(D, C);
-  fe H = fe_add(B, A);
-  xytz r;
-  r.X = fe_mul(E, F);
-  r.Y = fe_mul(G, H);
-  r.T = fe_mul(E, H);
-  r.Z = fe_mul(F, G);
-  return r;
-}
-
 // 2a by the dedicated doubling for a = -1 (Hisil et al. 2008):
 //   A = X^2  B = Y^2  C = 2 Z^2  E = (X+Y)^2 - A - B
 //   G = B - A  F = G - C  H = -(A + B)

@@ -51,10 +51,6 @@ constexpr uint32_t kOne[NL] = {0xffffff68u, 0x02cdffffu, 0x7fffffb1u, 0x51409f83
 constexpr uint32_t kR2[NL] = {0x9400cd22u, 0xb786686cu, 0xb00431b1u, 0x0329fcaau,
                               0x62d6b46du, 0x22a5f111u, 0x827dc3acu, 0xbfdf7d03u,
                               0x41790bf9u, 0x837e92f0u, 0x1e914b88u, 0x006dfccbu};
-// p - 2: the Fermat inversion exponent.
-constexpr uint32_t kPm2[NL] = {0xffffffffu, 0x8508bfffu, 0x30000000u, 0x170b5d44u,
-                               0xba094800u, 0x1ef3622fu, 0x00f5138fu, 0x1a22d9f3u,
-                               0x6ca1493bu, 0xc63b05c0u, 0x17c510eau, 0x01ae3a46u};
 
 __device__ __forceinline__ fe fe_const(const uint32_t (&c)[NL]) {
   fe r;
@@ -632,16 +628,5 @@ __device__ __forceinline__ fe fe_from_mont(const fe& a) {
   return fe_canon(fe_mul(a, one));
 }
 
-// Inverse by Fermat: a^(p-2), left-to-right square-and-multiply over the bits
-// of p - 2.  Input in Montgomery form (any lazily reduced value < 12p), output
-// in Montgomery form, < 2p.  Zero maps to zero.
-__device__ __noinline__ fe fe_inv(const fe& a) {
-  fe r = a;  // top bit of p-2 (bit 376) is set
-  for (int bit = 375; bit >= 0; --bit) {
-    r = fe_sqr(r);
-    if ((kPm2[bit >> 5] >> (bit & 31)) & 1u) r = fe_mul(r, a);
-  }
-  return r;
-}
 
 }  // namespace msm

@@ -6,12 +6,13 @@
 // the latency of one addition done by one lane is the length of its
 // instruction stream, so here four consecutive lanes ("a quad") share one
 // point: lane q of the quad holds coordinate q (0: X, 1: Y, 2: T or U = kT,
-// 3: Z).  Every formula below has four independent multiplications per phase,
-// so each lane does one Montgomery multiply per phase; the four products are
-// exchanged with DPP quad broadcasts (one instruction per word).
+// 3: Z).  The addition has four independent multiplications per phase, so
+// each lane does one Montgomery multiply per phase; the four products are
+// exchanged with DPP quad broadcasts (one instruction per word).  The quad
+// serves the small levels of the aggregation tree (many independent
+// additions per launch); the long chains run on the wider unit of
+// wide_unit.hpp.
 //
-//   doubling                       2 phases  (4 squarings, 4 products)
-//   addition, second operand XYUZ  2 phases  (A, B, C = T1 U2, Z1 Z2; products)
 //   addition, both XYTZ            3 phases  (extra k * (T1 T2) on lane 2)
 //
 // All lanes of a quad must be active.  Values follow the lazy-reduction
@@ -63,19 +64,6 @@ __device__ __forceinline__ fe quad_finish(int q, const fe& prod, const fe& p2) {
   return fe_mul(l, r);
 }
 
-// P1 + P2 where this lane holds coordinate q of P1 (XYTZ) and of P2 given
-// as (X, Y, U = kT, Z).
-__device__ __forceinline__ fe quad_add_u(const fe& p1, const fe& p2u, const fe& p2) {
-  const int q = quad_lane();
-  fe X1 = qbcast<0>(p1), Y1 = qbcast<1>(p1);
-  fe X2 = qbcast<0>(p2u), Y2 = qbcast<1>(p2u);
-  fe l = qpick(q, fe_sub_plus(Y1, X1, p2), fe_add(Y1, X1), p1, p1);
-  fe r = qpick(q, fe_sub_plus(Y2, X2, p2), fe_add(Y2, X2), p2u, p2u);
-  fe m = fe_mul(l, r);                 // A, B, C = T1 U2, Z1 Z2
-  m = fe_select(q == 3, fe_add(m, m), m);  // D = 2 Z1 Z2 on lane 3
-  return quad_finish(q, m, p2);
-}
-
 // P1 + P2, both XYTZ.
 __device__ __forceinline__ fe quad_add(const fe& p1, const fe& p2v, const fe& p2) {
   const int q = quad_lane();
@@ -88,26 +76,6 @@ __device__ __forceinline__ fe quad_add(const fe& p1, const fe& p2v, const fe& p2
   m = fe_mul(m, s);                    // C = k T1 T2 on lane 2, unchanged elsewhere
   m = fe_select(q == 3, fe_add(m, m), m);
   return quad_finish(q, m, p2);
-}
-
-// 2 P (dedicated doubling, a = -1; see pdbl in curve.hpp for the bounds).
-__device__ __forceinline__ fe quad_dbl(const fe& pc, const fe& p2) {
-  const int q = quad_lane();
-  fe X = qbcast<0>(pc), Y = qbcast<1>(pc);
-  // lane 0: X^2, lane 1: Y^2, lane 2: (X+Y)^2, lane 3: Z^2
-  fe l = qpick(q, X, Y, fe_add(X, Y), pc);
-  fe m = fe_mul(l, l);
-  fe A = qbcast<0>(m), B = qbcast<1>(m), S = qbcast<2>(m), Zs = qbcast<3>(m);
-  fe p4 = fe_add(p2, p2);
-  fe C = fe_add(Zs, Zs);
-  fe AB = fe_add(A, B);
-  fe E = fe_sub_plus(S, AB, p4);
-  fe G = fe_sub_plus(B, A, p2);
-  fe H = fe_sub_plus(fe_zero(), AB, p4);
-  fe F = fe_sub_plus(G, C, p4);
-  fe lo = qpick(q, E, G, E, F);
-  fe ro = qpick(q, F, H, H, G);
-  return fe_mul(lo, ro);
 }
 
 // T -> U = k T on lane 2 of the quad (XYTZ -> XYUZ); one phase.
