@@ -99,31 +99,35 @@ __global__ void __launch_bounds__(128) k_window_combine(const uint32_t* __restri
   __shared__ wunit_lds<2> s;
   const uint32_t w = blockIdx.x;
   wunit_init(s);  // accumulator = identity
+  unit_sync();    // (written by wave 0 for both waves)
   const wslot q = wslot_here();
   const uint32_t* V = root + (size_t)w * (bb + 1) * XYTZ_WORDS;
   limb_src nxt = wu_fetch(V + (size_t)(bb - 1) * XYTZ_WORDS, q.k, q.j);
   const int steps = (int)bb + (add_total ? 1 : 0);
+  uint32_t par = 0;
   for (int i = 0; i < steps; ++i) {
     // step i adds slot bb - 1 - i (i < bb) or the total (slot bb)
     const uint32_t* opd = s.opd[i & 1];
+    // each lane writes the coordinate limb its own wave reads
     if (q.act) s.opd[i & 1][16 * q.k + q.j] = limb_extract(nxt, q.j);
     const int following = i + 1 < (int)bb ? (int)bb - 2 - i : (int)bb;  // clamped
     nxt = wu_fetch(V + (size_t)following * XYTZ_WORDS, q.k, q.j);
-    unit_sync();
-    if (i >= 1 && i < (int)bb) wu_dbl(s, q);
-    wu_add_u(s, opd, q);
+    wave_lds_sync();
+    if (i >= 1 && i < (int)bb) wu_dbl(s, q, par);
+    wu_add_u(s, opd, q, par);
   }
+  __syncthreads();  // the accumulator's coordinates come from both waves
   if (threadIdx.x < 64) {
     // record 2w: XYTZ; record 2w + 1: XYUZ with U = k T (one more product,
     // in the first half of wave 0)
     wu_store_acc(s, wsum + (size_t)(2 * w) * XYTZ_WORDS);
     const bool h0 = q.k == 0 && q.act;
     const uint32_t u = wmul2(h0 ? s.acc[32 + q.j] : 0u, h0 ? limb_of_const(kK, q.j) : 0u, s.mul[0]);
-    if (h0) s.prod[32 + q.j] = u;
+    if (h0) s.prod[0][32 + q.j] = u;
     wave_lds_sync();
     const uint32_t lane = wlane();
     if (lane < 4) {
-      const uint32_t* src = lane == 2 ? s.prod + 32 : s.acc + 16 * lane;
+      const uint32_t* src = lane == 2 ? s.prod[0] + 32 : s.acc + 16 * lane;
       st_aos(wsum + (size_t)(2 * w + 1) * XYTZ_WORDS, (int)lane, words_of_limbs(src));
     }
   }
@@ -146,13 +150,15 @@ __global__ void __launch_bounds__(128) k_horner_wide(const uint32_t* __restrict_
   unit_sync();
   if (q.act) s.acc[16 * q.k + q.j] = limb_extract(top, q.j);  // S_{W-1}, XYTZ
   unit_sync();
+  uint32_t par = 0;
   for (int w = (int)W - 2; w >= 0; --w) {
     // S_w, XYUZ (read after the doublings); then fetch S_{w-1}
     if (q.act) s.opd[0][16 * q.k + q.j] = limb_extract(nxt, q.j);
     if (w >= 1) nxt = wu_fetch(ws + (size_t)(2 * w - 1) * XYTZ_WORDS, q.k, q.j);
-    for (uint32_t t = 0; t < c; ++t) wu_dbl(s, q);
-    wu_add_u(s, s.opd[0], q);
+    for (uint32_t t = 0; t < c; ++t) wu_dbl(s, q, par);
+    wu_add_u(s, s.opd[0], q, par);
   }
+  __syncthreads();  // the accumulator's coordinates come from both waves
   if (threadIdx.x < 64) wu_store_acc(s, qstate + (size_t)job * XYTZ_WORDS);
 }
 

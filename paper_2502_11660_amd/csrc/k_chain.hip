@@ -48,7 +48,9 @@ __global__ void __launch_bounds__(64) k_chain_lane(const uint32_t* __restrict__ 
 
 // The wide unit: waves 0 and 1 run the additions (two phases of four
 // products); wave 2 prepares the next operand (U = k T, one product) while
-// they add the current one, and fetches the point after that.
+// they add the current one, and fetches the point after that.  Its slot
+// write comes before the step's single unit_sync, which orders it before the
+// next step's first phase (and after the previous reads of that slot).
 __global__ void __launch_bounds__(192) k_chain_wide(const uint32_t* __restrict__ pts,
                                                     uint32_t count, uint32_t* __restrict__ out) {
   __shared__ wunit_lds<3> s;
@@ -75,9 +77,10 @@ __global__ void __launch_bounds__(192) k_chain_wide(const uint32_t* __restrict__
     }
   }
   unit_sync();
+  uint32_t par = 0;
   for (uint32_t i = 0; i < count; ++i) {
     if (!prep) {
-      wu_add_u(s, s.opd[i & 1], q);
+      wu_add_u(s, s.opd[i & 1], q, par);  // one unit_sync per step
     } else {
       // Unconditional and clamped (past the end it prepares a slot nobody
       // reads): a conditional fetch would make the compiler copy the fresh
@@ -95,10 +98,10 @@ __global__ void __launch_bounds__(192) k_chain_wide(const uint32_t* __restrict__
         o[32 + q.j] = u;
         o[48 + q.j] = c[3];
       }
-      unit_sync();  // the two syncs of wu_add_u
-      unit_sync();
+      unit_sync();  // the one sync of wu_add_u (the slot is written before it)
     }
   }
+  __syncthreads();
   if (threadIdx.x < 64) wu_store_acc(s, out);
 }
 

@@ -15,7 +15,7 @@
 // with every coordinate below 1.2p (inputs below 2p where noted),
 //   addition   E = B - A + 3p < 4.2p   F = D - C + 3p < 5.4p
 //              G = D + C < 3.6p        H = B + A < 2.4p
-//   doubling   E = S - A - B + 3p < 4.2p   G = B - A + 2p < 3.2p
+//   doubling   E = 2 T Z < 2.4p            G = B - A + 2p < 3.2p
 //              H = 3p - A - B <= 3p        F = G - 2 Z^2 + 3p < 6.2p
 // so every product operand stays below 8p and every product below 1.2p;
 // limbs stay below 2^28.
@@ -30,8 +30,8 @@ namespace msm {
 template <int WAVES>
 struct wunit_lds {
   uint32_t mul[WAVES][WMUL2_WORDS];
-  uint32_t acc[64];     // X, Y, T, Z of the accumulator
-  uint32_t prod[64];    // phase-1 products of the running operation
+  uint32_t acc[64];      // X, Y, T, Z of the accumulator
+  uint32_t prod[2][64];  // phase-1 products, alternating between operations
   uint32_t opd[2][64];  // second operands X, Y, U = kT, Z (two slots)
   uint32_t c2p[16], c3p[16];
 };
@@ -89,11 +89,22 @@ __device__ __forceinline__ void wu_products_out(wunit_lds<WAVES>& s, const wslot
   if (!q.act) s.acc[16 * q.k + q.j] = v;  // result limb j sits in lane 16 + j
 }
 
-// acc + opd (X2, Y2, U2 = k T2, Z2; coordinates below 2p): two phases.
-// Called by the two computing waves; other waves of the block must meet the
-// same two unit_syncs.
+// Both operations below take two phases and meet the other computing wave
+// once, in a unit_sync between the phases (other waves of the block must
+// meet it too).  The first phase of either operation reads only coordinates
+// its own wave wrote (wave 0: X, Y; wave 1: T, Z; the doubling forms
+// 2XY as 2TZ) and writes the product buffer par, which alternates between
+// operations: so no sync is needed after the second phase, while the other
+// wave may still be reading the previous buffer.  A cross-wave read of the
+// accumulator after the last operation needs a block barrier.
+
+// acc + opd (X2, Y2, U2 = k T2, Z2; coordinates below 2p; each wave reads
+// only its own coordinates of opd).
 template <int WAVES>
-__device__ __forceinline__ void wu_add_u(wunit_lds<WAVES>& s, const uint32_t* opd, const wslot& q) {
+__device__ __forceinline__ void wu_add_u(wunit_lds<WAVES>& s, const uint32_t* opd, const wslot& q,
+                                         uint32_t& par) {
+  uint32_t* prod = s.prod[par];
+  par ^= 1u;
   {
     const uint32_t x1 = s.acc[q.j], y1 = s.acc[16 + q.j], o1 = s.acc[16 * q.k + q.j];
     const uint32_t x2 = opd[q.j], y2 = opd[16 + q.j], o2 = opd[16 * q.k + q.j];
@@ -104,37 +115,38 @@ __device__ __forceinline__ void wu_add_u(wunit_lds<WAVES>& s, const uint32_t* op
     r = q.act ? r : 0u;
     uint32_t v = wmul2_hi(l, r, s.mul[threadIdx.x >> 6]);  // A, B, C = T1 U2, Z1 Z2
     if (q.k == 3) v <<= 1;                                // D = 2 Z1 Z2
-    if (!q.act) s.prod[16 * q.k + q.j] = v;
+    if (!q.act) prod[16 * q.k + q.j] = v;
   }
   unit_sync();
   {
-    const uint32_t A = s.prod[q.j], B = s.prod[16 + q.j], C = s.prod[32 + q.j],
-                   D = s.prod[48 + q.j], c = s.c3p[q.j];
+    const uint32_t A = prod[q.j], B = prod[16 + q.j], C = prod[32 + q.j], D = prod[48 + q.j],
+                   c = s.c3p[q.j];
     wu_products_out(s, q, (B + c) - A, (D + c) - C, D + C, B + A);
   }
-  unit_sync();
+  wave_lds_sync();
 }
 
-// 2 acc by the dedicated doubling (a = -1): two phases, as wu_add_u.
+// 2 acc by the dedicated doubling (a = -1), with E = 2XY taken as 2TZ:
+// A = X^2, B = Y^2, T Z, 2 Z^2 in the first phase.
 template <int WAVES>
-__device__ __forceinline__ void wu_dbl(wunit_lds<WAVES>& s, const wslot& q) {
+__device__ __forceinline__ void wu_dbl(wunit_lds<WAVES>& s, const wslot& q, uint32_t& par) {
+  uint32_t* prod = s.prod[par];
+  par ^= 1u;
   {
-    const uint32_t x = s.acc[q.j], y = s.acc[16 + q.j], o = s.acc[16 * q.k + q.j];
-    uint32_t l = q.k == 2 ? x + y : o;  // X, Y, X + Y, Z
-    l = q.act ? l : 0u;
-    uint32_t v = wmul2_hi(l, l, s.mul[threadIdx.x >> 6]);  // A, B, S, Z^2
-    if (q.k == 3) v <<= 1;                                // 2 Z^2
-    if (!q.act) s.prod[16 * q.k + q.j] = v;
+    const uint32_t o = s.acc[16 * q.k + q.j];            // X, Y, T, Z
+    const uint32_t r = q.k == 2 ? s.acc[48 + q.j] : o;   // X, Y, Z, Z
+    const uint32_t v0 = wmul2_hi(q.act ? o : 0u, q.act ? r : 0u, s.mul[threadIdx.x >> 6]);
+    const uint32_t v = q.k == 3 ? v0 << 1 : v0;          // 2 Z^2
+    if (!q.act) prod[16 * q.k + q.j] = v;
   }
   unit_sync();
   {
-    const uint32_t A = s.prod[q.j], B = s.prod[16 + q.j], S = s.prod[32 + q.j],
-                   Z2 = s.prod[48 + q.j];
+    const uint32_t A = prod[q.j], B = prod[16 + q.j], TZ = prod[32 + q.j], Z2 = prod[48 + q.j];
     const uint32_t c2 = s.c2p[q.j], c3 = s.c3p[q.j], AB = A + B;
     const uint32_t G = (B + c2) - A;
-    wu_products_out(s, q, (S + c3) - AB, (G + c3) - Z2, G, c3 - AB);
+    wu_products_out(s, q, TZ + TZ, (G + c3) - Z2, G, c3 - AB);
   }
-  unit_sync();
+  wave_lds_sync();
 }
 
 // the words of this lane's limb of coordinate `coord` of an AoS record (12
