@@ -83,6 +83,13 @@ struct ProfScope {
   ~ProfScope();
 };
 
+// Digit sort geometry: partitions of uniformly spread digits hold about
+// SORT_PART_TARGET entries; pass 2 stages up to SORT_PART_CAP in LDS and
+// sorts larger partitions on many blocks, in items of SORT_BIG_ITEM entries.
+constexpr uint32_t SORT_PART_TARGET = 4096;
+constexpr uint32_t SORT_PART_CAP = 7168;
+constexpr uint32_t SORT_BIG_ITEM = 4096;
+
 // ---------------------------------------------------------------------------
 // jobs and workspace plans (msm_api.hip)
 // ---------------------------------------------------------------------------
@@ -131,7 +138,7 @@ struct Plan {
   // byte offsets into the workspace
   size_t o_flags = 0, o_total = 0, o_offsets = 0, o_counts = 0, o_blocksums = 0, o_digits = 0,
          o_tmp = 0, o_key = 0, o_idx = 0, o_head = 0, o_tail = 0, o_buckets = 0, o_lvl0 = 0,
-         o_lvl1 = 0, o_wsum = 0, o_qstate = 0, o_longlist = 0, o_big = 0, o_bigdesc = 0, o_bigcnt = 0, o_jobs = 0, o_segoff = 0, bytes = 0;
+         o_lvl1 = 0, o_wsum = 0, o_qstate = 0, o_longlist = 0, o_big = 0, o_bigdesc = 0, o_bigcnt = 0, o_bigitem = 0, o_jobs = 0, o_segoff = 0, bytes = 0;
 };
 
 int num_windows(int c, int encoding);

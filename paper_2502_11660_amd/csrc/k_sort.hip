@@ -33,7 +33,7 @@ namespace {
 
 constexpr int SORT_THREADS = 256;
 constexpr uint32_t TILE = SORT_TILE;  // entries per pass-1 tile
-constexpr uint32_t PART_CAP = 8192;   // entries staged in LDS by pass 2
+constexpr uint32_t PART_CAP = SORT_PART_CAP;  // entries staged in LDS by pass 2
 constexpr unsigned BIG_GRID = 512;    // blocks of the large-partition kernels
 
 struct SortGeom {
@@ -196,11 +196,14 @@ __global__ void __launch_bounds__(SORT_THREADS) k_part_scatter(SortGeom g, uint3
                                                                const uint32_t* __restrict__ digits,
                                                                const uint32_t* __restrict__ scanned,
                                                                uint2* __restrict__ tmp) {
-  __shared__ uint32_t gstart[1u << 12];  // global start of (partition, this tile)
-  __shared__ uint32_t lstart[1u << 12];  // counts, then local starts in the tile
-  __shared__ uint2 stage[TILE];
-  const TileRef t = tile_ref(g, blockIdx.x);
+  // dynamic LDS, sized by the launch for H = 2^hi_bits partitions: the tile
+  // stage, then per partition its global start and its local count / start
+  extern __shared__ uint2 scatter_lds[];
   const uint32_t H = 1u << g.hi_bits;
+  uint2* stage = scatter_lds;
+  uint32_t* gstart = reinterpret_cast<uint32_t*>(scatter_lds + TILE);
+  uint32_t* lstart = gstart + H;
+  const TileRef t = tile_ref(g, blockIdx.x);
   for (uint32_t b = threadIdx.x; b < H; b += SORT_THREADS) {
     gstart[b] = scanned[count_index(g, t.d, t.w, b, t.tile)];
     lstart[b] = 0;
@@ -209,12 +212,18 @@ __global__ void __launch_bounds__(SORT_THREADS) k_part_scatter(SortGeom g, uint3
   const uint32_t e0 = t.tile * TILE, e1 = min(e0 + TILE, t.d.n);
   const uint32_t* dg = digits + (size_t)g.W * t.d.pt_off + (size_t)t.w * t.d.n;
   const uint32_t keybase = (t.j * g.W + t.w) << g.bb;
-  uint32_t part[PER_THREAD], rank[PER_THREAD];
+  uint32_t part[PER_THREAD], rank[PER_THREAD], dq[PER_THREAD];
   uint2 ent[PER_THREAD];
+  // all loads first (clamped, unconditional), so that they overlap
 #pragma unroll
   for (uint32_t r = 0; r < PER_THREAD; ++r) {
     const uint32_t e = e0 + r * SORT_THREADS + threadIdx.x;
-    const uint32_t q = e < e1 ? dg[e] : 0u;
+    dq[r] = dg[e < e1 ? e : e1 - 1];
+  }
+#pragma unroll
+  for (uint32_t r = 0; r < PER_THREAD; ++r) {
+    const uint32_t e = e0 + r * SORT_THREADS + threadIdx.x;
+    const uint32_t q = e < e1 ? dq[r] : 0u;
     part[r] = H;  // no entry
     rank[r] = 0;
     ent[r] = make_uint2(0u, 0u);
@@ -282,12 +291,25 @@ __global__ void __launch_bounds__(SORT_THREADS) k_part_sort(
   }
   if (threadIdx.x < 256) hist[threadIdx.x] = 0;
   __syncthreads();
-  for (uint32_t k = threadIdx.x; k < size; k += SORT_THREADS) {
-    const uint2 e = tmp[start + k];
-    const uint32_t lo = e.y & (L - 1);
-    ent_idx[k] = e.x;
-    ent_lo[k] = (uint8_t)lo;
-    atomicAdd(&hist[lo], 1u);
+  if (size > 0) {
+    // all loads first (clamped, unconditional), so that they overlap
+    constexpr uint32_t PER = (PART_CAP + SORT_THREADS - 1) / SORT_THREADS;
+    uint2 ev[PER];
+#pragma unroll
+    for (uint32_t r = 0; r < PER; ++r) {
+      const uint32_t k = r * SORT_THREADS + threadIdx.x;
+      ev[r] = tmp[start + (k < size ? k : size - 1)];
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < PER; ++r) {
+      const uint32_t k = r * SORT_THREADS + threadIdx.x;
+      if (k < size) {
+        const uint32_t lo = ev[r].y & (L - 1);
+        ent_idx[k] = ev[r].x;
+        ent_lo[k] = (uint8_t)lo;
+        atomicAdd(&hist[lo], 1u);
+      }
+    }
   }
   __syncthreads();
   for (uint32_t lo = threadIdx.x; lo < L; lo += SORT_THREADS) cur[lo] = hist[lo];
@@ -314,20 +336,17 @@ __global__ void __launch_bounds__(SORT_THREADS) k_part_sort(
 // Large partitions, sorted by many blocks.  big[0] = their count n, big[1..n]
 // their ids.  desc[4b .. 4b + 3] = id, start, size and first item of large
 // partition b, desc[4n] = the item count; an item is BIG_CH consecutive
-// entries of one large partition.  cnt[item * 256 + lo] holds the item's count
+// entries of one large partition, item_of[item] its partition.  cnt[item * 256 + lo] holds the item's count
 // of bucket lo, then its cursor (the bucket's start plus the entries of
 // earlier items).
-constexpr uint32_t BIG_CH = 4096;
+constexpr uint32_t BIG_CH = SORT_BIG_ITEM;
 
-__device__ __forceinline__ uint32_t big_of_item(const uint32_t* __restrict__ desc, uint32_t nbig,
-                                                uint32_t item) {
-  return find_job(nbig, item, [&](uint32_t b) { return desc[4 * b + 3]; });
-}
 
-// numbering of the items (one block)
+// numbering of the items (one block); item_of[item] = its large partition
 __global__ void __launch_bounds__(SORT_THREADS) k_big_plan(
     SortGeom g, const uint32_t* __restrict__ scanned, const uint32_t* __restrict__ total_p,
-    size_t ncounts, const uint32_t* __restrict__ big, uint32_t* __restrict__ desc) {
+    size_t ncounts, const uint32_t* __restrict__ big, uint32_t* __restrict__ desc,
+    uint32_t* __restrict__ item_of) {
   __shared__ uint32_t chunks[16 * SORT_THREADS];
   const uint32_t nbig = big[0], total = *total_p;
   uint32_t carry = 0;
@@ -344,7 +363,12 @@ __global__ void __launch_bounds__(SORT_THREADS) k_big_plan(
     }
     __syncthreads();
     const uint32_t tot = lds_exclusive_scan(chunks, n);
-    for (uint32_t i = threadIdx.x; i < n; i += SORT_THREADS) desc[4 * (base + i) + 3] = carry + chunks[i];
+    for (uint32_t i = threadIdx.x; i < n; i += SORT_THREADS) {
+      const uint32_t first = carry + chunks[i];
+      desc[4 * (base + i) + 3] = first;
+      const uint32_t items = (desc[4 * (base + i) + 2] + BIG_CH - 1) / BIG_CH;
+      for (uint32_t k = 0; k < items; ++k) item_of[first + k] = base + i;
+    }
     carry += tot;
     __syncthreads();
   }
@@ -355,6 +379,7 @@ __global__ void __launch_bounds__(SORT_THREADS) k_big_plan(
 __global__ void __launch_bounds__(SORT_THREADS) k_big_count(SortGeom g,
                                                             const uint32_t* __restrict__ big,
                                                             const uint32_t* __restrict__ desc,
+                                                            const uint32_t* __restrict__ item_of,
                                                             const uint2* __restrict__ tmp,
                                                             uint32_t* __restrict__ cnt) {
   __shared__ uint32_t hist[256];
@@ -362,13 +387,21 @@ __global__ void __launch_bounds__(SORT_THREADS) k_big_count(SortGeom g,
   if (nbig == 0) return;
   const uint32_t items = desc[4 * nbig], L = 1u << g.lo_bits;
   for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
-    const uint32_t b = big_of_item(desc, nbig, item);
+    const uint32_t b = item_of[item];
     const uint32_t start = desc[4 * b + 1], size = desc[4 * b + 2];
     const uint32_t e0 = (item - desc[4 * b + 3]) * BIG_CH, e1 = min(e0 + BIG_CH, size);
     if (threadIdx.x < 256) hist[threadIdx.x] = 0;
     __syncthreads();
-    for (uint32_t k = e0 + threadIdx.x; k < e1; k += SORT_THREADS)
-      atomicAdd(&hist[tmp[start + k].y & (L - 1)], 1u);
+    constexpr uint32_t PER = BIG_CH / SORT_THREADS;
+    uint32_t kv[PER];
+#pragma unroll
+    for (uint32_t r = 0; r < PER; ++r) {  // loads first, clamped (e1 > e0)
+      const uint32_t k = e0 + r * SORT_THREADS + threadIdx.x;
+      kv[r] = tmp[start + (k < e1 ? k : e1 - 1)].y;
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < PER; ++r)
+      if (e0 + r * SORT_THREADS + threadIdx.x < e1) atomicAdd(&hist[kv[r] & (L - 1)], 1u);
     __syncthreads();
     for (uint32_t lo = threadIdx.x; lo < L; lo += SORT_THREADS)
       cnt[(size_t)item * 256 + lo] = hist[lo];
@@ -415,6 +448,7 @@ __global__ void __launch_bounds__(SORT_THREADS) k_big_scan(SortGeom g,
 __global__ void __launch_bounds__(SORT_THREADS) k_big_scatter(SortGeom g,
                                                               const uint32_t* __restrict__ big,
                                                               const uint32_t* __restrict__ desc,
+                                                              const uint32_t* __restrict__ item_of,
                                                               const uint32_t* __restrict__ cnt,
                                                               const uint2* __restrict__ tmp,
                                                               uint32_t* __restrict__ key,
@@ -424,18 +458,27 @@ __global__ void __launch_bounds__(SORT_THREADS) k_big_scatter(SortGeom g,
   if (nbig == 0) return;
   const uint32_t items = desc[4 * nbig], L = 1u << g.lo_bits;
   for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
-    const uint32_t b = big_of_item(desc, nbig, item);
+    const uint32_t b = item_of[item];
     const uint32_t p = desc[4 * b], start = desc[4 * b + 1], size = desc[4 * b + 2];
     const uint32_t e0 = (item - desc[4 * b + 3]) * BIG_CH, e1 = min(e0 + BIG_CH, size);
     const uint32_t bucket0 = part_bucket0(g, p);
     for (uint32_t lo = threadIdx.x; lo < L; lo += SORT_THREADS) cur[lo] = cnt[(size_t)item * 256 + lo];
+    constexpr uint32_t PER = BIG_CH / SORT_THREADS;
+    uint2 ev[PER];
+#pragma unroll
+    for (uint32_t r = 0; r < PER; ++r) {  // loads first, clamped (e1 > e0)
+      const uint32_t k = e0 + r * SORT_THREADS + threadIdx.x;
+      ev[r] = tmp[start + (k < e1 ? k : e1 - 1)];
+    }
     __syncthreads();
-    for (uint32_t k = e0 + threadIdx.x; k < e1; k += SORT_THREADS) {
-      const uint2 e = tmp[start + k];
-      const uint32_t lo = e.y & (L - 1);
-      const uint32_t pos = start + atomicAdd(&cur[lo], 1u);
-      key[pos] = bucket0 + lo;
-      idx[pos] = e.x;
+#pragma unroll
+    for (uint32_t r = 0; r < PER; ++r) {
+      if (e0 + r * SORT_THREADS + threadIdx.x < e1) {
+        const uint32_t lo = ev[r].y & (L - 1);
+        const uint32_t pos = start + atomicAdd(&cur[lo], 1u);
+        key[pos] = bucket0 + lo;
+        idx[pos] = ev[r].x;
+      }
     }
     __syncthreads();
   }
@@ -525,12 +568,12 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_add(uint32_t* __restrict_
 
 // Split of the bb bucket bits: enough high bits that a partition of uniformly
 // distributed digits of the largest job holds about max_n / 2^hi <=
-// PART_CAP / 2 entries, at most 8 low bits (pass-2 histogram) and at most 12
+// SORT_PART_TARGET entries, at most 8 low bits (pass-2 histogram) and at most 12
 // high bits (pass-1 histogram).  Also the tile count and count-matrix size.
 void sort_geometry(Plan& pl) {
   const uint32_t bb = (uint32_t)pl.bb;
   uint32_t want = 0;
-  while (want < 12 && (pl.max_n >> want) > PART_CAP / 2) ++want;
+  while (want < 12 && (pl.max_n >> want) > SORT_PART_TARGET) ++want;
   uint32_t hi = std::max<uint32_t>(want, bb > 8 ? bb - 8 : 0);
   hi = std::min<uint32_t>(hi, std::min<uint32_t>(bb, 12));
   pl.hi_bits = hi;
@@ -568,18 +611,21 @@ int launch_sort(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t st) {
   k_scan_block<<<(unsigned)pl.nb, SCAN_THREADS, 0, st>>>(counts, pl.ncounts, blocksums);
   k_scan_top<<<1, SCAN_THREADS, 0, st>>>(blocksums, (uint32_t)pl.nb, total);
   k_scan_add<<<(unsigned)pl.nb, SCAN_THREADS, 0, st>>>(counts, pl.ncounts, blocksums);
-  k_part_scatter<<<(unsigned)pl.tiles, SORT_THREADS, 0, st>>>(g, off, digits, counts, tmp);
+  const size_t scatter_lds = TILE * sizeof(uint2) + 2 * ((size_t)4 << pl.hi_bits);
+  k_part_scatter<<<(unsigned)pl.tiles, SORT_THREADS, scatter_lds, st>>>(g, off, digits, counts, tmp);
   uint32_t* big = ws_at<uint32_t>(ws, pl.o_big);
   uint32_t* bigdesc = ws_at<uint32_t>(ws, pl.o_bigdesc);
   uint32_t* bigcnt = ws_at<uint32_t>(ws, pl.o_bigcnt);
+  uint32_t* bigitem = ws_at<uint32_t>(ws, pl.o_bigitem);
   if ((rc = launch_fill_u32(big, 1, 0u, st)) != MSM_OK) return rc;
   k_part_sort<<<(unsigned)(pl.S << pl.hi_bits), SORT_THREADS, 0, st>>>(
       g, counts, total, pl.ncounts, tmp, key, idx, offsets, buckets, big);
   // large partitions (none for evenly spread digits: these return at once)
-  k_big_plan<<<1, SORT_THREADS, 0, st>>>(g, counts, total, pl.ncounts, big, bigdesc);
-  k_big_count<<<BIG_GRID, SORT_THREADS, 0, st>>>(g, big, bigdesc, tmp, bigcnt);
+  k_big_plan<<<1, SORT_THREADS, 0, st>>>(g, counts, total, pl.ncounts, big, bigdesc, bigitem);
+  k_big_count<<<BIG_GRID, SORT_THREADS, 0, st>>>(g, big, bigdesc, bigitem, tmp, bigcnt);
   k_big_scan<<<BIG_GRID, SORT_THREADS, 0, st>>>(g, big, bigdesc, bigcnt, offsets, buckets);
-  k_big_scatter<<<BIG_GRID, SORT_THREADS, 0, st>>>(g, big, bigdesc, bigcnt, tmp, key, idx);
+  k_big_scatter<<<BIG_GRID, SORT_THREADS, 0, st>>>(g, big, bigdesc, bigitem, bigcnt, tmp, key,
+                                                   idx);
   HIPCHK(hipGetLastError());
   return MSM_OK;
 }

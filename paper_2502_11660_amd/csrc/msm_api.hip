@@ -172,12 +172,14 @@ bool make_plan(const size_t* ns, uint32_t J, int c_req, int encoding, Plan& pl) 
   pl.o_head = take(pl.chunks * rec);
   pl.o_tail = take(pl.chunks * rec);
   pl.o_longlist = take((pl.chunks + 1) * 4);
-  // large sort partitions: each holds more than 8192 entries, so there are
-  // at most NW / 8192 of them and NW / 4096 + that many items of 4096 entries
-  const size_t nbig_max = pl.NW / 8192 + 1;
+  // large sort partitions: each holds more than SORT_PART_CAP entries, so
+  // there are at most NW / SORT_PART_CAP of them, and NW / SORT_BIG_ITEM +
+  // that many items
+  const size_t nbig_max = pl.NW / SORT_PART_CAP + 1;
   pl.o_big = take((nbig_max + 1) * 4);
   pl.o_bigdesc = take((nbig_max + 1) * 16);
-  pl.o_bigcnt = take((pl.NW / 4096 + nbig_max + 1) * 256 * 4);
+  pl.o_bigcnt = take((pl.NW / SORT_BIG_ITEM + nbig_max + 1) * 256 * 4);
+  pl.o_bigitem = take((pl.NW / SORT_BIG_ITEM + nbig_max + 1) * 4);
   // buckets, then the tree levels ping-pong between lvl0 (level 0's M
   // records) and the bucket array, which level 0 has consumed
   pl.o_buckets = take(pl.M * rec);

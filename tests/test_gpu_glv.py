@@ -135,7 +135,7 @@ def test_glv_full_size_closed_form(c):
 def test_glv_sparse_top_window_large_partitions():
     """n = 2^15 with c = 10: the top window keeps 8 digit bits, so its 2^16
     entries crowd about 120 of 512 buckets and each of its first sort
-    partitions (32 buckets) holds ~16k entries, above the 8192-entry LDS stage:
+    partitions (32 buckets) holds ~16k entries, above the LDS stage of the sort (7168 entries):
     the many-block path (several items per partition, many buckets) runs."""
     n = 1 << 15
     seed = inputs.config_seed(4)
