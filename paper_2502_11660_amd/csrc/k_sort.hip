@@ -33,6 +33,7 @@ namespace {
 
 constexpr int SORT_THREADS = 256;
 constexpr uint32_t TILE = SORT_TILE;  // entries per pass-1 tile
+constexpr uint32_t PER_THREAD = TILE / SORT_THREADS;
 constexpr uint32_t PART_CAP = SORT_PART_CAP;  // entries staged in LDS by pass 2
 constexpr unsigned BIG_GRID = 512;    // blocks of the large-partition kernels
 
@@ -138,8 +139,15 @@ __global__ void __launch_bounds__(SORT_THREADS) k_part_count(SortGeom g, uint32_
   __syncthreads();
   const uint32_t e0 = t.tile * TILE, e1 = min(e0 + TILE, t.d.n);
   const uint32_t* dg = digits + (size_t)g.W * t.d.pt_off + (size_t)t.w * t.d.n;
-  for (uint32_t e = e0 + threadIdx.x; e < e1; e += SORT_THREADS) {
-    const uint32_t q = dg[e];
+  uint32_t dq[PER_THREAD];
+#pragma unroll
+  for (uint32_t r = 0; r < PER_THREAD; ++r) {  // loads first, clamped (e1 > e0)
+    const uint32_t e = e0 + r * SORT_THREADS + threadIdx.x;
+    dq[r] = dg[e < e1 ? e : e1 - 1];
+  }
+#pragma unroll
+  for (uint32_t r = 0; r < PER_THREAD; ++r) {
+    const uint32_t q = e0 + r * SORT_THREADS + threadIdx.x < e1 ? dq[r] : 0u;
     if (q) atomicAdd(&hist[bucket_of(q, off) >> g.lo_bits], 1u);
   }
   __syncthreads();
@@ -191,7 +199,6 @@ __device__ uint32_t lds_exclusive_scan(uint32_t* v, uint32_t n) {
 // pass 1b: scatter into (partition, tile) ranges; tmp entry = {idx | sign, key}.
 // The tile is first ordered by partition in LDS, so that consecutive threads
 // write consecutive entries of each partition's range.
-constexpr uint32_t PER_THREAD = TILE / SORT_THREADS;
 __global__ void __launch_bounds__(SORT_THREADS) k_part_scatter(SortGeom g, uint32_t off,
                                                                const uint32_t* __restrict__ digits,
                                                                const uint32_t* __restrict__ scanned,
