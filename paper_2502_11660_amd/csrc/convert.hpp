@@ -1,5 +1,6 @@
 // Field inversion and the Weierstrass <-> twisted-Edwards conversions (device).
 #pragma once
+#include <type_traits>
 #include "common.hpp"
 
 namespace msm {
@@ -107,24 +108,26 @@ __device__ __forceinline__ fe fe_neg_words(const fe& x) {
   return r;
 }
 
-// (x f + y g) / 2^31 for non-negative x, y whose combination is divisible by
-// 2^31 and below 2^384 in magnitude: returns the magnitude, neg = sign
+// (x f + y g) / 2^K for non-negative x, y whose combination is divisible by
+// 2^K and below 2^384 in magnitude: returns the magnitude, neg = sign
+template <int K>
 __device__ __forceinline__ fe comb_shift(const fe& x, const fe& y, int64_t f, int64_t g,
                                          bool& neg) {
   uint32_t w[NL + 1];
   lin_comb(x, y, f, g, w);
   fe r;
 #pragma unroll
-  for (int i = 0; i < NL; ++i) r.v[i] = __builtin_amdgcn_alignbit(w[i + 1], w[i], 31);
+  for (int i = 0; i < NL; ++i) r.v[i] = __builtin_amdgcn_alignbit(w[i + 1], w[i], K);
   neg = (int32_t)w[NL] < 0;
   return neg ? fe_neg_words(r) : r;
 }
 
-// (x f + y g) / 2^31 mod p for canonical x, y; canonical result
+// (x f + y g) / 2^K mod p for canonical x, y; canonical result
+template <int K>
 __device__ __forceinline__ fe comb_shift_mod(const fe& x, const fe& y, int64_t f, int64_t g) {
   uint32_t w[NL + 1];
   lin_comb(x, y, f, g, w);
-  const uint32_t m = (0u - w[0]) & 0x7fffffffu;  // makes the sum divisible by 2^31
+  const uint32_t m = (0u - w[0]) & ((1u << K) - 1u);  // makes the sum divisible by 2^K
   uint32_t r[NL];
   uint64_t c = 0;
 #pragma unroll
@@ -135,11 +138,11 @@ __device__ __forceinline__ fe comb_shift_mod(const fe& x, const fe& y, int64_t f
   const int64_t top = (int64_t)(int32_t)w[NL] + (int64_t)(c >> 32);
   fe q;
 #pragma unroll
-  for (int i = 0; i < NL - 1; ++i) q.v[i] = __builtin_amdgcn_alignbit(r[i + 1], r[i], 31);
-  q.v[NL - 1] = __builtin_amdgcn_alignbit((uint32_t)top, r[NL - 1], 31);
-  // |x f + y g| <= 2^31 p and m p < 2^31 p, so q lies in (-p, 2p)
+  for (int i = 0; i < NL - 1; ++i) q.v[i] = __builtin_amdgcn_alignbit(r[i + 1], r[i], K);
+  q.v[NL - 1] = __builtin_amdgcn_alignbit((uint32_t)top, r[NL - 1], K);
+  // |x f + y g| <= 2^K p and m p < 2^K p, so q lies in (-p, 2p)
   const fe P = fe_const(kP);
-  if ((top >> 31) < 0) return fe_add_c(q, P);
+  if ((top >> K) < 0) return fe_add_c(q, P);
   fe d;
   const uint32_t borrow = fe_sub_c(q, P, d);
   return borrow ? q : d;
@@ -151,50 +154,60 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
          (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
 }
 
-// Plain modular inverse y^-1 mod p of a canonical y (0 for y = 0).  UNIFORM:
-// y is the same in every lane of the wave, and the 31 divsteps of each round
-// then run on the scalar unit.
+// Plain modular inverse y^-1 mod p of a canonical y (0 for y = 0), by rounds of
+// divsteps on 64-bit approximations (the low K bits and the top 64 - K bits of
+// a, b), each round applying its 2x2 transition matrix to the full values.
+// Per lane: 26 rounds of 31 divsteps, 64-bit matrix entries.  UNIFORM (y the
+// same in every lane of the wave): 27 rounds of 30, on the scalar unit, with
+// 32-bit matrix entries (|entry| <= 2^30) and the comparison taken from a
+// subtraction's borrow, which the scalar unit has for 64 bits.
 template <bool UNIFORM = false>
 __device__ __noinline__ fe fe_inv_plain(const fe& y) {
+  constexpr int K = UNIFORM ? 30 : 31;
+  constexpr int ROUNDS = UNIFORM ? 27 : INV_ROUNDS;
+  using mat = typename std::conditional<UNIFORM, int32_t, int64_t>::type;
   fe a = y, b = fe_const(kP), u = fe_zero(), v = fe_zero();
   u.v[0] = 1u;
-  for (int round = 0; round < INV_ROUNDS; ++round) {
+  for (int round = 0; round < ROUNDS; ++round) {
     uint32_t n = bitlen_max(a, b);
     n = n < 64 ? 64u : n;
-    const uint64_t lo31 = 0x7fffffffull;
-    uint64_t ab = (a.v[0] & lo31) | ((bits_at(a, n - 33) & 0x1ffffffffull) << 31);
-    uint64_t bb = (b.v[0] & lo31) | ((bits_at(b, n - 33) & 0x1ffffffffull) << 31);
+    const uint64_t lomask = (1ull << K) - 1, himask = (1ull << (64 - K)) - 1;
+    uint64_t ab = (a.v[0] & lomask) | ((bits_at(a, n - (64 - K)) & himask) << K);
+    uint64_t bb = (b.v[0] & lomask) | ((bits_at(b, n - (64 - K)) & himask) << K);
     if constexpr (UNIFORM) {
       ab = uniform64(ab);
       bb = uniform64(bb);
     }
-    int64_t f0 = 1, g0 = 0, f1 = 0, g1 = 1;
-    for (int j = 0; j < 31; ++j) {
+    mat f0 = 1, g0 = 0, f1 = 0, g1 = 1;
+    for (int j = 0; j < K; ++j) {
       const bool odd = (ab & 1u) != 0;
-      const bool sw = odd && ab < bb;
-      const uint64_t ta = sw ? bb : ab, tb = sw ? ab : bb;
-      const int64_t tf0 = sw ? f1 : f0, tf1 = sw ? f0 : f1;
-      const int64_t tg0 = sw ? g1 : g0, tg1 = sw ? g0 : g1;
-      ab = (odd ? ta - tb : ta) >> 1;
-      bb = tb;
+      unsigned long long d;
+      const bool lt = __builtin_usubll_overflow(ab, bb, &d);  // d = ab - bb, lt = ab < bb
+      const bool sw = odd && lt;
+      const mat tf0 = sw ? f1 : f0, tf1 = sw ? f0 : f1;
+      const mat tg0 = sw ? g1 : g0, tg1 = sw ? g0 : g1;
+      const uint64_t na = odd ? (sw ? (0ull - d) : (uint64_t)d) : ab;  // |ab - bb| or ab
+      bb = sw ? ab : bb;
+      ab = na >> 1;
       f0 = odd ? tf0 - tf1 : tf0;
       g0 = odd ? tg0 - tg1 : tg0;
       f1 = tf1 * 2;
       g1 = tg1 * 2;
     }
+    int64_t F0 = f0, G0 = g0, F1 = f1, G1 = g1;
     bool na, nb;
-    const fe a2 = comb_shift(a, b, f0, g0, na);
-    const fe b2 = comb_shift(a, b, f1, g1, nb);
+    const fe a2 = comb_shift<K>(a, b, F0, G0, na);
+    const fe b2 = comb_shift<K>(a, b, F1, G1, nb);
     if (na) {
-      f0 = -f0;
-      g0 = -g0;
+      F0 = -F0;
+      G0 = -G0;
     }
     if (nb) {
-      f1 = -f1;
-      g1 = -g1;
+      F1 = -F1;
+      G1 = -G1;
     }
-    const fe u2 = comb_shift_mod(u, v, f0, g0);
-    const fe v2 = comb_shift_mod(u, v, f1, g1);
+    const fe u2 = comb_shift_mod<K>(u, v, F0, G0);
+    const fe v2 = comb_shift_mod<K>(u, v, F1, G1);
     a = a2;
     b = b2;
     u = u2;

@@ -523,18 +523,42 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_block(uint32_t* __restric
                                                              uint32_t* __restrict__ blocksums) {
   size_t base = (size_t)blockIdx.x * SCAN_ITEMS + (size_t)threadIdx.x * SCAN_PER_THREAD;
   uint32_t v[SCAN_PER_THREAD];
+  // a thread's 16 words are 64-byte aligned: 16-byte loads when all in range
+  const bool whole = base + SCAN_PER_THREAD <= n;
+  if (whole) {
+    const uint4* q = reinterpret_cast<const uint4*>(data + base);
+#pragma unroll
+    for (int j = 0; j < SCAN_PER_THREAD / 4; ++j) {
+      const uint4 w = q[j];
+      v[4 * j] = w.x;
+      v[4 * j + 1] = w.y;
+      v[4 * j + 2] = w.z;
+      v[4 * j + 3] = w.w;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < SCAN_PER_THREAD; ++j) v[j] = (base + j < n) ? data[base + j] : 0u;
+  }
   uint32_t sum = 0;
 #pragma unroll
-  for (int j = 0; j < SCAN_PER_THREAD; ++j) {
-    v[j] = (base + j < n) ? data[base + j] : 0u;
-    sum += v[j];
-  }
+  for (int j = 0; j < SCAN_PER_THREAD; ++j) sum += v[j];
   uint32_t excl;
   uint32_t total = block_exclusive_scan(sum, excl);
 #pragma unroll
   for (int j = 0; j < SCAN_PER_THREAD; ++j) {
-    if (base + j < n) data[base + j] = excl;
-    excl += v[j];
+    const uint32_t x = v[j];
+    v[j] = excl;
+    excl += x;
+  }
+  if (whole) {
+    uint4* q = reinterpret_cast<uint4*>(data + base);
+#pragma unroll
+    for (int j = 0; j < SCAN_PER_THREAD / 4; ++j)
+      q[j] = make_uint4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < SCAN_PER_THREAD; ++j)
+      if (base + j < n) data[base + j] = v[j];
   }
   if (threadIdx.x == 0) blocksums[blockIdx.x] = total;
 }
