@@ -154,6 +154,35 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
          (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
 }
 
+// Out-of-line product for code that runs once per result (the conversion
+// below): one wave runs it a single time from a cold instruction cache, where
+// ten inlined copies of the multiply cost more in instruction fetch than in
+// arithmetic.  The operands travel as 4-word vectors, which the calling
+// convention keeps in registers (two 12-word structures exceed its register
+// budget for aggregate arguments and would go through memory).
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+__device__ __noinline__ fe fe_mul_outlined(u32x4_t a0, u32x4_t a1, u32x4_t a2, u32x4_t b0,
+                                           u32x4_t b1, u32x4_t b2) {
+  fe a, b;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    a.v[i] = a0[i];
+    a.v[4 + i] = a1[i];
+    a.v[8 + i] = a2[i];
+    b.v[i] = b0[i];
+    b.v[4 + i] = b1[i];
+    b.v[8 + i] = b2[i];
+  }
+  return fe_mul(a, b);
+}
+__device__ __forceinline__ fe fe_mul_cold(const fe& a, const fe& b) {
+  const uint32_t* x = a.v;
+  const uint32_t* y = b.v;
+  return fe_mul_outlined(u32x4_t{x[0], x[1], x[2], x[3]}, u32x4_t{x[4], x[5], x[6], x[7]},
+                         u32x4_t{x[8], x[9], x[10], x[11]}, u32x4_t{y[0], y[1], y[2], y[3]},
+                         u32x4_t{y[4], y[5], y[6], y[7]}, u32x4_t{y[8], y[9], y[10], y[11]});
+}
+
 // Plain modular inverse y^-1 mod p of a canonical y (0 for y = 0), by rounds of
 // divsteps on 64-bit approximations (the low K bits and the top 64 - K bits of
 // a, b), each round applying its 2x2 transition matrix to the full values.
@@ -221,7 +250,7 @@ __device__ __noinline__ fe fe_inv_plain(const fe& y) {
 template <bool UNIFORM = false>
 __device__ __forceinline__ fe fe_inv_mont(const fe& am) {
   fe inv = fe_inv_plain<UNIFORM>(fe_canon(am));
-  return fe_canon(fe_mul(inv, fe_const(kR3)));
+  return fe_canon(fe_mul_cold(inv, fe_const(kR3)));
 }
 
 // Twisted-Edwards extended (Montgomery form) -> Weierstrass affine, ordinary
@@ -237,12 +266,14 @@ __device__ __forceinline__ bool te_to_weierstrass(const xytz& q, fe& xw, fe& yw)
   const fe p2 = fe_const(kP2);
   fe zpy = fe_add(q.Z, q.Y);           // Z + Y
   fe zmy = fe_sub_plus(q.Z, q.Y, p2);  // Z - Y
-  fe inv = fe_inv_mont<UNIFORM>(fe_mul(zmy, q.X));
-  fe u = fe_mul(fe_mul(zpy, q.X), inv);  // (Z + Y) / (Z - Y)
-  fe v = fe_mul(fe_mul(zpy, q.Z), inv);  // u / x_e
-  fe au = fe_mul(u, fe_const(kAlpha));
-  xw = fe_from_mont(fe_sub_plus(au, fe_const(kOne), p2));
-  yw = fe_from_mont(fe_mul(v, fe_const(kBeta)));
+  fe one = fe_zero();
+  one.v[0] = 1u;
+  fe inv = fe_inv_mont<UNIFORM>(fe_mul_cold(zmy, q.X));
+  fe u = fe_mul_cold(fe_mul_cold(zpy, q.X), inv);  // (Z + Y) / (Z - Y)
+  fe v = fe_mul_cold(fe_mul_cold(zpy, q.Z), inv);  // u / x_e
+  fe au = fe_mul_cold(u, fe_const(kAlpha));
+  xw = fe_canon(fe_mul_cold(fe_sub_plus(au, fe_const(kOne), p2), one));  // out of Montgomery form
+  yw = fe_canon(fe_mul_cold(fe_mul_cold(v, fe_const(kBeta)), one));
   return true;
 }
 
