@@ -1,6 +1,5 @@
 // Field inversion and the Weierstrass <-> twisted-Edwards conversions (device).
 #pragma once
-#include <type_traits>
 #include "common.hpp"
 
 namespace msm {
@@ -183,18 +182,65 @@ __device__ __forceinline__ fe fe_mul_cold(const fe& a, const fe& b) {
                          u32x4_t{y[4], y[5], y[6], y[7]}, u32x4_t{y[8], y[9], y[10], y[11]});
 }
 
+// K divsteps of the uniform inversion on the scalar unit.  a = (a1:a0) and
+// b = (b1:b0) are the 64-bit approximations; each matrix row travels packed as
+// one 64-bit integer P = f + g 2^32 (p0: f0, g0; p1: f1, g1), on which the
+// row operations (difference, doubling, swap) act as on the pair, so a divstep
+// is a short run of scalar instructions whose selects all read the scalar
+// condition code: set by the borrow of a - b (a < b), then by a odd and
+// a < b (swap), then by a odd.
+__device__ __forceinline__ void divstep_scalar(uint32_t& a0, uint32_t& a1, uint32_t& b0,
+                                               uint32_t& b1, uint32_t& p0l, uint32_t& p0h,
+                                               uint32_t& p1l, uint32_t& p1h) {
+  uint32_t d0, d1, n0, n1, t, q0l, q0h, e0, e1;
+  asm volatile(
+      "s_sub_u32 %[d0], %[a0], %[b0]\n\t"
+      "s_subb_u32 %[d1], %[a1], %[b1]\n\t"      // d = a - b, SCC = a < b
+      "s_cselect_b32 %[t], 1, 0\n\t"
+      "s_sub_u32 %[n0], 0, %[d0]\n\t"
+      "s_subb_u32 %[n1], 0, %[d1]\n\t"          // n = b - a
+      "s_and_b32 %[t], %[a0], %[t]\n\t"          // SCC = swap = a odd and a < b
+      "s_cselect_b32 %[d0], %[n0], %[d0]\n\t"
+      "s_cselect_b32 %[d1], %[n1], %[d1]\n\t"    // |a - b|
+      "s_cselect_b32 %[q0l], %[p1l], %[p0l]\n\t"
+      "s_cselect_b32 %[q0h], %[p1h], %[p0h]\n\t"
+      "s_cselect_b32 %[p1l], %[p0l], %[p1l]\n\t"
+      "s_cselect_b32 %[p1h], %[p0h], %[p1h]\n\t"  // rows swapped
+      "s_cselect_b32 %[b0], %[a0], %[b0]\n\t"
+      "s_cselect_b32 %[b1], %[a1], %[b1]\n\t"    // b = old a on a swap
+      "s_sub_u32 %[e0], %[q0l], %[p1l]\n\t"
+      "s_subb_u32 %[e1], %[q0h], %[p1h]\n\t"     // row difference
+      "s_bitcmp1_b32 %[a0], 0\n\t"               // SCC = a odd
+      "s_cselect_b32 %[a0], %[d0], %[a0]\n\t"
+      "s_cselect_b32 %[a1], %[d1], %[a1]\n\t"
+      "s_cselect_b32 %[p0l], %[e0], %[q0l]\n\t"
+      "s_cselect_b32 %[p0h], %[e1], %[q0h]\n\t"
+      "s_lshl_b32 %[t], %[a1], 31\n\t"
+      "s_lshr_b32 %[a0], %[a0], 1\n\t"
+      "s_or_b32 %[a0], %[a0], %[t]\n\t"
+      "s_lshr_b32 %[a1], %[a1], 1\n\t"           // a / 2
+      "s_add_u32 %[p1l], %[p1l], %[p1l]\n\t"
+      "s_addc_u32 %[p1h], %[p1h], %[p1h]"          // row 1 doubled
+      : [a0] "+s"(a0), [a1] "+s"(a1), [b0] "+s"(b0), [b1] "+s"(b1), [p0l] "+s"(p0l),
+        [p0h] "+s"(p0h), [p1l] "+s"(p1l), [p1h] "+s"(p1h), [d0] "=&s"(d0), [d1] "=&s"(d1),
+        [n0] "=&s"(n0), [n1] "=&s"(n1), [t] "=&s"(t), [q0l] "=&s"(q0l), [q0h] "=&s"(q0h),
+        [e0] "=&s"(e0), [e1] "=&s"(e1)
+      :
+      : "scc");
+}
+
 // Plain modular inverse y^-1 mod p of a canonical y (0 for y = 0), by rounds of
 // divsteps on 64-bit approximations (the low K bits and the top 64 - K bits of
 // a, b), each round applying its 2x2 transition matrix to the full values.
 // Per lane: 26 rounds of 31 divsteps, 64-bit matrix entries.  UNIFORM (y the
-// same in every lane of the wave): 27 rounds of 30, on the scalar unit, with
-// 32-bit matrix entries (|entry| <= 2^30) and the comparison taken from a
-// subtraction's borrow, which the scalar unit has for 64 bits.
+// same in every lane of the wave): rounds of 30 divsteps on the scalar unit
+// (divstep_scalar; |entry| <= 2^30), at most 27 of them, ending early once
+// a = 0 (b = gcd = 1 then, and v is the inverse): the round count depends on
+// y, which is a public result where this form is used.
 template <bool UNIFORM = false>
 __device__ __noinline__ fe fe_inv_plain(const fe& y) {
   constexpr int K = UNIFORM ? 30 : 31;
   constexpr int ROUNDS = UNIFORM ? 27 : INV_ROUNDS;
-  using mat = typename std::conditional<UNIFORM, int32_t, int64_t>::type;
   fe a = y, b = fe_const(kP), u = fe_zero(), v = fe_zero();
   u.v[0] = 1u;
   for (int round = 0; round < ROUNDS; ++round) {
@@ -207,23 +253,42 @@ __device__ __noinline__ fe fe_inv_plain(const fe& y) {
       ab = uniform64(ab);
       bb = uniform64(bb);
     }
-    mat f0 = 1, g0 = 0, f1 = 0, g1 = 1;
-    for (int j = 0; j < K; ++j) {
-      const bool odd = (ab & 1u) != 0;
-      unsigned long long d;
-      const bool lt = __builtin_usubll_overflow(ab, bb, &d);  // d = ab - bb, lt = ab < bb
-      const bool sw = odd && lt;
-      const mat tf0 = sw ? f1 : f0, tf1 = sw ? f0 : f1;
-      const mat tg0 = sw ? g1 : g0, tg1 = sw ? g0 : g1;
-      const uint64_t na = odd ? (sw ? (0ull - d) : (uint64_t)d) : ab;  // |ab - bb| or ab
-      bb = sw ? ab : bb;
-      ab = na >> 1;
-      f0 = odd ? tf0 - tf1 : tf0;
-      g0 = odd ? tg0 - tg1 : tg0;
-      f1 = tf1 * 2;
-      g1 = tg1 * 2;
+    int64_t F0, G0, F1, G1;
+    if constexpr (UNIFORM) {
+      uint32_t a0 = (uint32_t)ab, a1 = (uint32_t)(ab >> 32), b0 = (uint32_t)bb,
+               b1 = (uint32_t)(bb >> 32);
+      uint32_t p0l = 1u, p0h = 0u, p1l = 0u, p1h = 1u;
+#pragma unroll
+      for (int j = 0; j < K; ++j) divstep_scalar(a0, a1, b0, b1, p0l, p0h, p1l, p1h);
+      // unpack P = f + g 2^32 with |f|, |g| <= 2^30
+      const int64_t P0 = (int64_t)(((uint64_t)p0h << 32) | p0l);
+      const int64_t P1 = (int64_t)(((uint64_t)p1h << 32) | p1l);
+      F0 = (int32_t)p0l;
+      F1 = (int32_t)p1l;
+      G0 = (P0 - F0) >> 32;
+      G1 = (P1 - F1) >> 32;
+    } else {
+      int64_t f0 = 1, g0 = 0, f1 = 0, g1 = 1;
+      for (int j = 0; j < K; ++j) {
+        const bool odd = (ab & 1u) != 0;
+        unsigned long long d;
+        const bool lt = __builtin_usubll_overflow(ab, bb, &d);  // d = ab - bb, lt = ab < bb
+        const bool sw = odd && lt;
+        const int64_t tf0 = sw ? f1 : f0, tf1 = sw ? f0 : f1;
+        const int64_t tg0 = sw ? g1 : g0, tg1 = sw ? g0 : g1;
+        const uint64_t na = odd ? (sw ? (0ull - d) : (uint64_t)d) : ab;  // |ab - bb| or ab
+        bb = sw ? ab : bb;
+        ab = na >> 1;
+        f0 = odd ? tf0 - tf1 : tf0;
+        g0 = odd ? tg0 - tg1 : tg0;
+        f1 = tf1 * 2;
+        g1 = tg1 * 2;
+      }
+      F0 = f0;
+      G0 = g0;
+      F1 = f1;
+      G1 = g1;
     }
-    int64_t F0 = f0, G0 = g0, F1 = f1, G1 = g1;
     bool na, nb;
     const fe a2 = comb_shift<K>(a, b, F0, G0, na);
     const fe b2 = comb_shift<K>(a, b, F1, G1, nb);
@@ -241,6 +306,12 @@ __device__ __noinline__ fe fe_inv_plain(const fe& y) {
     b = b2;
     u = u2;
     v = v2;
+    if constexpr (UNIFORM) {
+      uint32_t o = 0;
+#pragma unroll
+      for (int i = 0; i < NL; ++i) o |= a.v[i];
+      if (__builtin_amdgcn_readfirstlane((int)o) == 0) break;
+    }
   }
   return v;
 }
