@@ -229,98 +229,209 @@ __device__ __forceinline__ void divstep_scalar(uint32_t& a0, uint32_t& a1, uint3
       : "scc");
 }
 
-// Plain modular inverse y^-1 mod p of a canonical y (0 for y = 0), by rounds of
-// divsteps on 64-bit approximations (the low K bits and the top 64 - K bits of
-// a, b), each round applying its 2x2 transition matrix to the full values.
-// Per lane: 26 rounds of 31 divsteps, 64-bit matrix entries.  UNIFORM (y the
-// same in every lane of the wave): rounds of 30 divsteps on the scalar unit
-// (divstep_scalar; |entry| <= 2^30), at most 27 of them, ending early once
-// a = 0 (b = gcd = 1 then, and v is the inverse): the round count depends on
-// y, which is a public result where this form is used.
-template <bool UNIFORM = false>
+// Plain modular inverse y^-1 mod p of a canonical y (0 for y = 0), per lane:
+// 26 rounds of 31 divsteps on 64-bit approximations (the low 31 bits and the
+// top 33 bits of a, b), each round applying its 2x2 transition matrix
+// (64-bit entries) to the full values.
 __device__ __noinline__ fe fe_inv_plain(const fe& y) {
-  constexpr int K = UNIFORM ? 30 : 31;
-  constexpr int ROUNDS = UNIFORM ? 27 : INV_ROUNDS;
+  constexpr int K = 31;
   fe a = y, b = fe_const(kP), u = fe_zero(), v = fe_zero();
   u.v[0] = 1u;
-  for (int round = 0; round < ROUNDS; ++round) {
+  for (int round = 0; round < INV_ROUNDS; ++round) {
     uint32_t n = bitlen_max(a, b);
     n = n < 64 ? 64u : n;
     const uint64_t lomask = (1ull << K) - 1, himask = (1ull << (64 - K)) - 1;
     uint64_t ab = (a.v[0] & lomask) | ((bits_at(a, n - (64 - K)) & himask) << K);
     uint64_t bb = (b.v[0] & lomask) | ((bits_at(b, n - (64 - K)) & himask) << K);
-    if constexpr (UNIFORM) {
-      ab = uniform64(ab);
-      bb = uniform64(bb);
-    }
-    int64_t F0, G0, F1, G1;
-    if constexpr (UNIFORM) {
-      uint32_t a0 = (uint32_t)ab, a1 = (uint32_t)(ab >> 32), b0 = (uint32_t)bb,
-               b1 = (uint32_t)(bb >> 32);
-      uint32_t p0l = 1u, p0h = 0u, p1l = 0u, p1h = 1u;
-#pragma unroll
-      for (int j = 0; j < K; ++j) divstep_scalar(a0, a1, b0, b1, p0l, p0h, p1l, p1h);
-      // unpack P = f + g 2^32 with |f|, |g| <= 2^30
-      const int64_t P0 = (int64_t)(((uint64_t)p0h << 32) | p0l);
-      const int64_t P1 = (int64_t)(((uint64_t)p1h << 32) | p1l);
-      F0 = (int32_t)p0l;
-      F1 = (int32_t)p1l;
-      G0 = (P0 - F0) >> 32;
-      G1 = (P1 - F1) >> 32;
-    } else {
-      int64_t f0 = 1, g0 = 0, f1 = 0, g1 = 1;
-      for (int j = 0; j < K; ++j) {
-        const bool odd = (ab & 1u) != 0;
-        unsigned long long d;
-        const bool lt = __builtin_usubll_overflow(ab, bb, &d);  // d = ab - bb, lt = ab < bb
-        const bool sw = odd && lt;
-        const int64_t tf0 = sw ? f1 : f0, tf1 = sw ? f0 : f1;
-        const int64_t tg0 = sw ? g1 : g0, tg1 = sw ? g0 : g1;
-        const uint64_t na = odd ? (sw ? (0ull - d) : (uint64_t)d) : ab;  // |ab - bb| or ab
-        bb = sw ? ab : bb;
-        ab = na >> 1;
-        f0 = odd ? tf0 - tf1 : tf0;
-        g0 = odd ? tg0 - tg1 : tg0;
-        f1 = tf1 * 2;
-        g1 = tg1 * 2;
-      }
-      F0 = f0;
-      G0 = g0;
-      F1 = f1;
-      G1 = g1;
+    int64_t f0 = 1, g0 = 0, f1 = 0, g1 = 1;
+    for (int j = 0; j < K; ++j) {
+      const bool odd = (ab & 1u) != 0;
+      unsigned long long d;
+      const bool lt = __builtin_usubll_overflow(ab, bb, &d);  // d = ab - bb, lt = ab < bb
+      const bool sw = odd && lt;
+      const int64_t tf0 = sw ? f1 : f0, tf1 = sw ? f0 : f1;
+      const int64_t tg0 = sw ? g1 : g0, tg1 = sw ? g0 : g1;
+      const uint64_t na = odd ? (sw ? (0ull - d) : (uint64_t)d) : ab;  // |ab - bb| or ab
+      bb = sw ? ab : bb;
+      ab = na >> 1;
+      f0 = odd ? tf0 - tf1 : tf0;
+      g0 = odd ? tg0 - tg1 : tg0;
+      f1 = tf1 * 2;
+      g1 = tg1 * 2;
     }
     bool na, nb;
-    const fe a2 = comb_shift<K>(a, b, F0, G0, na);
-    const fe b2 = comb_shift<K>(a, b, F1, G1, nb);
+    const fe a2 = comb_shift<K>(a, b, f0, g0, na);
+    const fe b2 = comb_shift<K>(a, b, f1, g1, nb);
     if (na) {
-      F0 = -F0;
-      G0 = -G0;
+      f0 = -f0;
+      g0 = -g0;
     }
     if (nb) {
-      F1 = -F1;
-      G1 = -G1;
+      f1 = -f1;
+      g1 = -g1;
     }
-    const fe u2 = comb_shift_mod<K>(u, v, F0, G0);
-    const fe v2 = comb_shift_mod<K>(u, v, F1, G1);
+    const fe u2 = comb_shift_mod<K>(u, v, f0, g0);
+    const fe v2 = comb_shift_mod<K>(u, v, f1, g1);
     a = a2;
     b = b2;
     u = u2;
     v = v2;
-    if constexpr (UNIFORM) {
-      uint32_t o = 0;
-#pragma unroll
-      for (int i = 0; i < NL; ++i) o |= a.v[i];
-      if (__builtin_amdgcn_readfirstlane((int)o) == 0) break;
-    }
   }
   return v;
+}
+
+// ---------------------------------------------------------------------------
+// The same inversion for a value held by every lane of a wave (one result per
+// wave), with the lanes put to work: lane 16 s + i holds word i (i < 12;
+// words 12..15 are zero) of segment s's operand pair, (a, b) in segments 0
+// and 1, (u, v) in segments 2 and 3.  A round reads the approximations of a
+// and b out of segment 0 (lane reads), runs its 30 divsteps on the scalar unit
+// (divstep_scalar), and then each segment forms its own combination at once:
+// 0: f0 a + g0 b, 1: f1 a + g1 b, 2: f0 u + g0 v + m p, 3: f1 u + g1 v + m p,
+// one word per lane (64-bit column products), turned into two's complement
+// words by two carry-lookahead passes over 16-lane rows, divided by 2^30 (a
+// funnel shift with the next lane's word), then made non-negative (a, b) or
+// reduced to [0, p) (u, v), and u, v negated mod p where the row of a, b
+// changed sign.  The rounds end once a = 0 (then b = gcd = 1 and v is the
+// inverse; at most 27 rounds cover the 753 divsteps): the round count depends
+// on y, which is a public result where this form is used.
+// ---------------------------------------------------------------------------
+
+constexpr uint64_t kRowTops = 0x8000800080008000ull;  // lane 15 of each row
+
+// Completes per-lane sums x < 2^33 (row-wise multiword additions, word i in
+// lane 16 s + i) by carry lookahead: a lane generates a carry when x >= 2^32
+// and passes one on when its word is all ones; no carry leaves a row.
+__device__ __forceinline__ uint32_t row_carry(uint64_t x) {
+  const uint64_t g = __ballot((x >> 32) != 0u) & ~kRowTops;
+  const uint64_t pp = __ballot((uint32_t)x == 0xffffffffu) & ~kRowTops;
+  const uint64_t gp = g | pp;
+  const uint64_t c = (g + gp) ^ g ^ gp;  // bit l: carry into lane l
+  return (uint32_t)x + (uint32_t)((c >> __lane_id()) & 1u);
+}
+
+// word of the lane below / above in the same row (0 past the row's ends)
+__device__ __forceinline__ uint32_t row_from_below(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x111, 0xF, 0xF, true);
+}
+__device__ __forceinline__ uint32_t row_from_above(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x101, 0xF, 0xF, true);
+}
+
+// word i of a 12-word constant (0 for i >= 12)
+__device__ __forceinline__ uint32_t word_of_const(const uint32_t (&c)[NL], uint32_t i) {
+  uint32_t r = 0u;
+#pragma unroll
+  for (uint32_t k = 0; k < (uint32_t)NL; ++k) r = (i == k) ? c[k] : r;
+  return r;
+}
+
+__device__ __noinline__ fe fe_inv_lanes(const fe& y) {
+  constexpr int K = 30;
+  constexpr int ROUNDS = 27;
+  const uint32_t l = __lane_id(), s = l >> 4, i = l & 15u, top = (l & 48u) | 12u;
+  const uint32_t pw = word_of_const(kP, i);
+  // -(2^31 sum_{j=1..13} 2^(32 j)) mod 2^512, the bias of the high halves
+  const uint32_t negc = i == 0 ? 0u : (i == 1 ? 0x80000000u : (i < 14 ? 0x7fffffffu : ~0u));
+  uint32_t yw = 0u;
+#pragma unroll
+  for (uint32_t k = 0; k < (uint32_t)NL; ++k) yw = (i == k) ? y.v[k] : yw;
+  uint32_t X = s < 2 ? yw : (i == 0 ? 1u : 0u);  // a = y, u = 1
+  uint32_t Y = s < 2 ? pw : 0u;                  // b = p, v = 0
+  for (int round = 0; round < ROUNDS; ++round) {
+    // 64-bit approximations of a and b: the low K bits and the 64 - K bits
+    // below their common bit length
+    const uint32_t w = X | Y;
+    const uint64_t nzw = __ballot(l < 12u && w != 0u);
+    uint32_t n = 0;
+    if (nzw != 0u) {
+      const uint32_t t = 63u - (uint32_t)__builtin_clzll(nzw);
+      const uint32_t wt = (uint32_t)__builtin_amdgcn_readlane((int)w, (int)t);
+      n = 32u * t + 32u - (uint32_t)__builtin_clz(wt);
+    }
+    n = n < 64u ? 64u : n;
+    const uint32_t pos = n - (64 - K), i0 = pos >> 5, sh = pos & 31u;
+    const uint32_t xa0 = (uint32_t)__builtin_amdgcn_readlane((int)X, (int)i0);
+    const uint32_t xa1 = (uint32_t)__builtin_amdgcn_readlane((int)X, (int)i0 + 1);
+    const uint32_t xa2 = (uint32_t)__builtin_amdgcn_readlane((int)X, (int)i0 + 2);
+    const uint32_t xb0 = (uint32_t)__builtin_amdgcn_readlane((int)Y, (int)i0);
+    const uint32_t xb1 = (uint32_t)__builtin_amdgcn_readlane((int)Y, (int)i0 + 1);
+    const uint32_t xb2 = (uint32_t)__builtin_amdgcn_readlane((int)Y, (int)i0 + 2);
+    const uint32_t alo = (uint32_t)__builtin_amdgcn_readlane((int)X, 0);
+    const uint32_t blo = (uint32_t)__builtin_amdgcn_readlane((int)Y, 0);
+    uint64_t ta = ((((uint64_t)xa1) << 32) | xa0) >> sh;
+    uint64_t tb = ((((uint64_t)xb1) << 32) | xb0) >> sh;
+    if (sh) {
+      ta |= (uint64_t)xa2 << (64 - sh);
+      tb |= (uint64_t)xb2 << (64 - sh);
+    }
+    const uint32_t lomask = (1u << K) - 1u;
+    uint32_t a0 = (alo & lomask) | ((uint32_t)ta << K), a1 = (uint32_t)(ta >> (32 - K));
+    uint32_t b0 = (blo & lomask) | ((uint32_t)tb << K), b1 = (uint32_t)(tb >> (32 - K));
+    uint32_t p0l = 1u, p0h = 0u, p1l = 0u, p1h = 1u;
+#pragma unroll
+    for (int j = 0; j < K; ++j) divstep_scalar(a0, a1, b0, b1, p0l, p0h, p1l, p1h);
+    // this segment's row (f, g), unpacked from P = f + g 2^32 (|f|, |g| <= 2^30)
+    const uint32_t pl = (s & 1u) ? p1l : p0l, ph = (s & 1u) ? p1h : p0h;
+    const int32_t f = (int32_t)pl;
+    const int32_t g = (int32_t)((((int64_t)(((uint64_t)ph << 32) | pl)) - f) >> 32);
+    // column products x f + y g, exact in two's complement 64 bits
+    uint64_t t = (uint64_t)X * (uint32_t)f + (uint64_t)Y * (uint32_t)g;
+    // m p with m = -(x f + y g) mod 2^K makes the u, v sums divisible by 2^K
+    const uint32_t m2 = (0u - (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)t, 32)) & lomask;
+    const uint32_t m3 = (0u - (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)t, 48)) & lomask;
+    t += (uint64_t)(s == 2 ? m2 : (s == 3 ? m3 : 0u)) * pw;
+    const uint32_t hi = (uint32_t)(t >> 32) - (f < 0 ? X : 0u) - (g < 0 ? Y : 0u);
+    // two's complement words: low halves plus the high halves of the column
+    // below, biased by 2^31 to keep every word sum non-negative, then the
+    // bias taken off
+    const uint32_t hb = i < 13u ? (hi ^ 0x80000000u) : 0u;
+    const uint32_t U = row_carry((uint64_t)(uint32_t)t + row_from_below(hb));
+    const uint32_t V = row_carry((uint64_t)U + negc);
+    // divided by 2^K; lane 12 holds the sign word
+    const uint32_t Q = __builtin_amdgcn_alignbit(row_from_above(V), V, K);
+    const uint64_t negm = __ballot(i == 12u && (int32_t)Q < 0);
+    const bool neg = ((negm >> top) & 1u) != 0u;
+    // a, b: magnitude (-Q = ~Q + 1); u, v: in (-p, 2p), so Q + p when
+    // negative, else Q - p (= Q + ~p + 1) kept only without a borrow
+    uint32_t xo = Q, yo = 0u;
+    if (s < 2u) {
+      xo = neg ? ~Q : Q;
+      yo = (neg && i == 0u) ? 1u : 0u;
+    } else {
+      yo = neg ? pw : ~pw + (i == 0u ? 1u : 0u);
+    }
+    xo = i <= 12u ? xo : 0u;
+    yo = i <= 12u ? yo : 0u;
+    uint32_t R = row_carry((uint64_t)xo + yo);
+    const uint64_t borm = __ballot(i == 12u && (int32_t)R < 0);
+    R = (s >= 2u && !neg && ((borm >> top) & 1u)) ? Q : R;
+    // u, v negated mod p (p - R, for R != 0) where a, b changed sign
+    const uint64_t nzm = __ballot(i < 12u && R != 0u);
+    const bool nz = ((nzm >> (l & 48u)) & 0xfffu) != 0u;
+    const bool dn = s >= 2u && nz && ((negm >> (((s - 2u) << 4) | 12u)) & 1u);
+    xo = i < 12u ? (dn ? ~R : R) : 0u;
+    yo = (dn && i < 12u) ? pw + (i == 0u ? 1u : 0u) : 0u;
+    R = row_carry((uint64_t)xo + yo);
+    R = i < 12u ? R : 0u;
+    // segment pairs exchange their results: (a, b) and (u, v) again
+    const uint32_t Rp = (uint32_t)__builtin_amdgcn_ds_swizzle((int)R, 0x401F);
+    X = (s & 1u) ? Rp : R;
+    Y = (s & 1u) ? R : Rp;
+    if (__ballot(l < 12u && X != 0u) == 0u) break;  // a = 0
+  }
+  fe r;
+#pragma unroll
+  for (int k = 0; k < NL; ++k) r.v[k] = (uint32_t)__builtin_amdgcn_readlane((int)Y, 32 + k);
+  return r;
 }
 
 // Inverse in Montgomery form: (aR)^-1 R^3 R^-1 = a^-1 R.  Input any value < 2p
 // representing aR; output canonical.
 template <bool UNIFORM = false>
 __device__ __forceinline__ fe fe_inv_mont(const fe& am) {
-  fe inv = fe_inv_plain<UNIFORM>(fe_canon(am));
+  const fe c = fe_canon(am);
+  fe inv = UNIFORM ? fe_inv_lanes(c) : fe_inv_plain(c);
   return fe_canon(fe_mul_cold(inv, fe_const(kR3)));
 }
 
