@@ -182,51 +182,39 @@ __device__ __forceinline__ fe fe_mul_cold(const fe& a, const fe& b) {
                          u32x4_t{y[4], y[5], y[6], y[7]}, u32x4_t{y[8], y[9], y[10], y[11]});
 }
 
-// K divsteps of the uniform inversion on the scalar unit.  a = (a1:a0) and
-// b = (b1:b0) are the 64-bit approximations; each matrix row travels packed as
-// one 64-bit integer P = f + g 2^32 (p0: f0, g0; p1: f1, g1), on which the
-// row operations (difference, doubling, swap) act as on the pair, so a divstep
-// is a short run of scalar instructions whose selects all read the scalar
-// condition code: set by the borrow of a - b (a < b), then by a odd and
-// a < b (swap), then by a odd.
-__device__ __forceinline__ void divstep_scalar(uint32_t& a0, uint32_t& a1, uint32_t& b0,
-                                               uint32_t& b1, uint32_t& p0l, uint32_t& p0h,
-                                               uint32_t& p1l, uint32_t& p1h) {
-  uint32_t d0, d1, n0, n1, t, q0l, q0h, e0, e1;
+// 30 divsteps of the uniform inversion on the scalar unit.  a and b are the
+// 64-bit approximations; each matrix row travels packed as one 64-bit integer
+// P = f + g 2^32 (P0: f0, g0; P1: f1, g1), on which the row operations
+// (difference, doubling, swap) act as on the pair.  A divstep is 17 scalar
+// instructions whose selects read the scalar condition code: set by the
+// borrow of a - b (a < b), then by a odd and a < b (swap), then by a odd.
+// The operands sit in fixed register pairs so that the 64-bit selects and
+// shifts can name their halves.
+__device__ __forceinline__ void divsteps30_scalar(uint64_t& a, uint64_t& b, uint64_t& P0,
+                                                  uint64_t& P1) {
   asm volatile(
-      "s_sub_u32 %[d0], %[a0], %[b0]\n\t"
-      "s_subb_u32 %[d1], %[a1], %[b1]\n\t"      // d = a - b, SCC = a < b
-      "s_cselect_b32 %[t], 1, 0\n\t"
-      "s_sub_u32 %[n0], 0, %[d0]\n\t"
-      "s_subb_u32 %[n1], 0, %[d1]\n\t"          // n = b - a
-      "s_and_b32 %[t], %[a0], %[t]\n\t"          // SCC = swap = a odd and a < b
-      "s_cselect_b32 %[d0], %[n0], %[d0]\n\t"
-      "s_cselect_b32 %[d1], %[n1], %[d1]\n\t"    // |a - b|
-      "s_cselect_b32 %[q0l], %[p1l], %[p0l]\n\t"
-      "s_cselect_b32 %[q0h], %[p1h], %[p0h]\n\t"
-      "s_cselect_b32 %[p1l], %[p0l], %[p1l]\n\t"
-      "s_cselect_b32 %[p1h], %[p0h], %[p1h]\n\t"  // rows swapped
-      "s_cselect_b32 %[b0], %[a0], %[b0]\n\t"
-      "s_cselect_b32 %[b1], %[a1], %[b1]\n\t"    // b = old a on a swap
-      "s_sub_u32 %[e0], %[q0l], %[p1l]\n\t"
-      "s_subb_u32 %[e1], %[q0h], %[p1h]\n\t"     // row difference
-      "s_bitcmp1_b32 %[a0], 0\n\t"               // SCC = a odd
-      "s_cselect_b32 %[a0], %[d0], %[a0]\n\t"
-      "s_cselect_b32 %[a1], %[d1], %[a1]\n\t"
-      "s_cselect_b32 %[p0l], %[e0], %[q0l]\n\t"
-      "s_cselect_b32 %[p0h], %[e1], %[q0h]\n\t"
-      "s_lshl_b32 %[t], %[a1], 31\n\t"
-      "s_lshr_b32 %[a0], %[a0], 1\n\t"
-      "s_or_b32 %[a0], %[a0], %[t]\n\t"
-      "s_lshr_b32 %[a1], %[a1], 1\n\t"           // a / 2
-      "s_add_u32 %[p1l], %[p1l], %[p1l]\n\t"
-      "s_addc_u32 %[p1h], %[p1h], %[p1h]"          // row 1 doubled
-      : [a0] "+s"(a0), [a1] "+s"(a1), [b0] "+s"(b0), [b1] "+s"(b1), [p0l] "+s"(p0l),
-        [p0h] "+s"(p0h), [p1l] "+s"(p1l), [p1h] "+s"(p1h), [d0] "=&s"(d0), [d1] "=&s"(d1),
-        [n0] "=&s"(n0), [n1] "=&s"(n1), [t] "=&s"(t), [q0l] "=&s"(q0l), [q0h] "=&s"(q0h),
-        [e0] "=&s"(e0), [e1] "=&s"(e1)
+      ".rept 30\n\t"
+      "s_sub_u32 s88, s80, s82\n\t"
+      "s_subb_u32 s89, s81, s83\n\t"                  // d = a - b, SCC = a < b
+      "s_cselect_b32 s96, 1, 0\n\t"
+      "s_sub_u32 s90, 0, s88\n\t"
+      "s_subb_u32 s91, 0, s89\n\t"                    // n = b - a
+      "s_and_b32 s96, s80, s96\n\t"                   // SCC = swap: a odd, a < b
+      "s_cselect_b64 s[88:89], s[90:91], s[88:89]\n\t"  // |a - b|
+      "s_cselect_b64 s[92:93], s[86:87], s[84:85]\n\t"  // rows swapped: q0 ...
+      "s_cselect_b64 s[86:87], s[84:85], s[86:87]\n\t"  // ... and P1
+      "s_cselect_b64 s[82:83], s[80:81], s[82:83]\n\t"  // b = old a on a swap
+      "s_sub_u32 s94, s92, s86\n\t"
+      "s_subb_u32 s95, s93, s87\n\t"                  // row difference q0 - P1
+      "s_bitcmp1_b32 s80, 0\n\t"                      // SCC = a odd
+      "s_cselect_b64 s[80:81], s[88:89], s[80:81]\n\t"
+      "s_cselect_b64 s[84:85], s[94:95], s[92:93]\n\t"
+      "s_lshr_b64 s[80:81], s[80:81], 1\n\t"          // a / 2
+      "s_lshl_b64 s[86:87], s[86:87], 1\n\t"          // row 1 doubled
+      ".endr"
+      : "+{s[80:81]}"(a), "+{s[82:83]}"(b), "+{s[84:85]}"(P0), "+{s[86:87]}"(P1)
       :
-      : "scc");
+      : "s88", "s89", "s90", "s91", "s92", "s93", "s94", "s95", "s96", "scc");
 }
 
 // Plain modular inverse y^-1 mod p of a canonical y (0 for y = 0), per lane:
@@ -286,7 +274,7 @@ __device__ __noinline__ fe fe_inv_plain(const fe& y) {
 // words 12..15 are zero) of segment s's operand pair, (a, b) in segments 0
 // and 1, (u, v) in segments 2 and 3.  A round reads the approximations of a
 // and b out of segment 0 (lane reads), runs its 30 divsteps on the scalar unit
-// (divstep_scalar), and then each segment forms its own combination at once:
+// (divsteps30_scalar), and then each segment forms its own combination at once:
 // 0: f0 a + g0 b, 1: f1 a + g1 b, 2: f0 u + g0 v + m p, 3: f1 u + g1 v + m p,
 // one word per lane (64-bit column products), turned into two's complement
 // words by two carry-lookahead passes over 16-lane rows, divided by 2^30 (a
@@ -366,15 +354,14 @@ __device__ __noinline__ fe fe_inv_lanes(const fe& y) {
       tb |= (uint64_t)xb2 << (64 - sh);
     }
     const uint32_t lomask = (1u << K) - 1u;
-    uint32_t a0 = (alo & lomask) | ((uint32_t)ta << K), a1 = (uint32_t)(ta >> (32 - K));
-    uint32_t b0 = (blo & lomask) | ((uint32_t)tb << K), b1 = (uint32_t)(tb >> (32 - K));
-    uint32_t p0l = 1u, p0h = 0u, p1l = 0u, p1h = 1u;
-#pragma unroll
-    for (int j = 0; j < K; ++j) divstep_scalar(a0, a1, b0, b1, p0l, p0h, p1l, p1h);
+    uint64_t ab = (alo & lomask) | (ta << K), bb = (blo & lomask) | (tb << K);
+    uint64_t P0 = 1u, P1 = 1ull << 32;
+    static_assert(K == 30, "divsteps30_scalar runs 30 divsteps");
+    divsteps30_scalar(ab, bb, P0, P1);
     // this segment's row (f, g), unpacked from P = f + g 2^32 (|f|, |g| <= 2^30)
-    const uint32_t pl = (s & 1u) ? p1l : p0l, ph = (s & 1u) ? p1h : p0h;
-    const int32_t f = (int32_t)pl;
-    const int32_t g = (int32_t)((((int64_t)(((uint64_t)ph << 32) | pl)) - f) >> 32);
+    const uint64_t P = (s & 1u) ? P1 : P0;
+    const int32_t f = (int32_t)(uint32_t)P;
+    const int32_t g = (int32_t)(((int64_t)P - f) >> 32);
     // column products x f + y g, exact in two's complement 64 bits
     uint64_t t = (uint64_t)X * (uint32_t)f + (uint64_t)Y * (uint32_t)g;
     // m p with m = -(x f + y g) mod 2^K makes the u, v sums divisible by 2^K
