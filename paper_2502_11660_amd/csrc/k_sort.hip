@@ -79,48 +79,59 @@ __device__ __forceinline__ size_t count_index(const SortGeom& g, const JobDesc& 
   return (seg_tile0 << g.hi_bits) + (size_t)hi * d.tps + tile;
 }
 
+// One signed digit: v (the window's c bits) plus the carry of the window
+// below, as q | sign << 31; negative (v - 2^c) from 2^(c-1) on, except in
+// the top window, which takes the carry.
+__device__ __forceinline__ uint32_t signed_digit(uint32_t v0, uint32_t& carry, int c, bool top) {
+  const uint32_t v = v0 + carry;
+  if (v >= (1u << (c - 1)) && !top) {  // d = v - 2^c < 0
+    carry = 1;
+    return ((1u << c) - v) | (v == (1u << c) ? 0u : 0x80000000u);
+  }
+  carry = 0;
+  return v;
+}
+
 // Digits of every window of every job.  Word (segment s = j W + w, point i)
 // at W pt_off + w n + i holds q | sign << 31, where q = 0 drops the entry and
 // otherwise bucket m = q - 1 (signed digits, q = |d|) or m = q (unsigned
 // digits, q = d, so unsigned bucket 0 never receives points).  With the
 // endomorphism split a job's n points are its n / 2 input points and their
 // images, interleaved: point 2i takes the digits of s0 of scalar i, point
-// 2i + 1 those of s1.
+// 2i + 1 those of s1; one thread splits scalar i and writes both digit words
+// of each window (n and pt_off are even there).  N counts threads: points,
+// or point pairs with the split.
 __global__ void __launch_bounds__(256) k_slice(JobView jv, uint32_t N, int c, int W, int encoding,
                                                uint32_t* __restrict__ digits,
                                                uint32_t* __restrict__ flags) {
-  const uint32_t gi = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gi >= N) return;
+  const uint32_t gt = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gt >= N) return;
+  const uint32_t gi = encoding == MSM_DIGITS_GLV ? 2u * gt : gt;  // first point
   const uint32_t j = jv.tab ? find_job(jv.J, gi, [&](uint32_t k) { return jv.tab[k].pt_off; }) : 0u;
   const JobDesc d = jv.get(j);
   const uint32_t i = gi - d.pt_off;
   uint32_t* out = digits + (size_t)W * d.pt_off + i;
-  scalar256 s;
   if (encoding == MSM_DIGITS_GLV) {
     scalar256 s0, s1;
     glv_split(ld_scalar(d.scalars, i >> 1, flags + j), s0, s1);
-    s = (i & 1u) ? s1 : s0;
-  } else {
-    s = ld_scalar(d.scalars, i, flags + j);
+    uint2* out2 = reinterpret_cast<uint2*>(out);
+    uint32_t carry0 = 0, carry1 = 0;
+    for (int w = 0; w < W; ++w) {
+      const bool top = w + 1 == W;
+      uint2 q;
+      q.x = signed_digit(digit_at(s0, w * c, c), carry0, c, top);
+      q.y = signed_digit(digit_at(s1, w * c, c), carry1, c, top);
+      out2[(size_t)w * (d.n >> 1)] = q;
+    }
+    return;
   }
+  const scalar256 s = ld_scalar(d.scalars, i, flags + j);
   if (encoding == MSM_DIGITS_UNSIGNED) {
     for (int w = 0; w < W; ++w) out[(size_t)w * d.n] = digit_at(s, w * c, c);
     return;
   }
-  const uint32_t half = 1u << (c - 1);
   uint32_t carry = 0;
-  for (int w = 0; w < W; ++w) {
-    const uint32_t v = digit_at(s, w * c, c) + carry;
-    uint32_t q;
-    if (v >= half && w + 1 < W) {  // d = v - 2^c < 0
-      q = ((1u << c) - v) | (v == (1u << c) ? 0u : 0x80000000u);
-      carry = 1;
-    } else {
-      q = v;
-      carry = 0;
-    }
-    out[(size_t)w * d.n] = q;
-  }
+  for (int w = 0; w < W; ++w) out[(size_t)w * d.n] = signed_digit(digit_at(s, w * c, c), carry, c, w + 1 == W);
 }
 
 // bucket index and the entry's index word of a digit word q != 0
@@ -636,8 +647,9 @@ int launch_sort(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t st) {
 
   int rc;
   if ((rc = launch_fill_u32(flags, pl.J, 0u, st)) != MSM_OK) return rc;
-  k_slice<<<grid_for(pl.N, 256), 256, 0, st>>>(g.jv, (uint32_t)pl.N, pl.c, pl.W, pl.encoding,
-                                                digits, flags);
+  const size_t slice_threads = pl.encoding == MSM_DIGITS_GLV ? pl.N / 2 : pl.N;
+  k_slice<<<grid_for(slice_threads, 256), 256, 0, st>>>(g.jv, (uint32_t)slice_threads, pl.c, pl.W,
+                                                        pl.encoding, digits, flags);
   k_part_count<<<(unsigned)pl.tiles, SORT_THREADS, 0, st>>>(g, off, digits, counts);
   k_scan_block<<<(unsigned)pl.nb, SCAN_THREADS, 0, st>>>(counts, pl.ncounts, blocksums);
   k_scan_top<<<1, SCAN_THREADS, 0, st>>>(blocksums, (uint32_t)pl.nb, total);
