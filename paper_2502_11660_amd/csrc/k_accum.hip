@@ -204,8 +204,7 @@ int launch_accumulate(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t s
   const int64_t* segoff = pl.J == 1 ? nullptr : ws_at<const int64_t>(ws, pl.o_segoff);
   const uint32_t K = pl.K, M = (uint32_t)pl.M;
   const unsigned grid = grid_for(pl.chunks, 256);
-  int rc;
-  if ((rc = launch_fill_u32(longlist, 1, 0u, st)) != MSM_OK) return rc;
+  // longlist[0] was cleared by the digit sort's scatter pass
   {
     ProfScope prof(PT_ACCUM, st);
     k_accum<<<grid, 256, 0, st>>>(pl.one.xyu, segoff, (uint32_t)pl.bb, key, idx, offsets, M, K,

@@ -88,6 +88,87 @@ __global__ void __launch_bounds__(256) k_tree_level_quad(const uint32_t* __restr
   quad_st(out + rec_index(w, nodes_out, n, slots_out, s) * XYTZ_WORDS, r);
 }
 
+// Same level, one wide unit (two waves) per output record, for levels with
+// few outputs, where the latency of one addition sets the level's time.  The
+// operands carry T (not U = k T), so the complete addition takes three
+// product phases, four products per phase across the unit's four half-waves:
+//   1: A = (Y1 - X1)(Y2 - X2), B = (Y1 + X1)(Y2 + X2), D = 2 Z1 Z2, V = T1 T2
+//   2: C = k V, T3 = E H                      (E = B - A, H = B + A)
+//   3: X3 = E F, Y3 = G H, Z3 = F G, T3 or U3 = k T3   (F = D - C, G = D + C)
+// (subtractions add the pre-borrowed 3p).  The copy of R.S (output slot h)
+// runs phase 3 alone on (X2, Y2, Z2, T2) times (1, 1, 1, 1 or k).  Every
+// input below 2p gives products below 1.2p and product operands below 6p.
+__global__ void __launch_bounds__(128) k_tree_level_wide(const uint32_t* __restrict__ in,
+                                                         uint32_t h, uint32_t nodes_in,
+                                                         uint32_t w_lo, uint32_t w_cnt,
+                                                         uint32_t* __restrict__ out, int to_u) {
+  __shared__ wunit_lds<2> s;
+  const uint32_t nodes_out = nodes_in >> 1, slots_in = h + 1, slots_out = h + 2;
+  const uint64_t g = blockIdx.x;  // one output record per block
+  if (g >= (uint64_t)w_cnt * nodes_out * slots_out) return;
+  const uint32_t slot = (uint32_t)(g % slots_out);
+  const uint32_t t = (uint32_t)(g / slots_out);
+  const uint32_t n = t % nodes_out, w = w_lo + t / nodes_out;
+  const uint32_t src = slot < h ? slot : h;
+  const uint32_t* L = in + rec_index(w, nodes_in, 2 * n, slots_in, src) * XYTZ_WORDS;
+  const uint32_t* R = in + rec_index(w, nodes_in, 2 * n + 1, slots_in, src) * XYTZ_WORDS;
+  wunit_init(s);
+  // operand limbs: thread e loads limb e & 15 of coordinate (e >> 4) & 3 of
+  // L (e < 64, into acc) or R (into opd[0])
+  {
+    const uint32_t e = threadIdx.x, coord = (e >> 4) & 3u, j = e & 15u;
+    const limb_src v = wu_fetch(e < 64 ? L : R, coord, j);
+    (e < 64 ? s.acc : s.opd[0])[16 * coord + j] = limb_extract(v, j);
+  }
+  unit_sync();
+  const wslot q = wslot_here();
+  const uint32_t wave = threadIdx.x >> 6;
+  uint32_t* P1 = s.prod[0];  // A, B, D, V
+  uint32_t* P2 = s.prod[1];  // C, T3
+  uint32_t* O = s.opd[1];    // output X, Y, T or U, Z
+  const uint32_t c3 = s.c3p[q.j];
+  uint32_t l3, r3;           // this half's phase-3 operands
+  if (slot == h) {
+    const uint32_t* R2 = s.opd[0];
+    l3 = q.k == 3 ? (to_u ? limb_of_const(kK, q.j) : limb_of_const(kOne, q.j))
+                  : limb_of_const(kOne, q.j);
+    r3 = R2[16 * (q.k == 2 ? 3u : (q.k == 3 ? 2u : q.k)) + q.j];  // X2, Y2, Z2, T2
+  } else {
+    {
+      const uint32_t* X = s.acc;
+      const uint32_t* Y = s.opd[0];
+      const uint32_t x1 = X[q.j], y1 = X[16 + q.j], x2 = Y[q.j], y2 = Y[16 + q.j];
+      uint32_t l = q.k == 0 ? (y1 + c3) - x1 : (q.k == 1 ? y1 + x1 : X[16 * (5u - q.k) + q.j]);
+      uint32_t r = q.k == 0 ? (y2 + c3) - x2 : (q.k == 1 ? y2 + x2 : Y[16 * (5u - q.k) + q.j]);
+      uint32_t v = wmul2_hi(q.act ? l : 0u, q.act ? r : 0u, s.mul[wave]);  // A, B, Z1 Z2, T1 T2
+      if (q.k == 2) v <<= 1;                                               // D = 2 Z1 Z2
+      if (!q.act) P1[16 * q.k + q.j] = v;
+    }
+    unit_sync();
+    const uint32_t A = P1[q.j], B = P1[16 + q.j];
+    if (wave == 0) {
+      const uint32_t l = q.k == 0 ? limb_of_const(kK, q.j) : (B + c3) - A;
+      const uint32_t r = q.k == 0 ? P1[48 + q.j] : B + A;
+      const uint32_t v = wmul2_hi(q.act ? l : 0u, q.act ? r : 0u, s.mul[0]);  // C, T3
+      if (!q.act) P2[16 * q.k + q.j] = v;
+    }
+    unit_sync();
+    const uint32_t D = P1[32 + q.j], C = P2[q.j];
+    const uint32_t E = (B + c3) - A, H = B + A, F = (D + c3) - C, G = D + C;
+    l3 = q.k == 0 ? E : (q.k == 1 ? G : (q.k == 2 ? F : (to_u ? limb_of_const(kK, q.j)
+                                                             : limb_of_const(kOne, q.j))));
+    r3 = q.k == 0 ? F : (q.k == 1 ? H : (q.k == 2 ? G : P2[16 + q.j]));
+  }
+  const uint32_t v = wmul2_hi(q.act ? l3 : 0u, q.act ? r3 : 0u, s.mul[wave]);
+  // X3, Y3, Z3, T3 / U3 to coordinates 0, 1, 3, 2
+  if (!q.act) O[16 * (q.k == 2 ? 3u : (q.k == 3 ? 2u : q.k)) + q.j] = v;
+  __syncthreads();  // the record's coordinates come from both waves
+  const uint32_t lane = wlane();
+  if (wave == 0 && lane < 4)
+    st_aos(out + rec_index(w, nodes_out, n, slots_out, slot) * XYTZ_WORDS, (int)lane,
+           words_of_limbs(O + 16 * lane));
+}
+
 // Per window (block w, one wide unit): S_w = sum_t 2^t X_t (+ S for signed
 // digits) by Horner's rule over the bits t, with X_t (slot t < bb of the
 // tree's root) and S (slot bb) in XYUZ form.  Writes S_w as XYTZ (record 2w)
@@ -183,8 +264,10 @@ __global__ void __launch_bounds__(64) k_finalize(const uint32_t* __restrict__ qs
   for (int l = 2 * NL + 2; l < MSM_RESULT_WORDS; ++l) result[l] = 0u;
 }
 
-// below this many outputs a tree level runs on quads
+// below this many outputs a tree level runs on quads, and up to WIDE_UPTO
+// outputs on wide units (one per output)
 constexpr uint64_t QUAD_BELOW = 65536;
+constexpr uint64_t WIDE_UPTO = 1024;
 
 }  // namespace
 
@@ -202,9 +285,11 @@ int launch_aggregate(const Plan& pl, const uint32_t* buckets, void* ws, hipStrea
     const uint64_t adds = (uint64_t)S * (nodes >> 1) * (h + 1);
     if (outs >= QUAD_BELOW)
       k_tree_level<<<(unsigned)((adds + 255) / 256), 256, 0, st>>>(in, h, nodes, 0, S, out, to_u);
-    else
+    else if (outs > WIDE_UPTO)
       k_tree_level_quad<<<(unsigned)((4 * outs + 255) / 256), 256, 0, st>>>(in, h, nodes, 0, S,
                                                                            out, to_u);
+    else
+      k_tree_level_wide<<<(unsigned)outs, 128, 0, st>>>(in, h, nodes, 0, S, out, to_u);
     in = out;
     nodes >>= 1;
   }

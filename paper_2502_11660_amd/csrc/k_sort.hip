@@ -213,7 +213,15 @@ __device__ uint32_t lds_exclusive_scan(uint32_t* v, uint32_t n) {
 __global__ void __launch_bounds__(SORT_THREADS) k_part_scatter(SortGeom g, uint32_t off,
                                                                const uint32_t* __restrict__ digits,
                                                                const uint32_t* __restrict__ scanned,
-                                                               uint2* __restrict__ tmp) {
+                                                               uint2* __restrict__ tmp,
+                                                               uint32_t* __restrict__ clear0,
+                                                               uint32_t* __restrict__ clear1) {
+  // two list counters of later passes start at zero (the large-partition
+  // list of pass 2 and the long-merge list of the accumulation)
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *clear0 = 0u;
+    *clear1 = 0u;
+  }
   // dynamic LDS, sized by the launch for H = 2^hi_bits partitions: the tile
   // stage, then per partition its global start and its local count / start
   extern __shared__ uint2 scatter_lds[];
@@ -655,12 +663,12 @@ int launch_sort(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t st) {
   k_scan_top<<<1, SCAN_THREADS, 0, st>>>(blocksums, (uint32_t)pl.nb, total);
   k_scan_add<<<(unsigned)pl.nb, SCAN_THREADS, 0, st>>>(counts, pl.ncounts, blocksums);
   const size_t scatter_lds = TILE * sizeof(uint2) + 2 * ((size_t)4 << pl.hi_bits);
-  k_part_scatter<<<(unsigned)pl.tiles, SORT_THREADS, scatter_lds, st>>>(g, off, digits, counts, tmp);
   uint32_t* big = ws_at<uint32_t>(ws, pl.o_big);
   uint32_t* bigdesc = ws_at<uint32_t>(ws, pl.o_bigdesc);
   uint32_t* bigcnt = ws_at<uint32_t>(ws, pl.o_bigcnt);
   uint32_t* bigitem = ws_at<uint32_t>(ws, pl.o_bigitem);
-  if ((rc = launch_fill_u32(big, 1, 0u, st)) != MSM_OK) return rc;
+  k_part_scatter<<<(unsigned)pl.tiles, SORT_THREADS, scatter_lds, st>>>(
+      g, off, digits, counts, tmp, big, ws_at<uint32_t>(ws, pl.o_longlist));
   k_part_sort<<<(unsigned)(pl.S << pl.hi_bits), SORT_THREADS, 0, st>>>(
       g, counts, total, pl.ncounts, tmp, key, idx, offsets, buckets, big);
   // large partitions (none for evenly spread digits: these return at once)
