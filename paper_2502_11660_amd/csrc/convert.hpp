@@ -154,9 +154,9 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
 }
 
 // Out-of-line product for code that runs once per result (the conversion
-// below): one wave runs it a single time from a cold instruction cache, where
-// ten inlined copies of the multiply cost more in instruction fetch than in
-// arithmetic.  The operands travel as 4-word vectors, which the calling
+// below): inlined, its ten multiplies make a long straight-line kernel that
+// each wave runs once from a cold instruction cache, where instruction fetch
+// costs more than the arithmetic.  The operands travel as 4-word vectors, which the calling
 // convention keeps in registers (two 12-word structures exceed its register
 // budget for aggregate arguments and would go through memory).
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
@@ -314,7 +314,7 @@ __device__ __forceinline__ uint32_t word_of_const(const uint32_t (&c)[NL], uint3
   return r;
 }
 
-__device__ __noinline__ fe fe_inv_lanes(const fe& y) {
+__device__ __noinline__ fe fe_inv_lanes(fe y) {  // by value: kept in registers
   constexpr int K = 30;
   constexpr int ROUNDS = 27;
   const uint32_t l = __lane_id(), s = l >> 4, i = l & 15u, top = (l & 48u) | 12u;
@@ -415,16 +415,13 @@ __device__ __noinline__ fe fe_inv_lanes(const fe& y) {
 
 // Inverse in Montgomery form: (aR)^-1 R^3 R^-1 = a^-1 R.  Input any value < 2p
 // representing aR; output canonical.
-template <bool UNIFORM = false>
 __device__ __forceinline__ fe fe_inv_mont(const fe& am) {
-  const fe c = fe_canon(am);
-  fe inv = UNIFORM ? fe_inv_lanes(c) : fe_inv_plain(c);
+  fe inv = fe_inv_plain(fe_canon(am));
   return fe_canon(fe_mul_cold(inv, fe_const(kR3)));
 }
 
 // Twisted-Edwards extended (Montgomery form) -> Weierstrass affine, ordinary
 // form, canonical.  Returns false for the identity (x = y = 0 written).
-template <bool UNIFORM = false>
 __device__ __forceinline__ bool te_to_weierstrass(const xytz& q, fe& xw, fe& yw) {
   fe X = fe_canon(q.X);
   if (fe_is_zero_canon(X)) {
@@ -437,7 +434,7 @@ __device__ __forceinline__ bool te_to_weierstrass(const xytz& q, fe& xw, fe& yw)
   fe zmy = fe_sub_plus(q.Z, q.Y, p2);  // Z - Y
   fe one = fe_zero();
   one.v[0] = 1u;
-  fe inv = fe_inv_mont<UNIFORM>(fe_mul_cold(zmy, q.X));
+  fe inv = fe_inv_mont(fe_mul_cold(zmy, q.X));
   fe u = fe_mul_cold(fe_mul_cold(zpy, q.X), inv);  // (Z + Y) / (Z - Y)
   fe v = fe_mul_cold(fe_mul_cold(zpy, q.Z), inv);  // u / x_e
   fe au = fe_mul_cold(u, fe_const(kAlpha));

@@ -243,16 +243,59 @@ __global__ void __launch_bounds__(128) k_horner_wide(const uint32_t* __restrict_
   if (threadIdx.x < 64) wu_store_acc(s, qstate + (size_t)job * XYTZ_WORDS);
 }
 
-// The affine Weierstrass result of each job, one wave per job (all lanes
-// compute the same values, so the inversion's divsteps run on the scalar
-// unit; lane 0 writes).
+// Twisted-Edwards extended (Montgomery form) -> Weierstrass affine, ordinary
+// form, canonical, on one wave whose lanes all hold Q: the field inversion is
+// lane-parallel (fe_inv_lanes) and the ten products around it run as wide
+// products, two per step (one per half-wave), in five dependent steps:
+//   d = (Z - Y) X, un = (Z + Y) X;   [d^-1]   im = d^-1 R^3 (Montgomery
+//   inverse), vn = (Z + Y) Z;   u = un im, v = vn im;   u alpha, v beta;
+//   x = (u alpha - 1) / R, y = v beta / R (out of Montgomery form).
+// Returns false for the identity (x = y = 0 written).
+__device__ bool wide_to_weierstrass(const xytz& Q, fe& xw, fe& yw, uint32_t* mul,
+                                    uint32_t* stage) {
+  if (fe_is_zero_canon(fe_canon(Q.X))) {
+    xw = fe_zero();
+    yw = fe_zero();
+    return false;
+  }
+  const uint32_t lane = wlane(), h = lane >> 5, j = lane & 15u;
+  const bool act = (lane & 31u) < 16u;
+  const uint32_t c2p = 2u * kP24[j] + (j < 15 ? (1u << 26) : 0u) - (j >= 1 ? 4u : 0u);
+  const uint32_t X = limb_of_const(Q.X.v, j), Y = limb_of_const(Q.Y.v, j),
+                 Z = limb_of_const(Q.Z.v, j);
+  // one step: half h multiplies its (l, r); the result limbs go to
+  // stage[16 slot_h + j]
+  auto step = [&](uint32_t l, uint32_t r, uint32_t slot0, uint32_t slot1) {
+    const uint32_t v = wmul2_hi(act ? l : 0u, act ? r : 0u, mul);
+    if (!act) stage[16 * (h ? slot1 : slot0) + j] = v;
+    wave_lds_sync();
+  };
+  wmul2_init(mul);
+  // stage slots: 0 d / im / u / u alpha / x, 1 un, 2 vn / v / v beta / y
+  step(h ? Z + Y : (Z + c2p) - Y, X, 0, 1);  // d (< 1.2p), un
+  const fe inv = fe_inv_lanes(fe_canon(words_of_limbs(stage)));
+  const uint32_t iv = limb_of_const(inv.v, j);
+  step(h ? Z + Y : iv, h ? Z : limb_of_const(kR3, j), 0, 2);  // im, vn
+  step(h ? stage[32 + j] : stage[16 + j], stage[j], 0, 2);    // u, v
+  step(stage[(h ? 32 : 0) + j], h ? limb_of_const(kBeta, j) : limb_of_const(kAlpha, j), 0, 2);
+  const uint32_t am = (stage[j] + c2p) - limb_of_const(kOne, j);  // u alpha - 1 (Montgomery)
+  step(h ? stage[32 + j] : am, j == 0 ? 1u : 0u, 0, 2);           // times 1 / R
+  xw = fe_canon(words_of_limbs(stage));
+  yw = fe_canon(words_of_limbs(stage + 32));
+  return true;
+}
+
+// The affine Weierstrass result of each job, one wave per job (lane 0
+// writes).
 __global__ void __launch_bounds__(64) k_finalize(const uint32_t* __restrict__ qstate, JobView jv,
                                                  const uint32_t* __restrict__ flags) {
+  __shared__ uint32_t mul[WMUL2_WORDS];
+  __shared__ uint32_t stage[48];
   const uint32_t j = blockIdx.x;
   uint32_t* result = jv.get(j).result;
   xytz Q = ld_xytz(qstate + (size_t)j * XYTZ_WORDS);
   fe xw, yw;
-  bool fin = te_to_weierstrass<true>(Q, xw, yw);
+  bool fin = wide_to_weierstrass(Q, xw, yw, mul, stage);
   if (threadIdx.x != 0) return;
 #pragma unroll
   for (int l = 0; l < NL; ++l) {
