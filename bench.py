@@ -389,7 +389,9 @@ def main():
     torch.cuda.synchronize()
     for ph in ("sort", "accum", "merge", "agg", "horner"):
         api.profile_read(ph)
-    api.profile_enable(True)
+    # timed steps: the accumulation kernel carries start / stop events on its
+    # own dispatch (no event records between kernels)
+    api.profile_enable(api.MSM_PROFILE_ACCUM_KERNEL)
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0.record()
@@ -397,13 +399,21 @@ def main():
         step()
     t1.record()
     torch.cuda.synchronize()
-    api.profile_enable(False)
+    api.profile_enable(api.MSM_PROFILE_OFF)
     ms_per_step = t0.elapsed_time(t1) / args.steps
+    tot, cnt = api.profile_read("accum")
+    accum_tot_ms = tot / max(cnt, 1)
+    # phase split from separate steps with events around every phase (which
+    # stall the stream briefly at each phase boundary)
+    api.profile_enable(api.MSM_PROFILE_PHASES)
+    for _ in range(min(args.steps, 3)):
+        step()
+    torch.cuda.synchronize()
+    api.profile_enable(api.MSM_PROFILE_OFF)
     phases = {}
     for ph in ("sort", "accum", "merge", "agg", "horner"):
         tot, cnt = api.profile_read(ph)
         phases[ph] = tot / max(cnt, 1)
-    accum_tot_ms = phases["accum"]
     # the result of the timed runs, against the closed form
     from oracle import msm as msm_oracle
     ok_result = api.decode_result(api.to_host(res)) == (

@@ -310,16 +310,26 @@ int msm_server_stats(msm_server* server, size_t* in_flight, size_t* queued,
                      size_t* bytes_in_use);
 int msm_server_destroy(msm_server* server);
 
-/* Per-phase timing for measurement.  While enabled, each call records HIP
- * events on its own stream around its phases: "sort" (histogram, scan,
- * scatter), "accum" (the bucket accumulation kernel), "merge" (split-bucket
- * merge), "agg" (bucket aggregation), "horner" (group aggregation and the
- * affine result).  msm_profile_read synchronises on the recorded events,
- * returns the summed milliseconds and the number of recorded launches of one
- * phase since the last read, and forgets them.  Recording adds event records
- * to the stream, so leave it disabled under graph capture.
- * Errors: MSM_EINVAL (unknown phase, null outputs), MSM_EHIP. */
-int msm_profile_enable(int on);
+/* Timing for measurement.  msm_profile_enable(mode):
+ *   MSM_PROFILE_OFF (0): nothing is recorded.
+ *   MSM_PROFILE_PHASES (1): each call records HIP events on its own stream
+ *     around its phases: "sort" (histogram, scan, scatter), "accum" (the
+ *     bucket accumulation kernel), "merge" (split-bucket merge), "agg"
+ *     (bucket aggregation), "horner" (group aggregation and the affine
+ *     result).  Each event record stalls the stream briefly between kernels,
+ *     so this mode adds several microseconds per phase boundary.
+ *   MSM_PROFILE_ACCUM_KERNEL (2): only "accum", from start and stop events
+ *     attached to the accumulation kernel's own dispatch: no event records
+ *     between kernels, so the stream runs as it does unprofiled.
+ * msm_profile_read synchronises on the recorded events, returns the summed
+ * milliseconds and the number of recorded launches of one phase since the
+ * last read, and forgets them.  Nothing is recorded under graph capture.
+ * Errors: MSM_EINVAL (mode out of range, unknown phase, null outputs),
+ * MSM_EHIP. */
+#define MSM_PROFILE_OFF 0
+#define MSM_PROFILE_PHASES 1
+#define MSM_PROFILE_ACCUM_KERNEL 2
+int msm_profile_enable(int mode);
 int msm_profile_read(const char* phase, double* total_ms, int* launches);
 
 /* Microbenchmarks for the roofline denominators (not part of the MSM path).

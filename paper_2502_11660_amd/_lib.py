@@ -38,6 +38,9 @@ MSM_MUL_MONT = 0
 MSM_MUL_BARRETT = 1
 MSM_MUL_KARATSUBA = 2
 MSM_MUL_WIDE = 3
+MSM_PROFILE_OFF = 0
+MSM_PROFILE_PHASES = 1
+MSM_PROFILE_ACCUM_KERNEL = 2
 
 
 class MsmJob(ctypes.Structure):

@@ -16,6 +16,7 @@ from ._lib import (MSM_DIGITS_GLV, MSM_DIGITS_SIGNED, MSM_DIGITS_UNSIGNED,  # no
                    MSM_FLAG_EXCEPT,
                    MSM_FLAG_OFFCURVE, MSM_FLAG_RANGE, MSM_FORM_XYTZ, MSM_FORM_XYU,
                    MSM_MUL_BARRETT, MSM_MUL_KARATSUBA, MSM_MUL_MONT, MSM_MUL_WIDE,
+                   MSM_PROFILE_ACCUM_KERNEL, MSM_PROFILE_OFF, MSM_PROFILE_PHASES,
                    MSM_RESULT_WORDS,
                    MSM_UNIT_LANE, MSM_UNIT_QUAD, MSM_UNIT_WIDE, MSMError, MsmJob)
 
@@ -287,8 +288,16 @@ def decode_result(res_u32):
     return (x, y), flags
 
 
-def profile_enable(on=True):
-    _lib.check("msm_profile_enable", _lib.lib().msm_profile_enable(1 if on else 0))
+def profile_enable(mode=MSM_PROFILE_PHASES):
+    """Timing mode (msm_profile_enable): MSM_PROFILE_OFF, MSM_PROFILE_PHASES
+    (events around every phase) or MSM_PROFILE_ACCUM_KERNEL (events attached
+    to the accumulation kernel's dispatch only); True / False mean phases /
+    off."""
+    if mode is True:
+        mode = MSM_PROFILE_PHASES
+    elif mode is False:
+        mode = MSM_PROFILE_OFF
+    _lib.check("msm_profile_enable", _lib.lib().msm_profile_enable(int(mode)))
 
 
 def profile_read(phase):

@@ -83,6 +83,12 @@ struct ProfScope {
   ~ProfScope();
 };
 
+// Start and stop events for one kernel dispatch of phase `tag`, when the
+// profiling mode times that kernel alone (false otherwise); the caller
+// launches with them (hipExtLaunchKernelGGL) and then records the pair.
+bool prof_kernel_events(int tag, hipStream_t st, hipEvent_t* a, hipEvent_t* b);
+void prof_kernel_record(int tag, hipEvent_t a, hipEvent_t b);
+
 // Digit sort geometry: partitions of uniformly spread digits hold about
 // SORT_PART_TARGET entries; pass 2 stages up to SORT_PART_CAP in LDS and
 // sorts larger partitions on many blocks, in items of SORT_BIG_ITEM entries.

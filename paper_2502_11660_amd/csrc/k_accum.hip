@@ -14,6 +14,8 @@
 // tail[c0] + head[c0+1] + ... + head[c1]: one lane sums it when the span
 // c1 - c0 is small; longer spans are first folded by a binary tree over the
 // head partials.
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 
 #include "common.hpp"
@@ -205,7 +207,13 @@ int launch_accumulate(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t s
   const uint32_t K = pl.K, M = (uint32_t)pl.M;
   const unsigned grid = grid_for(pl.chunks, 256);
   // longlist[0] was cleared by the digit sort's scatter pass
-  {
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (prof_kernel_events(PT_ACCUM, st, &ea, &eb)) {
+    // timed by events attached to the dispatch itself
+    hipExtLaunchKernelGGL(k_accum, dim3(grid), dim3(256), 0, st, ea, eb, 0, pl.one.xyu, segoff,
+                          (uint32_t)pl.bb, key, idx, offsets, M, K, buckets, head, tail);
+    prof_kernel_record(PT_ACCUM, ea, eb);
+  } else {
     ProfScope prof(PT_ACCUM, st);
     k_accum<<<grid, 256, 0, st>>>(pl.one.xyu, segoff, (uint32_t)pl.bb, key, idx, offsets, M, K,
                                   buckets, head, tail);

@@ -20,7 +20,7 @@ const char* const kProfNames[PT_COUNT] = {"sort", "accum", "merge", "agg", "horn
 
 struct ProfState {
   std::mutex mu;
-  bool on = false;
+  int mode = MSM_PROFILE_OFF;
   struct Rec {
     int tag;
     hipEvent_t a, b;
@@ -36,8 +36,10 @@ hipEvent_t prof_event() {
     g_prof.pool.pop_back();
     return e;
   }
+  // timing only: no system-scope fence (cache writeback and invalidation)
+  // when the event is recorded
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
@@ -49,7 +51,7 @@ void set_last_hip_error(int e) { g_last_hip = e; }
 
 ProfScope::ProfScope(int t, hipStream_t s) : tag(t), st(s) {
   std::lock_guard<std::mutex> g(g_prof.mu);
-  if (!g_prof.on) return;
+  if (g_prof.mode != MSM_PROFILE_PHASES) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   a = prof_event();
@@ -61,6 +63,24 @@ ProfScope::~ProfScope() {
   std::lock_guard<std::mutex> g(g_prof.mu);
   hipEvent_t b = prof_event();
   if (b && hipEventRecord(b, st) == hipSuccess) g_prof.recs.push_back({tag, a, b});
+}
+
+bool prof_kernel_events(int tag, hipStream_t st, hipEvent_t* a, hipEvent_t* b) {
+  std::lock_guard<std::mutex> g(g_prof.mu);
+  if (g_prof.mode != MSM_PROFILE_ACCUM_KERNEL || tag != PT_ACCUM) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return false;
+  *a = prof_event();
+  *b = prof_event();
+  if (*a && *b) return true;
+  if (*a) g_prof.pool.push_back(*a);
+  if (*b) g_prof.pool.push_back(*b);
+  return false;
+}
+
+void prof_kernel_record(int tag, hipEvent_t a, hipEvent_t b) {
+  std::lock_guard<std::mutex> g(g_prof.mu);
+  g_prof.recs.push_back({tag, a, b});
 }
 
 int num_windows(int c, int encoding) {
@@ -299,9 +319,10 @@ int msm_run(const uint32_t* xyu, const uint32_t* scalars, size_t n, int c, int e
   return enqueue_msm(pl, ws, (hipStream_t)stream);
 }
 
-int msm_profile_enable(int on) {
+int msm_profile_enable(int mode) {
+  if (mode < MSM_PROFILE_OFF || mode > MSM_PROFILE_ACCUM_KERNEL) return MSM_EINVAL;
   std::lock_guard<std::mutex> g(g_prof.mu);
-  g_prof.on = on != 0;
+  g_prof.mode = mode;
   return MSM_OK;
 }
 

@@ -86,6 +86,11 @@ def test_argument_validation_without_gpu(lib):
     assert lib.msm_padd_chain(None, 4, 0, p, None) == _lib.MSM_EINVAL
     assert lib.msm_accumulate_stream(p, 0, 4, p, None) == _lib.MSM_EINVAL
     assert lib.msm_accumulate_stream(p, 4, 0, p, None) == _lib.MSM_EINVAL
+    # timing modes: host state only
+    assert lib.msm_profile_enable(3) == _lib.MSM_EINVAL
+    assert lib.msm_profile_enable(-1) == _lib.MSM_EINVAL
+    for mode in (_lib.MSM_PROFILE_ACCUM_KERNEL, _lib.MSM_PROFILE_PHASES, _lib.MSM_PROFILE_OFF):
+        assert lib.msm_profile_enable(mode) == _lib.MSM_OK
     # batches: validated on the host
     Job = _lib.MsmJob
     jobs = (Job * 2)(Job(16, 16, 16, 100, 8), Job(16, 16, 16, 0, 8))
