@@ -47,8 +47,10 @@ __device__ __forceinline__ fe fe_add_c(const fe& a, const fe& b) {
 // u, v with the division by 2^31 done mod p (add m p with m = -x mod 2^31,
 // valid because p = 1 mod 2^46).  After 2 * 377 - 1 divsteps a = 0 and
 // b = gcd = 1, so v = y^-1; 26 rounds of 31 cover them (extra rounds leave
-// the state unchanged once a = 0).  Plain C++ throughout: the loop is
-// data-dependent per lane.
+// the state unchanged once a = 0).  The per-lane form is plain C++ (the loop
+// is data-dependent per lane); the form for one value per wave
+// (fe_inv_lanes) spreads the words over the lanes and runs the divsteps on
+// the scalar unit.
 // ---------------------------------------------------------------------------
 
 constexpr int INV_ROUNDS = 26;
@@ -145,12 +147,6 @@ __device__ __forceinline__ fe comb_shift_mod(const fe& x, const fe& y, int64_t f
   fe d;
   const uint32_t borrow = fe_sub_c(q, P, d);
   return borrow ? q : d;
-}
-
-// lane 0's value of x (for values that are the same in every lane)
-__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
-  return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(x >> 32)) << 32) |
-         (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
 }
 
 // Out-of-line product for code that runs once per result (the conversion
