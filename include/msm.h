@@ -114,6 +114,8 @@ int msm_padd_batch(const uint32_t* a_xytz, const uint32_t* b, uint32_t* out_xytz
  *   (A = accumulators), mixed addition, each sum written once at the end.
  *   xyu: AoS prepared records (msm_points_prepare).  out_xytz: A AoS XYTZ
  *   records (lazily reduced; accumulators without points hold the identity).
+ *   Up to 1024 accumulators run one wide unit each (the latency unit
+ *   above), more run one lane each.
  *   Errors: MSM_EINVAL (null pointers, n = 0, A = 0, n or A >= 2^31). */
 #define MSM_UNIT_QUAD 0
 #define MSM_UNIT_LANE 1

@@ -126,6 +126,37 @@ __global__ void __launch_bounds__(256) k_acc_stream(const uint32_t* __restrict__
   st_xytz(out + (size_t)a * XYTZ_WORDS, acc);
 }
 
+// Few accumulators: one wide unit per accumulator (block a) instead of one
+// lane, so each step costs the wide unit's latency instead of a lane's.  The
+// prepared point is the addition's second operand with Z2 = 1; each lane
+// fetches its limb of the next point while the current addition runs.
+__global__ void __launch_bounds__(128) k_acc_stream_wide(const uint32_t* __restrict__ xyu_pts,
+                                                         uint32_t n, uint32_t A,
+                                                         uint32_t* __restrict__ out) {
+  __shared__ wunit_lds<2> s;
+  const uint32_t a = blockIdx.x;
+  wunit_init(s);
+  const wslot q = wslot_here();
+  const uint32_t one = limb_of_const(kOne, q.j);
+  const uint32_t coord = q.k < 3 ? q.k : 0u;  // X, Y, U words of the record; Z2 = 1
+  limb_src nxt = limb_fetch(xyu_pts + (size_t)(a < n ? a : 0u) * XYU_WORDS + coord * NL, q.j);
+  unit_sync();
+  uint32_t par = 0, step = 0;
+  for (uint32_t i = a; i < n; i += A, ++step) {
+    uint32_t* o = s.opd[step & 1];
+    if (q.act) o[16 * q.k + q.j] = q.k == 3 ? one : limb_extract(nxt, q.j);
+    const uint32_t nx = i + A < n ? i + A : i;  // clamped: loaded, not used
+    nxt = limb_fetch(xyu_pts + (size_t)nx * XYU_WORDS + coord * NL, q.j);
+    wave_lds_sync();  // each wave reads the coordinates its own lanes wrote
+    wu_add_u(s, o, q, par);
+  }
+  __syncthreads();  // the accumulator's coordinates come from both waves
+  if (threadIdx.x < 64) wu_store_acc(s, out + (size_t)a * XYTZ_WORDS);
+}
+
+// up to this many accumulators the stream runs on wide units
+constexpr size_t STREAM_WIDE_UPTO = 1024;
+
 }  // namespace
 }  // namespace msm
 
@@ -154,8 +185,12 @@ int msm_accumulate_stream(const uint32_t* xyu, size_t n, size_t accumulators, ui
   if (!xyu || !out_xytz || n == 0 || n >= (1u << 31) || accumulators == 0 ||
       accumulators >= (1u << 31))
     return MSM_EINVAL;
-  k_acc_stream<<<grid_for(accumulators, 256), 256, 0, (hipStream_t)stream>>>(
-      xyu, (uint32_t)n, (uint32_t)accumulators, out_xytz);
+  if (accumulators <= STREAM_WIDE_UPTO)
+    k_acc_stream_wide<<<(unsigned)accumulators, 128, 0, (hipStream_t)stream>>>(
+        xyu, (uint32_t)n, (uint32_t)accumulators, out_xytz);
+  else
+    k_acc_stream<<<grid_for(accumulators, 256), 256, 0, (hipStream_t)stream>>>(
+        xyu, (uint32_t)n, (uint32_t)accumulators, out_xytz);
   HIPCHK(hipGetLastError());
   return MSM_OK;
 }
