@@ -123,7 +123,7 @@ struct JobView {
   __device__ __forceinline__ JobDesc get(uint32_t j) const { return tab ? tab[j] : one; }
 };
 
-constexpr uint32_t SORT_TILE = 4096;  // digits per pass-1 sort tile
+constexpr uint32_t SORT_TILE = 8192;  // digits per pass-1 sort tile
 
 struct Plan {
   int c = 0, W = 0;
