@@ -137,3 +137,38 @@ def closed_form(scalars, ks):
     """For P_i = k_i G:  sum_i s_i P_i = ((sum_i s_i k_i) mod r) G."""
     tot = sum(s * k for s, k in zip(scalars, ks)) % R_ORDER
     return smul(tot, G)
+
+
+def dot_mod_r(s_words, k_words):
+    """(sum_i s_i k_i) mod r for scalars given as (n, 8) arrays of
+    little-endian 32-bit words, computed exactly and fast for large n.
+
+    Every value is cut into sixteen 16-bit digits, so
+    sum_i s_i k_i = sum_{a,b} 2^(16 (a+b)) D[a][b] with
+    D[a][b] = sum_i s_i[a] k_i[b].  Each digit product is below 2^32, so a
+    sum of at most 2^20 of them stays below 2^52 and the 16 x 16 sums D are
+    exact as float64 matrix products of the digit columns (every partial sum
+    is an integer below 2^53); longer inputs are summed in blocks of 2^20."""
+    import numpy as np
+    s = np.ascontiguousarray(s_words, dtype=np.uint32).reshape(-1, 8)
+    k = np.ascontiguousarray(k_words, dtype=np.uint32).reshape(-1, 8)
+    assert s.shape == k.shape
+
+    def digits(w):
+        out = np.empty((w.shape[0], 16), dtype=np.float64)
+        out[:, 0::2] = w & 0xFFFF
+        out[:, 1::2] = w >> 16
+        return out
+
+    tot = 0
+    for lo in range(0, s.shape[0], 1 << 20):
+        D = digits(s[lo:lo + (1 << 20)]).T @ digits(k[lo:lo + (1 << 20)])
+        for a in range(16):
+            for b in range(16):
+                tot += int(D[a, b]) << (16 * (a + b))
+    return tot % R_ORDER
+
+
+def closed_form_words(s_words, k_words):
+    """closed_form for scalars and point multipliers given as word arrays."""
+    return smul(dot_mod_r(s_words, k_words), G)

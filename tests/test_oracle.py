@@ -107,11 +107,13 @@ def test_generator_on_curve_and_order_r():
 
 
 def test_group_order_kills_random_point():
-    q = random_curve_point()
+    q = random_curve_point(random.Random(7))
     assert curve.smul(field.COFACTOR * R_ORDER, q) is curve.INF
-    assert curve.smul(field.COFACTOR, q) is not curve.INF or True
-    # cofactor clearing lands in G1
+    # a random curve point lies outside G1 (h > 1), and the subgroup test sees it
+    assert not curve.in_subgroup(q)
+    # cofactor clearing lands in G1, at a point other than the identity
     g1 = curve.smul(field.COFACTOR, q)
+    assert g1 is not curve.INF
     assert curve.in_subgroup(g1)
 
 
@@ -131,6 +133,10 @@ def test_sqrt_and_inverse():
         assert s * s % P == a * a % P
         assert s <= P - s
         assert field.finv(a) * a % P == 1
+        # Fermat's little theorem gives the same inverse
+        assert field.finv(a) == pow(a, P - 2, P)
+    for a in (1, 2, P - 1, (P + 1) // 2, 1 << 376):
+        assert field.finv(a) == pow(a, P - 2, P)
     with pytest.raises(ZeroDivisionError):
         field.finv(0)
     # 3 is a square (needed by the twisted-Edwards map)
@@ -238,6 +244,31 @@ def test_msm_linearity_and_closed_form():
     assert curve.add(m1, m2) == m12
     assert m1 == msm.closed_form(s1, ks)
     assert msm.msm_naive([0] * n, pts) is curve.INF
+
+
+def test_dot_mod_r_equals_plain_sum():
+    """The digit-matrix form of sum s_i k_i mod r against the plain integer
+    sum: random values, the largest 253- and 256-bit words, a block boundary
+    (2^20 + 3 rows, so two blocks are summed) and an empty tail."""
+    rng = np.random.default_rng(5)
+    for n in (1, 7, 1000):
+        s = rng.integers(0, 2**32, size=(n, 8), dtype=np.uint32)
+        k = rng.integers(0, 2**32, size=(n, 8), dtype=np.uint32)
+        si = [inputs.words_to_int(r) for r in s]
+        ki = [inputs.words_to_int(r) for r in k]
+        assert msm.dot_mod_r(s, k) == sum(a * b for a, b in zip(si, ki)) % R_ORDER
+    n = (1 << 20) + 3
+    s = np.full((n, 8), 0xFFFFFFFF, dtype=np.uint32)
+    k = np.full((n, 8), 0xFFFFFFFF, dtype=np.uint32)
+    assert msm.dot_mod_r(s, k) == n * ((1 << 256) - 1) ** 2 % R_ORDER
+    s[:, 7] = 0x1FFFFFFF
+    k[:, 7] = 0x1FFFFFFF
+    assert msm.dot_mod_r(s, k) == n * ((1 << 253) - 1) ** 2 % R_ORDER
+    sw = inputs.scalars_mod_r(11, 50)
+    kw = inputs.nonzero_scalars_mod_r(12, 50)
+    si = [inputs.words_to_int(r) for r in sw]
+    ki = [inputs.words_to_int(r) for r in kw]
+    assert msm.closed_form_words(sw, kw) == msm.closed_form(si, ki)
 
 
 @pytest.mark.parametrize("c", [1, 4, 8, 13])
