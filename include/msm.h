@@ -147,6 +147,10 @@ int msm_fe_mul_batch(const uint32_t* a, const uint32_t* b, uint32_t* out, size_t
  *    bits, one per lane, two elements per wave), with the reduction digits
  *    formed as one product m = (a b mod R)(-p^-1) mod R: the latency-oriented
  *    form; same output as MSM_MUL_MONT.
+ *  MSM_MUL_F28: the carry-free core of the one-lane PADD unit: 14 limbs of
+ *    28 bits, one per 32-bit word, so a column of 32x32->64 multiply-adds
+ *    needs no carry word; Montgomery with R' = 2^392:
+ *    out = a b^rounds 2^(-392 rounds) mod p.
  * a, b, out: SoA, one coordinate (12 x count words); inputs canonical
  * (< p); output canonical.  Errors: MSM_EINVAL (null pointers, count = 0 or
  * >= 2^31, rounds < 1, unknown variant), MSM_EHIP. */
@@ -154,6 +158,7 @@ int msm_fe_mul_batch(const uint32_t* a, const uint32_t* b, uint32_t* out, size_t
 #define MSM_MUL_BARRETT 1
 #define MSM_MUL_KARATSUBA 2
 #define MSM_MUL_WIDE 3
+#define MSM_MUL_F28 4
 int msm_fe_mul_chain(const uint32_t* a, const uint32_t* b, uint32_t* out, size_t count,
                      int variant, int rounds, void* stream);
 
@@ -286,10 +291,15 @@ int msm_batch_destroy(msm_batch* batch);
  *   picks msm_default_window(n)).  Its workspace (msm_workspace_bytes) is its
  *   footprint: it is admitted -- launched on the stream with the fewest
  *   requests in flight -- as soon as that much of the arena is free and no
- *   earlier request is still waiting (FIFO).  The job's buffers must stay
- *   valid until the request is reported finished.  *ticket receives the
- *   request's id (1, 2, ... in submission order).  MSM_ENOSPC when the
- *   footprint exceeds the whole budget (nothing is queued).
+ *   earlier request is still waiting (FIFO).  Ordering: an event is recorded
+ *   on `stream` (the producer's stream; NULL = the null stream) at the call,
+ *   and the request's kernels wait for it, so work the caller enqueued on
+ *   that stream before submitting (writing the points or scalars, clearing
+ *   the result) happens first.  The job's buffers must stay valid, and
+ *   unwritten, until the request is reported finished; its result is valid
+ *   from then on.  *ticket receives the request's id (1, 2, ... in
+ *   submission order).  MSM_ENOSPC when the footprint exceeds the whole
+ *   budget (nothing is queued).
  * msm_server_progress: non-blocking; retires requests whose work has
  *   finished (their results are then valid), admits waiting ones, and writes
  *   up to cap finished tickets (oldest first) to the HOST array done, their
@@ -305,7 +315,7 @@ int msm_batch_destroy(msm_batch* batch);
 typedef struct msm_server msm_server;
 
 int msm_server_create(size_t hbm_budget_bytes, int streams, int encoding, msm_server** out);
-int msm_server_submit(msm_server* server, const msm_job* job, uint64_t* ticket);
+int msm_server_submit(msm_server* server, const msm_job* job, void* stream, uint64_t* ticket);
 int msm_server_progress(msm_server* server, uint64_t* done, size_t cap, size_t* ndone);
 int msm_server_drain(msm_server* server);
 int msm_server_stats(msm_server* server, size_t* in_flight, size_t* queued,

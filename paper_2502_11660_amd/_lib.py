@@ -38,6 +38,7 @@ MSM_MUL_MONT = 0
 MSM_MUL_BARRETT = 1
 MSM_MUL_KARATSUBA = 2
 MSM_MUL_WIDE = 3
+MSM_MUL_F28 = 4
 MSM_PROFILE_OFF = 0
 MSM_PROFILE_PHASES = 1
 MSM_PROFILE_ACCUM_KERNEL = 2
@@ -70,7 +71,7 @@ SIGNATURES = {
     "msm_batch_run": (_I, [_P, _P]),
     "msm_batch_destroy": (_I, [_P]),
     "msm_server_create": (_I, [_SZ, _I, _I, ctypes.POINTER(ctypes.c_void_p)]),
-    "msm_server_submit": (_I, [_P, ctypes.POINTER(MsmJob), ctypes.POINTER(ctypes.c_uint64)]),
+    "msm_server_submit": (_I, [_P, ctypes.POINTER(MsmJob), _P, ctypes.POINTER(ctypes.c_uint64)]),
     "msm_server_progress": (_I, [_P, ctypes.POINTER(ctypes.c_uint64), _SZ,
                                  ctypes.POINTER(ctypes.c_size_t)]),
     "msm_server_drain": (_I, [_P]),

@@ -15,7 +15,7 @@ from . import _lib
 from ._lib import (MSM_DIGITS_GLV, MSM_DIGITS_SIGNED, MSM_DIGITS_UNSIGNED,  # noqa: F401
                    MSM_FLAG_EXCEPT,
                    MSM_FLAG_OFFCURVE, MSM_FLAG_RANGE, MSM_FORM_XYTZ, MSM_FORM_XYU,
-                   MSM_MUL_BARRETT, MSM_MUL_KARATSUBA, MSM_MUL_MONT, MSM_MUL_WIDE,
+                   MSM_MUL_BARRETT, MSM_MUL_F28, MSM_MUL_KARATSUBA, MSM_MUL_MONT, MSM_MUL_WIDE,
                    MSM_PROFILE_ACCUM_KERNEL, MSM_PROFILE_OFF, MSM_PROFILE_PHASES,
                    MSM_RESULT_WORDS,
                    MSM_UNIT_LANE, MSM_UNIT_QUAD, MSM_UNIT_WIDE, MSMError, MsmJob)
@@ -331,10 +331,12 @@ class Server:
         self._buf = (ctypes.c_uint64 * 1024)()
 
     def submit(self, xyu, scalars, result, n, c=0):
+        """Queue one MSM; it runs after the work already enqueued on the
+        current stream (the producer of its inputs)."""
         arr = _job_array([(xyu, scalars, result, n, c)], self.encoding)
         t = ctypes.c_uint64(0)
         _lib.check("msm_server_submit", _lib.lib().msm_server_submit(
-            self._h, arr, ctypes.byref(t)))
+            self._h, arr, _stream(), ctypes.byref(t)))
         self._live[t.value] = (xyu, scalars, result)
         return t.value
 

@@ -22,6 +22,7 @@
 // job of the batch.
 #include "common.hpp"
 #include "convert.hpp"
+#include "curve28.hpp"
 #include "quad.hpp"
 #include "wide_unit.hpp"
 
@@ -57,9 +58,12 @@ __global__ void __launch_bounds__(256) k_tree_level(const uint32_t* __restrict__
     st_xytz(O + (size_t)h * XYTZ_WORDS, c);
   }
   const uint32_t s = a < h ? a : h + 1;  // output slot
-  xytz r = padd_full(ld_xytz(L + (size_t)a * XYTZ_WORDS), ld_xytz(R + (size_t)a * XYTZ_WORDS), p2);
-  if (to_u) r.T = fe_mul(r.T, fe_const(kK));
-  st_xytz(O + (size_t)s * XYTZ_WORDS, r);
+  // the addition on the carry-free 28-bit form (curve28.hpp); U = k T there
+  // uses k in that form, so U stays consistent with the point's scale
+  xytz28 r = padd28_full(pt28_from(ld_xytz(L + (size_t)a * XYTZ_WORDS)),
+                         pt28_from(ld_xytz(R + (size_t)a * XYTZ_WORDS)));
+  if (to_u) r.T = f28_mul(r.T, f28_const(kK28));
+  st_xytz(O + (size_t)s * XYTZ_WORDS, pt28_to_words(r));
 }
 
 // Same level, four lanes per output record.

@@ -1,8 +1,11 @@
 // Elementwise kernels: batched field multiply, batched PADD (the paper's
 // "task", Sec. II-D / V-A), point preparation and the synthetic point
 // generator.
+#include <algorithm>
+
 #include "common.hpp"
 #include "convert.hpp"
+#include "curve28.hpp"
 
 namespace msm {
 namespace {
@@ -19,64 +22,119 @@ __global__ void __launch_bounds__(256) k_fe_mul(const uint32_t* __restrict__ a,
 }
 
 // out_i = a_i + b_i, SoA limb-major operands; FORM selects the mixed
-// (b prepared: X, Y, U, Z = 1) or the complete (b extended) addition.
+// (b prepared: X, Y, U, Z = 1) or the complete (b extended) addition.  On the
+// carry-free 28-bit field form (curve28.hpp); outputs canonical.
 template <int FORM>
 __global__ void __launch_bounds__(256) k_padd(const uint32_t* __restrict__ a,
-                                              const uint32_t* __restrict__ b,
-                                              uint32_t* __restrict__ out, uint32_t count) {
+                                                const uint32_t* __restrict__ b,
+                                                uint32_t* __restrict__ out, uint32_t count) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
-  const fe p2 = fe_const(kP2);
-  xytz pa;
-  pa.X = ld_soa(a, count, 0, i);
-  pa.Y = ld_soa(a, count, 1, i);
-  pa.T = ld_soa(a, count, 2, i);
-  pa.Z = ld_soa(a, count, 3, i);
-  xytz r;
+  xytz28 pa;
+  pa.X = f28_from_words(ld_soa(a, count, 0, i));
+  pa.Y = f28_from_words(ld_soa(a, count, 1, i));
+  pa.T = f28_from_words(ld_soa(a, count, 2, i));
+  pa.Z = f28_from_words(ld_soa(a, count, 3, i));
+  xytz28 r;
   if (FORM == MSM_FORM_XYU) {
-    xyu pb;
-    pb.X = ld_soa(b, count, 0, i);
-    pb.Y = ld_soa(b, count, 1, i);
-    pb.U = ld_soa(b, count, 2, i);
-    r = padd_mixed(pa, pb, p2);
+    xyu28 pb;
+    pb.X = f28_from_words(ld_soa(b, count, 0, i));
+    pb.Y = f28_from_words(ld_soa(b, count, 1, i));
+    pb.U = f28_from_words(ld_soa(b, count, 2, i));
+    r = padd28_mixed(pa, pb);
   } else {
-    xytz pb;
-    pb.X = ld_soa(b, count, 0, i);
-    pb.Y = ld_soa(b, count, 1, i);
-    pb.T = ld_soa(b, count, 2, i);
-    pb.Z = ld_soa(b, count, 3, i);
-    r = padd_full(pa, pb, p2);
+    xytz28 pb;
+    pb.X = f28_from_words(ld_soa(b, count, 0, i));
+    pb.Y = f28_from_words(ld_soa(b, count, 1, i));
+    pb.T = f28_from_words(ld_soa(b, count, 2, i));
+    pb.Z = f28_from_words(ld_soa(b, count, 3, i));
+    r = padd28_full(pa, pb);
   }
-  st_soa(out, count, 0, i, fe_canon(r.X));
-  st_soa(out, count, 1, i, fe_canon(r.Y));
-  st_soa(out, count, 2, i, fe_canon(r.T));
-  st_soa(out, count, 3, i, fe_canon(r.Z));
+  st_soa(out, count, 0, i, fe_canon(f28_to_words(r.X)));
+  st_soa(out, count, 1, i, fe_canon(f28_to_words(r.Y)));
+  st_soa(out, count, 2, i, fe_canon(f28_to_words(r.T)));
+  st_soa(out, count, 3, i, fe_canon(f28_to_words(r.Z)));
 }
 
-// Weierstrass affine (ordinary form) -> prepared (X, Y, U = k x y), Z = 1:
+// Weierstrass affine (ordinary form) -> prepared (X, Y, U = k x y), Z = 1
+// (Sec. II-D: inputs enter as (X, Y, U, Z = 1)):
 //   w = x + 1,  x_e = (beta/alpha) w / y,  y_e = (w - alpha) / (w + alpha)
-// with one inversion of y (w + alpha) per point.
-// prepared record (x_e, y_e, k x_e y_e) of the affine point (x, y), both in
-// Montgomery form; flags for off-curve / map-exceptional inputs
-__device__ __forceinline__ uint32_t prepare_one(const fe& x, const fe& y, uint32_t* rec) {
+// so each point needs the inverse of its denominator y (w + alpha).  The
+// inverses come from one inversion per wave (Montgomery's trick, on two
+// levels).  Each lane walks its points forward multiplying their
+// denominators into a running product (each point's record slot keeps the
+// product before it); the wave then forms prefix and suffix products of the
+// 64 lane products (six shuffle-and-multiply steps each), inverts the wave's
+// total once with all lanes cooperating (fe_inv_lanes), and gives each lane
+// the inverse of its own product as total^-1 x prefix x suffix.  Walking
+// back, the inverse of point j's denominator is (inverse of the product up to
+// j) times (product before j), and multiplying by denominator j steps the
+// inverse back.  With the image phi(P) = (omega x, y) the two denominators
+// y (w + alpha) and y (omega x + 1 + alpha) of a point are multiplied first,
+// so one entry serves both.  A zero denominator (an exceptional point,
+// flagged; it cannot lie in the prime-order subgroup) enters the product as
+// 1 so that it does not spoil the batch; its own record is then
+// unspecified.
+
+// Preparation runs once per point set, off the MSM's path; its products are
+// the out-of-line multiply (fe_mul_cold), which keeps the kernel's register
+// footprint small enough for several waves per SIMD.
+
+// lane-to-lane moves of a field element (lanes without a source keep x)
+__device__ __forceinline__ fe fe_shfl_up(const fe& x, int d) {
+  fe r;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) r.v[i] = (uint32_t)__shfl_up((int)x.v[i], d, 64);
+  return r;
+}
+
+__device__ __forceinline__ fe fe_shfl_down(const fe& x, int d) {
+  fe r;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) r.v[i] = (uint32_t)__shfl_down((int)x.v[i], d, 64);
+  return r;
+}
+
+// Every lane's v^-1 (Montgomery form, canonical) for non-zero v < 2p, with
+// one inversion for the wave.  All 64 lanes of the wave must take part.
+__device__ __forceinline__ fe wave_batch_inverse(const fe& v) {
+  const int lane = (int)__lane_id();
+  fe P = v, Q = v;  // inclusive prefix and suffix products over the lanes
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const fe pu = fe_mul_cold(P, fe_shfl_up(P, d));
+    const fe qd = fe_mul_cold(Q, fe_shfl_down(Q, d));
+    P = fe_select(lane >= d, pu, P);
+    Q = fe_select(lane + d < 64, qd, Q);
+  }
+  const fe E = fe_select(lane == 0, fe_const(kOne), fe_shfl_up(P, 1));    // lanes below
+  const fe S = fe_select(lane == 63, fe_const(kOne), fe_shfl_down(Q, 1)); // lanes above
+  fe total;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) total.v[i] = (uint32_t)__builtin_amdgcn_readlane((int)P.v[i], 63);
+  const fe inv_total = fe_mul_cold(fe_inv_lanes(fe_canon(total)), fe_const(kR3));
+  return fe_mul_cold(fe_mul_cold(inv_total, E), S);
+}
+
+// the denominator y (x + 1 + alpha)
+__device__ __forceinline__ fe prep_den(const fe& x, const fe& y) {
+  return fe_mul_cold(y, fe_add(fe_add(x, fe_const(kOne)), fe_const(kAlpha)));
+}
+
+// the record (x_e, y_e, k x_e y_e), canonical, given the inverse of the
+// denominator
+__device__ __forceinline__ void prep_record(const fe& x, const fe& y, const fe& inv,
+                                            uint32_t* rec) {
   const fe p2 = fe_const(kP2);
-  uint32_t flags = 0;
-  fe lhs = fe_canon(fe_sqr(y));
-  fe rhs = fe_canon(fe_add(fe_mul(fe_sqr(x), x), fe_const(kOne)));
-  if (!fe_eq_canon(lhs, rhs)) flags |= MSM_FLAG_OFFCURVE;
-  fe w = fe_add(x, fe_const(kOne));               // < 4p
-  fe wpa = fe_add(w, fe_const(kAlpha));           // < 6p
-  fe wma = fe_sub_plus(w, fe_const(kAlpha), p2);  // < 6p
-  fe den = fe_mul(y, wpa);
-  if (fe_is_zero_canon(fe_canon(den))) flags |= MSM_FLAG_EXCEPT;
-  fe inv = fe_inv_mont(den);
-  fe xe = fe_mul(fe_mul(fe_mul(w, wpa), inv), fe_const(kBetaOverAlpha));
-  fe ye = fe_mul(fe_mul(wma, y), inv);
-  fe u = fe_mul(fe_mul(xe, ye), fe_const(kK));
+  const fe w = fe_add(x, fe_const(kOne));                 // < 4p
+  const fe wpa = fe_add(w, fe_const(kAlpha));             // < 6p
+  const fe wma = fe_sub_plus(w, fe_const(kAlpha), p2);    // < 6p
+  const fe xe = fe_mul_cold(fe_mul_cold(fe_mul_cold(w, wpa), inv), fe_const(kBetaOverAlpha));
+  const fe ye = fe_mul_cold(fe_mul_cold(wma, y), inv);
+  const fe u = fe_mul_cold(fe_mul_cold(xe, ye), fe_const(kK));
   st_aos(rec, 0, fe_canon(xe));
   st_aos(rec, 1, fe_canon(ye));
   st_aos(rec, 2, fe_canon(u));
-  return flags;
 }
 
 __device__ __forceinline__ void prepare_identity(uint32_t* rec) {
@@ -85,25 +143,71 @@ __device__ __forceinline__ void prepare_identity(uint32_t* rec) {
   st_aos(rec, 2, fe_zero());
 }
 
-// ENDO: records 2i and 2i + 1 hold point i and its image (omega x, y)
+// the point's factor of the batch product (1 for a zero denominator)
+__device__ __forceinline__ fe batch_factor(const fe& den_a, const fe& den_b, bool endo,
+                                           uint32_t& flags) {
+  fe d = endo ? fe_mul_cold(den_a, den_b) : den_a;
+  if (fe_is_zero_canon(fe_canon(d))) {
+    flags |= MSM_FLAG_EXCEPT;
+    d = fe_const(kOne);
+  }
+  return d;
+}
+
+// Thread t prepares points i = t + j T, j = 0 .. m-1 (i < n), T = threads;
+// threads t >= T take part in the wave-wide inversion only.
+// ENDO: records 2i and 2i + 1 hold point i and its image (omega x, y).
 template <bool ENDO>
 __global__ void __launch_bounds__(256) k_prepare(const uint32_t* __restrict__ xy,
                                                  const uint32_t* __restrict__ inf,
                                                  uint32_t* __restrict__ out, uint32_t n,
+                                                 uint32_t T, uint32_t m,
                                                  uint32_t* __restrict__ status) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  uint32_t* rec = out + (size_t)(ENDO ? 2 * i : i) * XYU_WORDS;
-  uint32_t* rec2 = rec + XYU_WORDS;
-  if (inf && inf[i]) {
-    prepare_identity(rec);
-    if (ENDO) prepare_identity(rec2);
-    return;
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t mine = t < T ? m : 0u;
+  uint32_t flags = 0;
+  fe c = fe_const(kOne);  // product of the factors so far
+  uint32_t last = 0;      // points of this thread
+  for (uint32_t j = 0; j < mine; ++j) {
+    const uint64_t i = (uint64_t)t + (uint64_t)j * T;
+    if (i >= n) break;
+    last = j + 1;
+    if (inf && inf[i]) continue;
+    const fe x = fe_mul_cold(ld_soa(xy, n, 0, (size_t)i), fe_const(kR2));
+    const fe y = fe_mul_cold(ld_soa(xy, n, 1, (size_t)i), fe_const(kR2));
+    const fe lhs = fe_canon(fe_mul_cold(y, y));
+    const fe rhs = fe_canon(fe_add(fe_mul_cold(fe_mul_cold(x, x), x), fe_const(kOne)));
+    if (!fe_eq_canon(lhs, rhs)) flags |= MSM_FLAG_OFFCURVE;
+    const fe den_a = prep_den(x, y);
+    const fe den_b = ENDO ? prep_den(fe_mul_cold(x, fe_const(kOmega)), y) : den_a;
+    st_aos(out + (size_t)(ENDO ? 2 * i : i) * XYU_WORDS, 0, fe_canon(c));  // product before i
+    c = fe_mul_cold(c, batch_factor(den_a, den_b, ENDO, flags));
   }
-  const fe x = fe_to_mont(ld_soa(xy, n, 0, i));
-  const fe y = fe_to_mont(ld_soa(xy, n, 1, i));
-  uint32_t flags = prepare_one(x, y, rec);
-  if (ENDO) flags |= prepare_one(fe_mul(x, fe_const(kOmega)), y, rec2);
+  fe tinv = wave_batch_inverse(c);  // inverse of this thread's product
+  for (uint32_t jj = last; jj-- > 0;) {
+    const uint64_t i = (uint64_t)t + (uint64_t)jj * T;
+    uint32_t* rec = out + (size_t)(ENDO ? 2 * i : i) * XYU_WORDS;
+    if (inf && inf[i]) {
+      prepare_identity(rec);
+      if (ENDO) prepare_identity(rec + XYU_WORDS);
+      continue;
+    }
+    const fe x = fe_mul_cold(ld_soa(xy, n, 0, (size_t)i), fe_const(kR2));
+    const fe y = fe_mul_cold(ld_soa(xy, n, 1, (size_t)i), fe_const(kR2));
+    const fe den_a = prep_den(x, y);
+    const fe xb = ENDO ? fe_mul_cold(x, fe_const(kOmega)) : x;
+    const fe den_b = ENDO ? prep_den(xb, y) : den_a;
+    uint32_t dummy = 0;
+    const fe d = batch_factor(den_a, den_b, ENDO, dummy);
+    const fe inv_d = fe_mul_cold(tinv, ld_aos(rec, 0));  // 1 / d
+    tinv = fe_mul_cold(tinv, d);                          // 1 / (product before this point)
+    if (ENDO) {
+      prep_record(x, y, fe_mul_cold(inv_d, den_b), rec);
+      prep_record(xb, y, fe_mul_cold(inv_d, den_a), rec + XYU_WORDS);
+    } else {
+      prep_record(x, y, inv_d, rec);
+    }
+  }
   if (flags) atomicOr(status, flags);
 }
 
@@ -164,10 +268,14 @@ int launch_padd(const uint32_t* a, const uint32_t* b, uint32_t* out, uint32_t co
 
 int launch_prepare(const uint32_t* xy, const uint32_t* inf, uint32_t* xyu, uint32_t n,
                    uint32_t* status, bool endo, hipStream_t st) {
+  // points per thread: enough threads for four waves per SIMD
+  // (256 CUs x 4 SIMDs x 64 lanes x 4), the rest of the points batched
+  const uint32_t m = std::max<uint32_t>(1u, std::min<uint32_t>(64u, n / 262144u));
+  const uint32_t T = (uint32_t)(((uint64_t)n + m - 1) / m);
   if (endo)
-    k_prepare<true><<<grid_for(n, 256), 256, 0, st>>>(xy, inf, xyu, n, status);
+    k_prepare<true><<<grid_for(T, 256), 256, 0, st>>>(xy, inf, xyu, n, T, m, status);
   else
-    k_prepare<false><<<grid_for(n, 256), 256, 0, st>>>(xy, inf, xyu, n, status);
+    k_prepare<false><<<grid_for(T, 256), 256, 0, st>>>(xy, inf, xyu, n, T, m, status);
   HIPCHK(hipGetLastError());
   return MSM_OK;
 }

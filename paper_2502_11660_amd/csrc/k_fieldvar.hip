@@ -3,6 +3,7 @@
 // waiting for the previous (so a launch of many lanes measures multiplication
 // throughput and the value pins every product).
 #include "common.hpp"
+#include "fe28.hpp"
 #include "field_variants.hpp"
 #include "wide.hpp"
 
@@ -27,6 +28,19 @@ __global__ void __launch_bounds__(256) k_fe_mul_chain(const uint32_t* __restrict
   const fe y = ld_soa(b, count, 0, i);
   for (uint32_t r = 0; r < rounds; ++r) x = mul_variant<V>(x, y);
   st_soa(out, count, 0, i, fe_canon(x));
+}
+
+// the carry-free 28-bit core (R' = 2^392): out = a b^rounds 2^(-392 rounds)
+__global__ void __launch_bounds__(256) k_fe_mul_chain_f28(const uint32_t* __restrict__ a,
+                                                          const uint32_t* __restrict__ b,
+                                                          uint32_t* __restrict__ out,
+                                                          uint32_t count, uint32_t rounds) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  fe28 x = f28_from_words(ld_soa(a, count, 0, i));
+  const fe28 y = f28_from_words(ld_soa(b, count, 0, i));
+  for (uint32_t r = 0; r < rounds; ++r) x = f28_mul(x, y);
+  st_soa(out, count, 0, i, fe_canon(f28_to_words(x)));
 }
 
 // two elements per wave (one per 32-lane half): the same chain with the
@@ -80,6 +94,9 @@ extern "C" int msm_fe_mul_chain(const uint32_t* a, const uint32_t* b, uint32_t* 
     case MSM_MUL_KARATSUBA:
       k_fe_mul_chain<MSM_MUL_KARATSUBA><<<grid, 256, 0, st>>>(a, b, out, (uint32_t)count,
                                                               (uint32_t)rounds);
+      break;
+    case MSM_MUL_F28:
+      k_fe_mul_chain_f28<<<grid, 256, 0, st>>>(a, b, out, (uint32_t)count, (uint32_t)rounds);
       break;
     case MSM_MUL_WIDE:
       k_fe_mul_chain_wide<<<(unsigned)((count + 1) / 2), 64, 0, st>>>(a, b, out, (uint32_t)count,

@@ -71,6 +71,7 @@ struct Request {
   Plan plan;
   size_t off = 0;
   int stream = -1;
+  hipEvent_t ready = nullptr;  // recorded on the caller's stream at submission
   hipEvent_t done = nullptr;
 };
 
@@ -115,14 +116,18 @@ int admit(msm_server* s) {
     s->queued.pop_front();
     r.off = off;
     r.stream = k;
-    int rc = take_event(s, r.done);
+    // the request's kernels wait for what the caller enqueued before submitting
+    int rc = hipStreamWaitEvent(s->streams[k], r.ready, 0) == hipSuccess ? MSM_OK : MSM_EHIP;
+    if (rc == MSM_OK) rc = take_event(s, r.done);
     if (rc == MSM_OK) rc = enqueue_msm(r.plan, s->base + off, s->streams[k]);
     if (rc == MSM_OK && hipEventRecord(r.done, s->streams[k]) != hipSuccess) rc = MSM_EHIP;
     if (rc != MSM_OK) {
       s->arena.release(off, r.plan.bytes);
       if (r.done) s->events.push_back(r.done);
+      s->events.push_back(r.ready);
       return rc;
     }
+    s->events.push_back(r.ready);  // the wait is enqueued; the event can be reused
     ++s->load[k];
     s->running.push_back(r);
   }
@@ -156,6 +161,7 @@ int retire(msm_server* s) {
 void destroy(msm_server* s) {
   for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
   for (Request& r : s->running) s->events.push_back(r.done);
+  for (Request& r : s->queued) s->events.push_back(r.ready);
   for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
   if (s->base) (void)hipFree(s->base);
@@ -197,7 +203,7 @@ int msm_server_create(size_t hbm_budget_bytes, int streams, int encoding, msm_se
   return MSM_OK;
 }
 
-int msm_server_submit(msm_server* s, const msm_job* job, uint64_t* ticket) {
+int msm_server_submit(msm_server* s, const msm_job* job, void* stream, uint64_t* ticket) {
   if (!s || !job || !ticket || !job->xyu || !job->scalars || !job->result) return MSM_EINVAL;
   Request r;
   r.job = *job;
@@ -208,6 +214,11 @@ int msm_server_submit(msm_server* s, const msm_job* job, uint64_t* ticket) {
   r.plan.one.xyu = job->xyu;
   r.plan.one.scalars = job->scalars;
   r.plan.one.result = job->result;
+  if (take_event(s, r.ready) != MSM_OK) return MSM_EHIP;
+  if (hipEventRecord(r.ready, (hipStream_t)stream) != hipSuccess) {
+    s->events.push_back(r.ready);
+    return MSM_EHIP;
+  }
   r.ticket = s->next_ticket++;
   *ticket = r.ticket;
   s->queued.push_back(r);

@@ -111,7 +111,7 @@ def test_argument_validation_without_gpu(lib):
     assert lib.msm_server_create(1 << 30, 4, 9, ctypes.byref(srv)) == _lib.MSM_EINVAL
     assert lib.msm_server_create(1 << 30, 4, S, None) == _lib.MSM_EINVAL
     t = ctypes.c_uint64()
-    assert lib.msm_server_submit(None, jobs, ctypes.byref(t)) == _lib.MSM_EINVAL
+    assert lib.msm_server_submit(None, jobs, None, ctypes.byref(t)) == _lib.MSM_EINVAL
     k = ctypes.c_size_t()
     assert lib.msm_server_progress(None, None, 0, ctypes.byref(k)) == _lib.MSM_EINVAL
     assert lib.msm_server_drain(None) == _lib.MSM_EINVAL

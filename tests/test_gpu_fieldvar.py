@@ -1,6 +1,8 @@
 """GPU parity of the field-multiplication cores compared in the benchmark
-(Montgomery, Barrett, Karatsuba-Montgomery) against plain modular arithmetic:
-chained products out = a b^rounds (times R^-rounds for the Montgomery forms)."""
+(Montgomery, Barrett, Karatsuba-Montgomery, lane-parallel Montgomery and the
+carry-free 28-bit Montgomery core) against plain modular arithmetic: chained
+products out = a b^rounds (times R^-rounds for the Montgomery forms, with
+R = 2^384, or 2^392 for the 28-bit core)."""
 
 import random
 
@@ -14,17 +16,20 @@ from tests import helpers as H
 pytestmark = pytest.mark.gpu
 
 R_INV = pow(1 << 384, -1, P)
+R28_INV = pow(1 << 392, -1, P)
 
 
 def _expected(variant, a, b, rounds):
     v = a * pow(b, rounds, P) % P
     if variant in (api.MSM_MUL_MONT, api.MSM_MUL_KARATSUBA, api.MSM_MUL_WIDE):
         v = v * pow(R_INV, rounds, P) % P
+    if variant == api.MSM_MUL_F28:
+        v = v * pow(R28_INV, rounds, P) % P
     return v
 
 
 @pytest.mark.parametrize("variant", [api.MSM_MUL_MONT, api.MSM_MUL_BARRETT,
-                                     api.MSM_MUL_KARATSUBA, api.MSM_MUL_WIDE])
+                                     api.MSM_MUL_KARATSUBA, api.MSM_MUL_WIDE, api.MSM_MUL_F28])
 @pytest.mark.parametrize("rounds", [1, 7])
 def test_fe_mul_chain_variants(variant, rounds):
     rng = random.Random(100 + variant * 10 + rounds)

@@ -86,3 +86,27 @@ def test_served_trace_equals_plain_replay(oracle_pool):
     assert np.all(np.isfinite(lat_s)) and np.all(lat_s > 0)
     s = serve.summarize(lat_s, wall_s, np.ones(nreq, dtype=bool))
     assert s["p99_ms"] >= s["p50_ms"] > 0
+
+
+def test_server_request_waits_for_the_producer_stream(oracle_pool):
+    """Inputs written on the caller's stream just before submission (behind
+    other queued work, with no synchronisation) are what the request reads."""
+    ks, pts = oracle_pool
+    xyu_pool = _pool(pts)
+    n = 1500
+    sc = [inputs.words_to_int(r) for r in inputs.scalars_mod_r(9400, n)]
+    src = _dev(H.scalar_words(sc))
+    dst = torch.zeros_like(src)
+    res = api.words(api.MSM_RESULT_WORDS)
+    res.fill_(-1)
+    busy = _dev(H.scalar_words([inputs.words_to_int(r) for r in inputs.scalars_mod_r(9401, 2048)]))
+    torch.cuda.synchronize()
+    srv = api.Server(1 << 28, streams=2)
+    for _ in range(4):                      # work ahead of the producer's writes
+        api.msm_run(xyu_pool[:2048 * 36], busy, 2048, 0)
+    dst.copy_(src)
+    srv.submit(xyu_pool[:n * 36], dst, res, n, 0)
+    srv.drain()
+    assert srv.progress() == [1]
+    assert api.decode_result(api.to_host(res)) == (msm.closed_form(sc, ks[:n]), 0)
+    srv.destroy()
