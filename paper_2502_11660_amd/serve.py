@@ -4,6 +4,7 @@ overlapping on the device) or run by the plain path one at a time, first in
 first out.  Latency is completion time minus arrival time on the host clock.
 """
 
+import sys
 import time
 
 import numpy as np
@@ -38,7 +39,7 @@ def replay_served(server, arrivals, jobs, progress_every=None):
             last_report = now
             fl, q, b = server.stats()
             print("[serve] t=%.1fs submitted=%d done=%d in_flight=%d queued=%d arena=%.2f GB"
-                  % (now, i, done, fl, q, b / 1e9), flush=True)
+                  % (now, i, done, fl, q, b / 1e9), file=sys.stderr, flush=True)
     return lat, time.perf_counter() - t0
 
 
@@ -61,7 +62,7 @@ def replay_plain(arrivals, jobs, encoding=api.MSM_DIGITS_SIGNED, workspaces=None
         now = time.perf_counter() - t0
         if progress_every and now - last_report >= progress_every:
             last_report = now
-            print("[plain] t=%.1fs done=%d" % (now, i + 1), flush=True)
+            print("[plain] t=%.1fs done=%d" % (now, i + 1), file=sys.stderr, flush=True)
     return lat, time.perf_counter() - t0
 
 

@@ -164,3 +164,55 @@ def test_gen_points_edge_scalars():
             assert f == 1 and rec == (0, 0)
         else:
             assert f == 0 and rec == want
+
+
+# --------------------------------------------------------------------------
+# the full-size PADD workload: 2^22 independent pairs, 4096 sampled outputs
+# --------------------------------------------------------------------------
+
+PAIRS_FULL = 1 << 22
+POOL_FULL = 8192
+SAMPLE_FULL = 4096
+
+
+@pytest.fixture(scope="module")
+def pair_pool():
+    """8192 oracle points in twisted-Edwards form, as extended records with a
+    random projective scale (Z != 1) and as prepared records."""
+    from oracle import points
+    seed = inputs.config_seed(2)
+    ks = [inputs.words_to_int(r) for r in inputs.nonzero_scalars_mod_r(seed, POOL_FULL, stream=3)]
+    tp = [te.w_to_te(p) for p in points.gen_points(ks)]
+    lam = [inputs.words_to_int(r)
+           for r in inputs.base_field_elements(seed, POOL_FULL, stream=4)]
+    ext = [H.te_extended_mont(p, lam[i]) for i, p in enumerate(tp)]
+    prep = [H.te_prepared_mont(p) for p in tp]
+    return tp, _dev(H.soa(ext, 4)), _dev(H.soa(prep, 3))
+
+
+@pytest.mark.parametrize("form", [api.MSM_FORM_XYU, api.MSM_FORM_XYTZ])
+def test_padd_batch_full_size_sampled(pair_pool, form):
+    """out_i = a_i + b_i over 2^22 pairs gathered from the pool (the timed
+    launch: one msm_padd_batch call of 2^22 elements), 4096 outputs chosen at
+    random compared with the oracle's affine twisted-Edwards sum."""
+    import torch
+    tp, ext, prep = pair_pool
+    rng = np.random.Generator(np.random.PCG64([inputs.config_seed(2), 5 + form]))
+    ja = rng.integers(0, POOL_FULL, PAIRS_FULL)
+    jb = rng.integers(0, POOL_FULL, PAIRS_FULL)
+    dev = ext.device
+    nb = 4 if form == api.MSM_FORM_XYTZ else 3
+    src_b = ext if form == api.MSM_FORM_XYTZ else prep
+    A = ext.view(48, POOL_FULL).index_select(1, torch.from_numpy(ja).to(dev)).contiguous().view(-1)
+    B = src_b.view(12 * nb, POOL_FULL).index_select(
+        1, torch.from_numpy(jb).to(dev)).contiguous().view(-1)
+    out = api.padd_batch(A, B, PAIRS_FULL, form)
+    sample = np.sort(rng.choice(PAIRS_FULL, SAMPLE_FULL, replace=False))
+    sample[-1] = PAIRS_FULL - 1                     # the ragged end of the last block
+    got = out.view(48, PAIRS_FULL).index_select(
+        1, torch.from_numpy(sample).to(dev)).cpu().numpy().view(np.uint32)
+    rows = H.unsoa(got.reshape(-1), 4, SAMPLE_FULL)
+    for t, i in enumerate(sample):
+        rec = rows[t]
+        assert all(v < P for v in rec)
+        assert H.normalize_extended_mont(rec) == te.te_add(tp[ja[i]], tp[jb[i]]), (form, int(i))
