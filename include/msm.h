@@ -236,6 +236,24 @@ int msm_bucket_accumulate(const uint32_t* xyu, const uint32_t* scalars, size_t n
 int msm_run(const uint32_t* xyu, const uint32_t* scalars, size_t n, int c, int encoding,
             uint32_t* result, void* ws, size_t ws_bytes, void* stream);
 
+/* Full MSM as msm_run, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the workspace is a library-owned device array of
+ * MSM_NOALLOC_SCRATCH_BYTES per GPU (reserved when the library is loaded on
+ * that GPU and held until the process ends), so the call allocates nothing;
+ * the caller passes inputs and the result buffer as for msm_run.  It fits n
+ * up to 2^16 points at the default width in every encoding
+ * (msm_workspace_bytes(n, c, encoding) must not exceed
+ * MSM_NOALLOC_SCRATCH_BYTES).  Every call on a GPU
+ * shares that GPU's array: calls whose work overlaps on one GPU (on
+ * different streams, or from several threads) race and must be ordered by
+ * the caller; each call initialises what it reads of the array.  No timing
+ * events are recorded.  Errors: as msm_run, and MSM_ENOSPC when the MSM
+ * needs more than the array. */
+#define MSM_NOALLOC_SCRATCH_BYTES (128u << 20)
+int msm_run_noalloc(const uint32_t* xyu, const uint32_t* scalars, size_t n, int c, int encoding,
+                    uint32_t* result, void* stream);
+
 /* Batched MSMs: many independent MSMs of different sizes as one launch
  * sequence (Sec. II-C per job; running many independent units side by side
  * is the paper's way of scaling PADD throughput, Sec. IV).  Jobs with the

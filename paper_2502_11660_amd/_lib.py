@@ -39,6 +39,7 @@ MSM_MUL_BARRETT = 1
 MSM_MUL_KARATSUBA = 2
 MSM_MUL_WIDE = 3
 MSM_MUL_F28 = 4
+MSM_NOALLOC_SCRATCH_BYTES = 128 << 20
 MSM_PROFILE_OFF = 0
 MSM_PROFILE_PHASES = 1
 MSM_PROFILE_ACCUM_KERNEL = 2
@@ -65,6 +66,7 @@ SIGNATURES = {
     "msm_window_bits": (_I, [_I, _I]),
     "msm_bucket_accumulate": (_I, [_P, _P, _SZ, _I, _I, _P, _P, _SZ, _P]),
     "msm_run": (_I, [_P, _P, _SZ, _I, _I, _P, _P, _SZ, _P]),
+    "msm_run_noalloc": (_I, [_P, _P, _SZ, _I, _I, _P, _P]),
     "msm_batch_workspace_bytes": (_SZ, [ctypes.POINTER(MsmJob), _SZ, _I]),
     "msm_batch_create": (_I, [ctypes.POINTER(MsmJob), _SZ, _I, _P, _SZ, _I,
                               ctypes.POINTER(ctypes.c_void_p)]),

@@ -216,6 +216,22 @@ def msm_run(xyu, scalars, n, c=0, encoding=MSM_DIGITS_SIGNED, result=None, ws=No
     return result
 
 
+def msm_run_noalloc(xyu, scalars, n, c=0, encoding=MSM_DIGITS_SIGNED, result=None):
+    """msm_run on the library's own device scratch (msm_run_noalloc): no
+    workspace argument; the call allocates nothing (pass `result` to keep
+    the caller side allocation-free too)."""
+    _dev(xyu, "xyu")
+    _dev(scalars, "scalars")
+    if xyu.numel() != XYU_WORDS * _records(n, encoding) or scalars.numel() != SCALAR_WORDS * n:
+        raise ValueError("input sizes do not match n")
+    if result is None:
+        result = words(MSM_RESULT_WORDS, xyu.device)
+    _dev(result, "result")
+    _lib.check("msm_run_noalloc", _lib.lib().msm_run_noalloc(
+        _ptr(xyu), _ptr(scalars), n, c, encoding, _ptr(result), _stream()))
+    return result
+
+
 def _job_array(jobs, encoding=MSM_DIGITS_SIGNED):
     arr = (MsmJob * len(jobs))()
     for a, (xyu, scalars, result, n, c) in zip(arr, jobs):

@@ -49,7 +49,12 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 void set_last_hip_error(int e) { g_last_hip = e; }
 
+// set while msm_run_noalloc enqueues: no timing events are taken then (an
+// event pool refill would create events)
+static thread_local bool t_no_events = false;
+
 ProfScope::ProfScope(int t, hipStream_t s) : tag(t), st(s) {
+  if (t_no_events) return;
   std::lock_guard<std::mutex> g(g_prof.mu);
   if (g_prof.mode != MSM_PROFILE_PHASES) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -66,6 +71,7 @@ ProfScope::~ProfScope() {
 }
 
 bool prof_kernel_events(int tag, hipStream_t st, hipEvent_t* a, hipEvent_t* b) {
+  if (t_no_events) return false;
   std::lock_guard<std::mutex> g(g_prof.mu);
   if (g_prof.mode != MSM_PROFILE_ACCUM_KERNEL || tag != PT_ACCUM) return false;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -226,6 +232,32 @@ int enqueue_msm(const Plan& pl, void* ws, hipStream_t st) {
   return launch_horner(pl, ws, st);
 }
 
+// Scratch of msm_run_noalloc: a file-scope device array, one copy per GPU,
+// held until the process ends.  Host code must not use the array's name as a
+// device address; the address comes from hipGetSymbolAddress, taken once per
+// device (with that device current) on the entry point's first call there.
+constexpr size_t kScratchBytes = (size_t)MSM_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static int scratch_of_current_device(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return MSM_EINVAL;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return MSM_EHIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MSM_OK;
+}
+
 }  // namespace msm
 
 using namespace msm;
@@ -317,6 +349,25 @@ int msm_run(const uint32_t* xyu, const uint32_t* scalars, size_t n, int c, int e
   pl.one.scalars = scalars;
   pl.one.result = result;
   return enqueue_msm(pl, ws, (hipStream_t)stream);
+}
+
+int msm_run_noalloc(const uint32_t* xyu, const uint32_t* scalars, size_t n, int c, int encoding,
+                    uint32_t* result, void* stream) {
+  if (!xyu || !scalars || !result) return MSM_EINVAL;
+  if (c == 0) c = default_window(n);
+  Plan pl;
+  if (!make_plan(&n, 1, c, encoding, pl)) return MSM_EINVAL;
+  if (pl.bytes > kScratchBytes) return MSM_ENOSPC;  // the MSM needs more than the scratch
+  void* ws = nullptr;
+  const int rc = scratch_of_current_device(&ws);
+  if (rc != MSM_OK) return rc;
+  pl.one.xyu = xyu;
+  pl.one.scalars = scalars;
+  pl.one.result = result;
+  t_no_events = true;
+  const int rc2 = enqueue_msm(pl, ws, (hipStream_t)stream);
+  t_no_events = false;
+  return rc2;
 }
 
 int msm_profile_enable(int mode) {

@@ -74,6 +74,11 @@ def test_argument_validation_without_gpu(lib):
     assert lib.msm_run(p, p, 16, 1, S, p, p, 1 << 30, None) == _lib.MSM_EINVAL  # signed: c >= 2
     assert lib.msm_run(p, p, 16, 8, 7, p, p, 1 << 30, None) == _lib.MSM_EINVAL
     assert lib.msm_run(p, p, 16, 8, S, p, p, 100, None) == _lib.MSM_ENOSPC
+    assert lib.msm_run_noalloc(None, p, 16, 8, S, p, None) == _lib.MSM_EINVAL
+    assert lib.msm_run_noalloc(p, p, 0, 8, S, p, None) == _lib.MSM_EINVAL
+    assert lib.msm_run_noalloc(p, p, 16, 21, S, p, None) == _lib.MSM_EINVAL
+    # more than the library's scratch: refused before any device call
+    assert lib.msm_run_noalloc(p, p, 1 << 20, 16, S, p, None) == _lib.MSM_ENOSPC
     assert lib.msm_bucket_accumulate(p, p, 16, 8, U, None, p, 1 << 30, None) == _lib.MSM_EINVAL
     assert lib.msm_bucket_accumulate(p, p, 1 << 26, 8, U, p, p, 1 << 40, None) == _lib.MSM_EINVAL
     assert lib.msm_workspace_bytes(0, 8, S) == 0
