@@ -501,30 +501,44 @@ def batched_leg(torch, api, wl, pools, s_all):
     print("[bench] autotuned %d size classes x 2 encodings in %.1f s" % (len(bu), tune_s),
           file=sys.stderr, flush=True)
 
-    def jobs_with(enc, cfun, results):
+    def jobs_with(enc, cfun, results, sfun=None):
         rec = 2 if enc == "glv" else 1
         jobs = []
         for j, n in enumerate(wl.sizes4):
             o, so = wl.offs4[j], wl.soffs4[j]
             jobs.append((pools[enc][rec * o * 36:rec * (o + n) * 36], s_dev[so * 8:(so + n) * 8],
-                         results[j], n, cfun(n)))
+                         results[j], n, cfun(n), sfun(n) if sfun else None))
         return jobs
 
     reps = 5
     out = {"jobs": JOBS, "points": int(sum(wl.sizes4)), "sizes_log2_range": [10, 18],
            "seed": wl.seed4, "autotune_s": tune_s,
-           "tuned_c": {enc: {"u%d" % u: t.choose(1 << u) for u in bu} for enc, t in tuners.items()}}
+           "tuned_c": {enc: {"u%d" % u: t.choose(1 << u) for u in bu} for enc, t in tuners.items()},
+           "tuned_schedule": {enc: {"u%d" % u: t.schedule(1 << u) for u in bu}
+                              for enc, t in tuners.items()}}
     res_b = {enc: [api.words(api.MSM_RESULT_WORDS, dev) for _ in wl.sizes4] for enc in tuners}
     for enc, t in tuners.items():
         for graph in (True, False):
-            b = api.Batch(jobs_with(enc, t.choose, res_b[enc]), ENCODINGS[enc], use_graph=graph)
+            b = api.Batch(jobs_with(enc, t.choose, res_b[enc], t.schedule), ENCODINGS[enc],
+                          use_graph=graph)
             b.run()
             ms = timed(b.run, reps, torch)
             out["batched_%s_%s" % (enc, "graph" if graph else "nograph")] = {
                 "ms": ms, "msms_per_s": JOBS / (ms * 1e-3),
-                "classes": len({t.choose(n) for n in wl.sizes4})}
+                "classes": len({(t.choose(n), tuple(sorted(t.schedule(n).items())))
+                                for n in wl.sizes4})}
             b.destroy()
-    best = min((k for k in out if k.startswith("batched_")), key=lambda k: out[k]["ms"])
+    # the best encoding's batch with widths tuned but the default schedule
+    enc_s = min(("signed", "glv"), key=lambda e: min(out["batched_%s_graph" % e]["ms"],
+                                                      out["batched_%s_nograph" % e]["ms"]))
+    b = api.Batch(jobs_with(enc_s, tuners[enc_s].choose, res_b[enc_s]), ENCODINGS[enc_s],
+                  use_graph=False)
+    b.run()
+    ms = timed(b.run, reps, torch)
+    out["batched_%s_nograph_default_schedule" % enc_s] = {"ms": ms, "msms_per_s": JOBS / (ms * 1e-3)}
+    b.destroy()
+    best = min((k for k in out if k.startswith("batched_") and "default_schedule" not in k),
+               key=lambda k: out[k]["ms"])
     best_enc = best.split("_")[1]
     out["batched_best"] = best
     maxws = max(max(api.workspace_bytes(n, api.default_window(n)) for n in wl.sizes4),
@@ -536,7 +550,7 @@ def batched_leg(torch, api, wl, pools, s_all):
         jobs = jobs_with(enc, cfun, results)
 
         def seq():
-            for (x, sc, r, n, c) in jobs:
+            for (x, sc, r, n, c, _) in jobs:
                 api.msm_run(x, sc, n, c, ENCODINGS[enc], result=r, ws=ws)
         seq()
         return timed(seq, reps, torch)
@@ -646,14 +660,28 @@ def served_leg(torch, api, wl, pools, args):
 
 def bucket_scatter_figure(phases_ms, entries, n):
     """Algorithmic HBM bytes of the digit slicing and bucket sort at n points
-    with `entries` digit entries (non-zero and zero digits alike are slotted),
-    per the layout: 32 B of scalar read per point; per entry a 4-byte digit
+    with `entries` digit slots (non-zero and zero digits alike are slotted),
+    per the layout: 32 B of scalar read per point; per slot a 4-byte digit
     written and read, an 8-byte (index, key) staging pair written and read,
-    and the sorted key and index written (8 B)."""
+    and the sorted key and index written (8 B); and the bytes the committed
+    rocprofv3 counter summary measured for the sort phase's kernels, per
+    slot, times these slots (null when the sort sources changed since)."""
     nbytes = 32 * n + entries * (4 + 4 + 8 + 8 + 8)
     ms = phases_ms.get("sort")
-    return {"algorithmic_bytes": nbytes, "phase_ms": ms,
-            "GBps": nbytes / (ms * 1e-3) / 1e9 if ms else None}
+    out = {"algorithmic_bytes": nbytes, "phase_ms": ms,
+           "GBps": nbytes / (ms * 1e-3) / 1e9 if ms else None,
+           "traffic_bytes": None, "traffic_GBps": None}
+    from paper_2502_11660_amd import profsum
+    try:
+        with open(os.path.join(ROOT, "profiles", "sort_phase_traffic.json")) as f:
+            rec = json.load(f)
+        if rec.get("sources_sha256") == profsum.sources_sha256(rec.get("sources", [])):
+            tb = rec["bytes_per_entry"] * entries
+            out["traffic_bytes"] = tb
+            out["traffic_GBps"] = tb / (ms * 1e-3) / 1e9 if ms else None
+    except (OSError, ValueError, KeyError):
+        pass
+    return out
 
 
 def main():
@@ -677,6 +705,9 @@ def main():
                     help="measured seconds of the served trace")
     ap.add_argument("--serve-warmup", type=float, default=5.0,
                     help="warm-up seconds of the served trace")
+    ap.add_argument("--msm-only", action="store_true",
+                    help="only the n = 2^20 MSM at --c/--encoding (for profiling): no oracle leg, "
+                         "no n = 1024 run, no PADD, batched or served workloads")
     ap.add_argument("--microbench", action="store_true",
                     help="only measure the VALU issue rates and HBM copy bandwidth")
     args = ap.parse_args()
@@ -689,6 +720,8 @@ def main():
     if args.microbench:
         print(json.dumps(microbench()))
         return
+    if args.msm_only:
+        args.no_checks = args.no_padd_kernel = args.no_batch = args.no_serve = True
 
     wl = Workloads(args)
     cpu = None
@@ -736,12 +769,14 @@ def main():
     pts_for = {"signed": xyu, "unsigned": xyu, "glv": xyu_endo}
 
     # workload 1: n = 1024, c = 8, the paper's unsigned slices
-    res1 = api.words(api.MSM_RESULT_WORDS, dev)
-    f1 = lambda: api.msm_run(xyu[:1024 * 36], api.to_device(wl.s1, dev), 1024, 8,
-                             ENCODINGS["unsigned"], result=res1)
-    f1()
-    config1 = {"n": 1024, "c": 8, "digits": "unsigned", "ms": timed(f1, 5, torch),
-               "result_ok": check(api.to_host(res1), expected["c1"] if expected else None)}
+    config1 = None
+    if not args.msm_only:
+        res1 = api.words(api.MSM_RESULT_WORDS, dev)
+        f1 = lambda: api.msm_run(xyu[:1024 * 36], api.to_device(wl.s1, dev), 1024, 8,
+                                 ENCODINGS["unsigned"], result=res1)
+        f1()
+        config1 = {"n": 1024, "c": 8, "digits": "unsigned", "ms": timed(f1, 5, torch),
+                   "result_ok": check(api.to_host(res1), expected["c1"] if expected else None)}
 
     # workload 3: the width sweep (every result checked)
     sweep = sweep_leg(torch, api, wl, pts_for, s_dev, args)
@@ -898,7 +933,7 @@ def main():
             "peak": PEAK_LANE_OPS / 1e12,
             "unit": "T word-products/s (32x32-bit products of the 12-word Montgomery form)",
             "frac": achieved / PEAK_LANE_OPS,
-            "traffic": accum_traffic(),
+            "traffic": accum_traffic(entries),
             "work_per_launch": {"mixed_padds": entries, "word_products_per_padd": MULS_MIXED * MAD_PER_MUL},
             "launch_ms": accum_ms,
         },
@@ -946,9 +981,11 @@ def microbench():
     return out
 
 
-def accum_traffic():
+def accum_traffic(entries):
     """HBM bytes per accumulation launch from the committed rocprofv3 counter
-    summary, if it was taken on the current accumulation kernel sources."""
+    summary, if it was taken on the current accumulation kernel sources: the
+    profiled bytes per digit entry times this launch's entries (the profile
+    may be of another window width), or the profiled bytes per launch."""
     from paper_2502_11660_amd import profsum
     path = os.path.join(ROOT, "profiles", "k_accum_traffic.json")
     try:
@@ -958,6 +995,8 @@ def accum_traffic():
         return None
     if rec.get("sources_sha256") != profsum.sources_sha256(rec.get("sources", [])):
         return None
+    if rec.get("bytes_per_entry"):
+        return rec["bytes_per_entry"] * entries
     return rec.get("bytes_per_launch")
 
 

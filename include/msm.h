@@ -90,8 +90,8 @@ extern "C" {
  * a_xytz: SoA, 4 coordinates x 12 words x count.  b: SoA, 4 coordinates
  * (MSM_FORM_XYTZ, complete addition) or 3 coordinates (MSM_FORM_XYU, mixed
  * addition with Z2 = 1).  out_xytz: SoA like a_xytz, canonical; may alias a.
- * Errors: MSM_EINVAL for null pointers, count = 0 or count >= 2^31, or an
- * unknown b_form. */
+ * Errors: MSM_EINVAL for null pointers, count = 0 or count >= 2^29 (larger
+ * batches exceed the device memory anyway), or an unknown b_form. */
 int msm_padd_batch(const uint32_t* a_xytz, const uint32_t* b, uint32_t* out_xytz, size_t count,
                    int b_form, void* stream);
 
@@ -263,8 +263,16 @@ int msm_run_noalloc(const uint32_t* xyu, const uint32_t* scalars, size_t n, int 
  *
  * msm_job: device pointers owned by the caller (prepared points, scalars,
  * MSM_RESULT_WORDS result words), n >= 1 points, window width c (0 = the
- * msm_default_window(n) choice).  A batch keeps the pointers: between runs
- * the caller may rewrite the scalars and points in place, not move them.
+ * msm_default_window(n) choice), and the schedule (0 = the default for
+ * each): chunk, the digit entries one lane sums in bucket accumulation
+ * (default: enough entries that one resident round of lanes covers the
+ * class; values below 4 are raised to 4); tree_quad, aggregation-tree levels
+ * with fewer outputs than this run on the four-lane unit (default 65536);
+ * tree_wide, levels with at most this many outputs run on the wide two-wave
+ * unit (default 1024).  Jobs of a batch with the same width and schedule
+ * form one class.  The schedule changes the time, never the result.  A batch
+ * keeps the pointers: between runs the caller may rewrite the scalars and
+ * points in place, not move them.
  *
  * msm_batch_workspace_bytes: device bytes a batch of these jobs needs
  *   (0 for invalid jobs).
@@ -287,6 +295,9 @@ typedef struct msm_job {
   uint32_t* result;
   size_t n;
   int c;
+  int chunk;      /* accumulation entries per lane (0 = default) */
+  int tree_quad;  /* quad-unit threshold of the aggregation tree (0 = 65536) */
+  int tree_wide;  /* wide-unit threshold of the aggregation tree (0 = 1024) */
 } msm_job;
 
 typedef struct msm_batch msm_batch;

@@ -48,7 +48,8 @@ MSM_PROFILE_ACCUM_KERNEL = 2
 class MsmJob(ctypes.Structure):
     """struct msm_job"""
     _fields_ = [("xyu", ctypes.c_void_p), ("scalars", ctypes.c_void_p),
-                ("result", ctypes.c_void_p), ("n", ctypes.c_size_t), ("c", ctypes.c_int)]
+                ("result", ctypes.c_void_p), ("n", ctypes.c_size_t), ("c", ctypes.c_int),
+                ("chunk", ctypes.c_int), ("tree_quad", ctypes.c_int), ("tree_wide", ctypes.c_int)]
 
 # every exported symbol and its (restype, argtypes)
 _P = ctypes.c_void_p

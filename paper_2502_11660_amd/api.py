@@ -233,8 +233,13 @@ def msm_run_noalloc(xyu, scalars, n, c=0, encoding=MSM_DIGITS_SIGNED, result=Non
 
 
 def _job_array(jobs, encoding=MSM_DIGITS_SIGNED):
+    """jobs: (xyu, scalars, result, n, c) or (xyu, scalars, result, n, c,
+    schedule) tuples; schedule is a dict with any of chunk, tree_quad,
+    tree_wide (msm_job's schedule fields; missing or 0 = default)."""
     arr = (MsmJob * len(jobs))()
-    for a, (xyu, scalars, result, n, c) in zip(arr, jobs):
+    for a, job in zip(arr, jobs):
+        xyu, scalars, result, n, c = job[:5]
+        sched = job[5] if len(job) > 5 and job[5] else {}
         for t, name in ((xyu, "xyu"), (scalars, "scalars"), (result, "result")):
             _dev(t, name)
         if xyu.numel() < XYU_WORDS * _records(n, encoding) or scalars.numel() < SCALAR_WORDS * n:
@@ -243,6 +248,9 @@ def _job_array(jobs, encoding=MSM_DIGITS_SIGNED):
             raise ValueError("job result buffer too small")
         a.xyu, a.scalars, a.result = xyu.data_ptr(), scalars.data_ptr(), result.data_ptr()
         a.n, a.c = int(n), int(c)
+        a.chunk = int(sched.get("chunk", 0))
+        a.tree_quad = int(sched.get("tree_quad", 0))
+        a.tree_wide = int(sched.get("tree_wide", 0))
     return arr
 
 
@@ -346,10 +354,11 @@ class Server:
         self._live = {}
         self._buf = (ctypes.c_uint64 * 1024)()
 
-    def submit(self, xyu, scalars, result, n, c=0):
+    def submit(self, xyu, scalars, result, n, c=0, schedule=None):
         """Queue one MSM; it runs after the work already enqueued on the
-        current stream (the producer of its inputs)."""
-        arr = _job_array([(xyu, scalars, result, n, c)], self.encoding)
+        current stream (the producer of its inputs).  schedule: as for a
+        batch job (chunk, tree_quad, tree_wide)."""
+        arr = _job_array([(xyu, scalars, result, n, c, schedule)], self.encoding)
         t = ctypes.c_uint64(0)
         _lib.check("msm_server_submit", _lib.lib().msm_server_submit(
             self._h, arr, _stream(), ctypes.byref(t)))

@@ -138,6 +138,8 @@ struct Plan {
   size_t tiles = 0;   // pass-1 sort tiles over all segments
   size_t chunks = 0;  // accumulation chunks
   uint32_t K = 32;    // entries per accumulation chunk
+  uint64_t tree_quad = 65536;  // tree levels with fewer outputs run on quads
+  uint64_t tree_wide = 1024;   // levels with at most this many outputs on wide units
   uint32_t lo_bits = 0, hi_bits = 0;  // split of the bb bucket bits in the sort
   size_t ncounts = 0, nb = 0;         // sort count matrix size, its scan blocks
   JobDesc one{};  // the job when J = 1; otherwise one.xyu is the base of segment offsets
@@ -150,8 +152,21 @@ struct Plan {
 int num_windows(int c, int encoding);
 int window_bits(int c, int encoding);
 int default_window(size_t n);
-// plan of a batch with job sizes ns[0..J); false for invalid sizes or c
-bool make_plan(const size_t* ns, uint32_t J, int c, int encoding, Plan& pl);
+// schedule of a plan (0 = default for each; msm_job's chunk, tree_quad,
+// tree_wide)
+struct Schedule {
+  int chunk = 0, tree_quad = 0, tree_wide = 0;
+  bool operator<(const Schedule& o) const {
+    if (chunk != o.chunk) return chunk < o.chunk;
+    if (tree_quad != o.tree_quad) return tree_quad < o.tree_quad;
+    return tree_wide < o.tree_wide;
+  }
+};
+
+// plan of a batch with job sizes ns[0..J); false for invalid sizes, c or
+// schedule values
+bool make_plan(const size_t* ns, uint32_t J, int c, int encoding, Plan& pl,
+               const Schedule& sched = Schedule());
 
 template <typename T>
 inline T* ws_at(void* ws, size_t off) {

@@ -311,10 +311,6 @@ __global__ void __launch_bounds__(64) k_finalize(const uint32_t* __restrict__ qs
   for (int l = 2 * NL + 2; l < MSM_RESULT_WORDS; ++l) result[l] = 0u;
 }
 
-// below this many outputs a tree level runs on quads, and up to WIDE_UPTO
-// outputs on wide units (one per output)
-constexpr uint64_t QUAD_BELOW = 65536;
-constexpr uint64_t WIDE_UPTO = 1024;
 
 }  // namespace
 
@@ -330,9 +326,11 @@ int launch_aggregate(const Plan& pl, const uint32_t* buckets, void* ws, hipStrea
     const uint64_t outs = (uint64_t)S * (nodes >> 1) * (h + 2);
     const int to_u = (h + 1 == bb) ? 1 : 0;
     const uint64_t adds = (uint64_t)S * (nodes >> 1) * (h + 1);
-    if (outs >= QUAD_BELOW)
+    // the schedule's unit thresholds (defaults: below 65536 outputs a level
+    // runs on quads, up to 1024 outputs on wide units, one per output)
+    if (outs >= pl.tree_quad)
       k_tree_level<<<(unsigned)((adds + 255) / 256), 256, 0, st>>>(in, h, nodes, 0, S, out, to_u);
-    else if (outs > WIDE_UPTO)
+    else if (outs > pl.tree_wide)
       k_tree_level_quad<<<(unsigned)((4 * outs + 255) / 256), 256, 0, st>>>(in, h, nodes, 0, S,
                                                                            out, to_u);
     else

@@ -21,39 +21,79 @@ __global__ void __launch_bounds__(256) k_fe_mul(const uint32_t* __restrict__ a,
   st_soa(out, count, 0, i, r);
 }
 
+// SoA rows through buffer instructions: row r of an array (word r count + i
+// of element i) is a wave-uniform base, so its buffer descriptor lives in
+// scalar registers and every load or store takes the one per-lane byte
+// offset 4 i, with no per-access address arithmetic on the vector unit.
+// Requires count < 2^29 (4 count fits a descriptor's 32-bit byte range).
+constexpr uint32_t kBufferFlags = 0x00020000u;  // raw 32-bit buffer access
+
+__device__ __forceinline__ fe ld_rows(const uint32_t* __restrict__ base, uint32_t count, int coord,
+                                      uint32_t voff) {
+  fe r;
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
+    const uint32_t* row = base + (size_t)(coord * NL + l) * count;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)row, 0, (int)(count * 4u), kBufferFlags);
+    r.v[l] = __builtin_amdgcn_raw_buffer_load_b32(rs, voff, 0, 0);
+  }
+  return r;
+}
+
+__device__ __forceinline__ void st_rows(uint32_t* __restrict__ base, uint32_t count, int coord,
+                                        uint32_t voff, const fe& x) {
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
+    uint32_t* row = base + (size_t)(coord * NL + l) * count;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)row, 0, (int)(count * 4u), kBufferFlags);
+    __builtin_amdgcn_raw_buffer_store_b32(x.v[l], rs, voff, 0, 0);
+  }
+}
+
+// canonical form of a product output (< 2p): one conditional subtraction
+__device__ __forceinline__ fe canon_of_product(const fe28& x) {
+  const fe w = f28_to_words(x);
+  uint64_t br;
+  const fe t = fe_sub_mask(w, fe_const(kP), br);
+  return fe_pick(br, w, t);
+}
+
 // out_i = a_i + b_i, SoA limb-major operands; FORM selects the mixed
 // (b prepared: X, Y, U, Z = 1) or the complete (b extended) addition.  On the
 // carry-free 28-bit field form (curve28.hpp); outputs canonical.
 template <int FORM>
 __global__ void __launch_bounds__(256) k_padd(const uint32_t* __restrict__ a,
-                                                const uint32_t* __restrict__ b,
-                                                uint32_t* __restrict__ out, uint32_t count) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+                                              const uint32_t* __restrict__ b,
+                                              uint32_t* __restrict__ out, uint32_t count) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
+  const uint32_t vo = 4u * i;
   xytz28 pa;
-  pa.X = f28_from_words(ld_soa(a, count, 0, i));
-  pa.Y = f28_from_words(ld_soa(a, count, 1, i));
-  pa.T = f28_from_words(ld_soa(a, count, 2, i));
-  pa.Z = f28_from_words(ld_soa(a, count, 3, i));
+  pa.X = f28_from_words(ld_rows(a, count, 0, vo));
+  pa.Y = f28_from_words(ld_rows(a, count, 1, vo));
+  pa.T = f28_from_words(ld_rows(a, count, 2, vo));
+  pa.Z = f28_from_words(ld_rows(a, count, 3, vo));
   xytz28 r;
   if (FORM == MSM_FORM_XYU) {
     xyu28 pb;
-    pb.X = f28_from_words(ld_soa(b, count, 0, i));
-    pb.Y = f28_from_words(ld_soa(b, count, 1, i));
-    pb.U = f28_from_words(ld_soa(b, count, 2, i));
+    pb.X = f28_from_words(ld_rows(b, count, 0, vo));
+    pb.Y = f28_from_words(ld_rows(b, count, 1, vo));
+    pb.U = f28_from_words(ld_rows(b, count, 2, vo));
     r = padd28_mixed(pa, pb);
   } else {
     xytz28 pb;
-    pb.X = f28_from_words(ld_soa(b, count, 0, i));
-    pb.Y = f28_from_words(ld_soa(b, count, 1, i));
-    pb.T = f28_from_words(ld_soa(b, count, 2, i));
-    pb.Z = f28_from_words(ld_soa(b, count, 3, i));
+    pb.X = f28_from_words(ld_rows(b, count, 0, vo));
+    pb.Y = f28_from_words(ld_rows(b, count, 1, vo));
+    pb.T = f28_from_words(ld_rows(b, count, 2, vo));
+    pb.Z = f28_from_words(ld_rows(b, count, 3, vo));
     r = padd28_full(pa, pb);
   }
-  st_soa(out, count, 0, i, fe_canon(f28_to_words(r.X)));
-  st_soa(out, count, 1, i, fe_canon(f28_to_words(r.Y)));
-  st_soa(out, count, 2, i, fe_canon(f28_to_words(r.T)));
-  st_soa(out, count, 3, i, fe_canon(f28_to_words(r.Z)));
+  st_rows(out, count, 0, vo, canon_of_product(r.X));
+  st_rows(out, count, 1, vo, canon_of_product(r.Y));
+  st_rows(out, count, 2, vo, canon_of_product(r.T));
+  st_rows(out, count, 3, vo, canon_of_product(r.Z));
 }
 
 // Weierstrass affine (ordinary form) -> prepared (X, Y, U = k x y), Z = 1

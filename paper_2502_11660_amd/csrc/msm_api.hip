@@ -138,10 +138,14 @@ static int device_cus() {
   return cus;
 }
 
-bool make_plan(const size_t* ns, uint32_t J, int c_req, int encoding, Plan& pl) {
+bool make_plan(const size_t* ns, uint32_t J, int c_req, int encoding, Plan& pl,
+               const Schedule& sched) {
   pl = Plan();
   const int W = num_windows(c_req, encoding);
   if (W == 0 || J == 0 || !ns) return false;
+  if (sched.chunk < 0 || sched.tree_quad < 0 || sched.tree_wide < 0) return false;
+  if (sched.tree_quad) pl.tree_quad = (uint64_t)sched.tree_quad;
+  if (sched.tree_wide) pl.tree_wide = (uint64_t)sched.tree_wide;
   const int c = window_bits(c_req, encoding);
   pl.c = c;
   pl.W = W;
@@ -177,7 +181,8 @@ bool make_plan(const size_t* ns, uint32_t J, int c_req, int encoding, Plan& pl) 
   // waves per SIMD), so that every lane runs exactly once and no second,
   // mostly idle round follows; at least 16 entries per chunk
   const size_t lanes = (size_t)device_cus() * 4 * 3 * 64;
-  pl.K = (uint32_t)std::max<size_t>(16, (pl.NW + lanes - 1) / lanes);
+  pl.K = sched.chunk ? (uint32_t)std::max(4, sched.chunk)
+                     : (uint32_t)std::max<size_t>(16, (pl.NW + lanes - 1) / lanes);
   pl.chunks = (pl.NW + pl.K - 1) / pl.K;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -297,7 +302,7 @@ int msm_fe_mul_batch(const uint32_t* a, const uint32_t* b, uint32_t* out, size_t
 
 int msm_padd_batch(const uint32_t* a_xytz, const uint32_t* b, uint32_t* out_xytz, size_t count,
                    int b_form, void* stream) {
-  if (!a_xytz || !b || !out_xytz || count == 0 || count >= (1u << 31)) return MSM_EINVAL;
+  if (!a_xytz || !b || !out_xytz || count == 0 || count >= (1u << 29)) return MSM_EINVAL;
   if (b_form != MSM_FORM_XYTZ && b_form != MSM_FORM_XYU) return MSM_EINVAL;
   return launch_padd(a_xytz, b, out_xytz, (uint32_t)count, b_form, (hipStream_t)stream);
 }

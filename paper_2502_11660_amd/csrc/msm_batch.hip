@@ -1,6 +1,7 @@
 // Batched MSMs (msm_batch_* in include/msm.h).
 //
-// Jobs are grouped into classes by window width.  Each class is one pipeline
+// Jobs are grouped into classes by window width and schedule (accumulation
+// chunk size, aggregation-tree unit thresholds).  Each class is one pipeline
 // (sort, accumulation, aggregation, group aggregation) whose kernels cover
 // every window of every job in the class, so a batch of many small MSMs fills
 // the chip like one large MSM and its many latency-bound group-aggregation
@@ -34,29 +35,41 @@ namespace {
 
 inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-// classes of a job list: window width -> job indices (in job order)
-bool classify(const msm_job* jobs, size_t njobs, int encoding,
-              std::map<int, std::vector<size_t>>& cls) {
+// a class: jobs with the same window width and schedule
+typedef std::pair<int, Schedule> ClassKey;
+typedef std::map<ClassKey, std::vector<size_t>> Classes;
+
+Schedule schedule_of(const msm_job& jb) {
+  Schedule s;
+  s.chunk = jb.chunk;
+  s.tree_quad = jb.tree_quad;
+  s.tree_wide = jb.tree_wide;
+  return s;
+}
+
+// classes of a job list: (window width, schedule) -> job indices (in job order)
+bool classify(const msm_job* jobs, size_t njobs, int encoding, Classes& cls) {
   if (!jobs || njobs == 0 || njobs >= ((size_t)1 << 20)) return false;
   for (size_t i = 0; i < njobs; ++i) {
     const msm_job& jb = jobs[i];
     if (!jb.xyu || !jb.scalars || !jb.result || jb.n == 0) return false;
+    if (jb.chunk < 0 || jb.tree_quad < 0 || jb.tree_wide < 0) return false;
     const int c = jb.c == 0 ? default_window(jb.n) : jb.c;
     if (num_windows(c, encoding) == 0) return false;
-    cls[c].push_back(i);
+    cls[ClassKey(c, schedule_of(jb))].push_back(i);
   }
   return true;
 }
 
-bool plan_classes(const msm_job* jobs, const std::map<int, std::vector<size_t>>& cls,
-                  int encoding, std::vector<Plan>& plans, std::vector<size_t>& off,
-                  size_t& total) {
+bool plan_classes(const msm_job* jobs, const Classes& cls, int encoding, std::vector<Plan>& plans,
+                  std::vector<size_t>& off, size_t& total) {
   total = 0;
   for (const auto& kv : cls) {
     std::vector<size_t> ns;
     for (size_t i : kv.second) ns.push_back(jobs[i].n);
     Plan pl;
-    if (!make_plan(ns.data(), (uint32_t)ns.size(), kv.first, encoding, pl)) return false;
+    if (!make_plan(ns.data(), (uint32_t)ns.size(), kv.first.first, encoding, pl, kv.first.second))
+      return false;
     plans.push_back(pl);
     off.push_back(total);
     total += align256(pl.bytes);
@@ -93,7 +106,7 @@ void release(msm_batch* b) {
 
 int create(const msm_job* jobs, size_t njobs, int encoding, void* ws, size_t ws_bytes,
            int use_graph, msm_batch* b) {
-  std::map<int, std::vector<size_t>> cls;
+  Classes cls;
   if (!ws || !classify(jobs, njobs, encoding, cls)) return MSM_EINVAL;
   size_t total = 0;
   if (!plan_classes(jobs, cls, encoding, b->plans, b->ws_off, total)) return MSM_EINVAL;
@@ -152,7 +165,7 @@ int create(const msm_job* jobs, size_t njobs, int encoding, void* ws, size_t ws_
 extern "C" {
 
 size_t msm_batch_workspace_bytes(const msm_job* jobs, size_t njobs, int encoding) {
-  std::map<int, std::vector<size_t>> cls;
+  Classes cls;
   if (!classify(jobs, njobs, encoding, cls)) return 0;
   std::vector<Plan> plans;
   std::vector<size_t> off;

@@ -209,7 +209,11 @@ int msm_server_submit(msm_server* s, const msm_job* job, void* stream, uint64_t*
   r.job = *job;
   const int c = job->c == 0 ? default_window(job->n) : job->c;
   size_t n = job->n;
-  if (!make_plan(&n, 1, c, s->encoding, r.plan)) return MSM_EINVAL;
+  Schedule sched;
+  sched.chunk = job->chunk;
+  sched.tree_quad = job->tree_quad;
+  sched.tree_wide = job->tree_wide;
+  if (!make_plan(&n, 1, c, s->encoding, r.plan, sched)) return MSM_EINVAL;
   if (r.plan.bytes > s->arena.size) return MSM_ENOSPC;
   r.plan.one.xyu = job->xyu;
   r.plan.one.scalars = job->scalars;

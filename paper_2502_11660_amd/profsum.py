@@ -4,12 +4,20 @@
       markdown table: kernel, calls, total ms, average us, share of time
   python -m paper_2502_11660_amd.profsum traffic --fetch CSV --write CSV
           --calib-fetch CSV --calib-write CSV --copy-bytes N --kernel NAME
+          [--entries E]
       HBM bytes per launch of one kernel from FETCH_SIZE / WRITE_SIZE counter
       runs (KiB per dispatch), each scaled by the factor that maps the same
       counter on the copy microbenchmark (k_mb_copy, N bytes read and N bytes
       written per launch) onto its known size; prints JSON, including a
       SHA-256 of the accumulation kernel's sources so that a reader can tell
-      whether the counters still describe the current kernel.
+      whether the counters still describe the current kernel, and with
+      --entries the bytes per digit entry of the profiled launches.
+  python -m paper_2502_11660_amd.profsum valu CSV [--kernel NAME ...]
+      VALU counters per dispatch of the named kernels (averaged over their
+      dispatches): instructions issued (SQ_INSTS_VALU and its 32/64-bit
+      integer parts), SQ_ACTIVE_INST_VALU, GRBM_GUI_ACTIVE summed over the
+      XCDs and the dispatch time, hence the mean engine clock and the share
+      of SIMD cycles that issue VALU work (4 cycles per wave64 instruction).
 """
 
 import argparse
@@ -22,7 +30,8 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ACCUM_SOURCES = ["paper_2502_11660_amd/csrc/k_accum.hip", "paper_2502_11660_amd/csrc/curve.hpp",
-                 "paper_2502_11660_amd/csrc/field.hpp"]
+                 "paper_2502_11660_amd/csrc/field.hpp", "paper_2502_11660_amd/csrc/fe28.hpp",
+                 "paper_2502_11660_amd/csrc/curve28.hpp"]
 
 
 def short_name(name):
@@ -51,36 +60,76 @@ def stats_table(path):
 
 
 def counter_per_dispatch(path, kernel, counter):
-    vals = []
+    """The counter's value per dispatch of the kernel, for the dispatches of
+    its largest grid (smaller launches of the same kernel in the profiled
+    program, such as a small MSM before the measured one, are left out)."""
+    per = {}
+    grid = {}
     for r in csv.DictReader(open(path)):
         if short_name(r["Kernel_Name"]) == kernel and r["Counter_Name"] == counter:
-            vals.append(float(r["Counter_Value"]))
-    if not vals:
+            d = r["Dispatch_Id"]
+            per[d] = per.get(d, 0.0) + float(r["Counter_Value"])
+            grid[d] = int(r.get("Grid_Size") or 0)
+    if not per:
         raise SystemExit("no %s samples of %s in %s" % (counter, kernel, path))
-    return vals
+    top = max(grid.values())
+    return [v for d, v in per.items() if grid[d] == top]
 
 
 def traffic(args):
+    """HBM bytes per launch of one kernel, or summed over several kernels
+    (one launch each, e.g. the kernels of one phase)."""
     kib = 1024.0
     cf = counter_per_dispatch(args.calib_fetch, "k_mb_copy", "FETCH_SIZE")
     cw = counter_per_dispatch(args.calib_write, "k_mb_copy", "WRITE_SIZE")
     f_fac = args.copy_bytes / (sum(cf) / len(cf) * kib)
     w_fac = args.copy_bytes / (sum(cw) / len(cw) * kib)
-    kf = counter_per_dispatch(args.fetch, args.kernel, "FETCH_SIZE")
-    kw = counter_per_dispatch(args.write, args.kernel, "WRITE_SIZE")
-    fetch = sum(kf) / len(kf) * kib * f_fac
-    write = sum(kw) / len(kw) * kib * w_fac
+    fetch = write = 0.0
+    launches = []
+    for k in args.kernel:
+        kf = counter_per_dispatch(args.fetch, k, "FETCH_SIZE")
+        kw = counter_per_dispatch(args.write, k, "WRITE_SIZE")
+        fetch += sum(kf) / len(kf) * kib * f_fac
+        write += sum(kw) / len(kw) * kib * w_fac
+        launches.append([len(kf), len(kw)])
+    sources = ACCUM_SOURCES if args.kernel == ["k_accum"] else args.sources
     return {
-        "kernel": args.kernel,
+        "kernel": args.kernel[0] if len(args.kernel) == 1 else args.kernel,
         "fetch_bytes_per_launch": fetch,
         "write_bytes_per_launch": write,
         "bytes_per_launch": fetch + write,
-        "launches": [len(kf), len(kw)],
+        "launches": launches[0] if len(launches) == 1 else launches,
         "copy_calibration": {"bytes_each_way": args.copy_bytes, "fetch_factor": f_fac,
                              "write_factor": w_fac},
-        "sources": ACCUM_SOURCES,
-        "sources_sha256": sources_sha256(),
+        "sources": sources,
+        "sources_sha256": sources_sha256(sources),
     }
+
+
+def valu(args, xcds=8, simds=1024):
+    rows = list(csv.DictReader(open(args.csv)))
+    out = {}
+    for name in args.kernel:
+        per = {}
+        for r in rows:
+            if short_name(r["Kernel_Name"]) != name:
+                continue
+            d = per.setdefault(r["Dispatch_Id"], {"ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
+            d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        if not per:
+            raise SystemExit("no dispatches of %s in %s" % (name, args.csv))
+        big = max(per.values(), key=lambda d: d.get("SQ_INSTS_VALU", 0.0))
+        keep = [d for d in per.values() if d.get("SQ_INSTS_VALU", 0.0) >= 0.5 * big.get("SQ_INSTS_VALU", 0.0)]
+        avg = {k: sum(d[k] for d in keep) / len(keep) for k in keep[0]}
+        cyc = avg.get("GRBM_GUI_ACTIVE", 0.0) / xcds
+        ent = {"dispatches": len(keep), "ns": avg["ns"]}
+        ent.update({k: avg[k] for k in sorted(avg) if k != "ns"})
+        if cyc:
+            ent["engine_clock_GHz"] = cyc / avg["ns"]
+            if "SQ_INSTS_VALU" in avg:
+                ent["valu_issue_share"] = 4.0 * avg["SQ_INSTS_VALU"] / (simds * cyc)
+        out[name] = ent
+    return out
 
 
 def main(argv=None):
@@ -92,12 +141,27 @@ def main(argv=None):
     for k in ("fetch", "write", "calib_fetch", "calib_write"):
         t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
     t.add_argument("--copy-bytes", type=float, required=True)
-    t.add_argument("--kernel", default="k_accum")
+    t.add_argument("--kernel", action="append", default=None,
+                   help="kernel (repeat to sum several); default k_accum")
+    t.add_argument("--sources", nargs="*", default=[],
+                   help="source files the figure describes (default: the accumulation kernel's)")
+    t.add_argument("--entries", type=float, default=0.0,
+                   help="digit entries per profiled launch (adds bytes per entry)")
+    v = sub.add_parser("valu")
+    v.add_argument("csv")
+    v.add_argument("--kernel", action="append", required=True)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(stats_table(a.csv))
+    elif a.cmd == "valu":
+        print(json.dumps(valu(a), indent=1))
     else:
-        print(json.dumps(traffic(a), indent=1))
+        a.kernel = a.kernel or ["k_accum"]
+        rec = traffic(a)
+        if a.entries:
+            rec["entries_per_launch"] = a.entries
+            rec["bytes_per_entry"] = rec["bytes_per_launch"] / a.entries
+        print(json.dumps(rec, indent=1))
 
 
 if __name__ == "__main__":

@@ -54,7 +54,7 @@ def replay_plain(arrivals, jobs, encoding=api.MSM_DIGITS_SIGNED, workspaces=None
     for i in range(nreq):
         while time.perf_counter() - t0 < arrivals[i]:
             pass
-        xyu, sc, res, n, c = jobs[i]
+        xyu, sc, res, n, c = jobs[i][:5]
         ws = workspaces(n, c) if workspaces else None
         api.msm_run(xyu, sc, n, c, encoding, result=res, ws=ws)
         torch.cuda.current_stream().synchronize()

@@ -102,6 +102,10 @@ def test_argument_validation_without_gpu(lib):
     assert lib.msm_batch_workspace_bytes(jobs, 2, S) == 0          # n = 0
     assert lib.msm_batch_workspace_bytes(jobs, 1, S) > 0
     assert lib.msm_batch_workspace_bytes(jobs, 0, S) == 0
+    neg = (Job * 1)(Job(16, 16, 16, 100, 8, -1, 0, 0))
+    assert lib.msm_batch_workspace_bytes(neg, 1, S) == 0          # negative schedule value
+    sch = (Job * 2)(Job(16, 16, 16, 100, 8), Job(16, 16, 16, 100, 8, 7, 16, 4096))
+    assert lib.msm_batch_workspace_bytes(sch, 2, S) > lib.msm_batch_workspace_bytes(sch, 1, S)
     h = ctypes.c_void_p()
     assert lib.msm_batch_create(jobs, 2, S, p, 1 << 40, 0, ctypes.byref(h)) == _lib.MSM_EINVAL
     assert lib.msm_batch_create(jobs, 1, S, p, 100, 0, ctypes.byref(h)) == _lib.MSM_ENOSPC

@@ -143,3 +143,39 @@ def test_batch_64_jobs_log_uniform_sizes():
     for (x, s, res, n, c) in jobs:
         assert _result(res) == (msm.closed_form(ss[off:off + n], ks[off:off + n]), 0), n
         off += n
+
+
+@pytest.mark.parametrize("sched", [{"chunk": 5}, {"chunk": 300}, {"tree_quad": 2048},
+                                   {"tree_quad": 1 << 20, "tree_wide": 1},
+                                   {"chunk": 7, "tree_quad": 16, "tree_wide": 4096}])
+def test_batch_schedules_change_nothing_but_time(oracle_pool, sched):
+    """Jobs with explicit schedules (accumulation chunk, tree unit thresholds)
+    give the same result words as the default schedule, and the closed form;
+    jobs of one width with different schedules form separate classes."""
+    ks, pts = oracle_pool
+    xyu_pool = _prepared_pool(pts)
+    sizes = [1500, 33, 2048, 700]
+    jobs, meta = _jobs_from_pool(xyu_pool, sizes, [9, 9, 11, 9], 6300)
+    ref = api.Batch(jobs)
+    ref.run()
+    torch.cuda.synchronize()
+    want = [api.to_host(j[2]).copy() for j in jobs]
+    ref.destroy()
+    mixed = [j + ((sched if i % 2 == 0 else None),) for i, j in enumerate(jobs)]
+    for j in jobs:
+        j[2].fill_(-1)
+    b = api.Batch(mixed)
+    b.run()
+    torch.cuda.synchronize()
+    for (xyu, st, res, n, c), (off, sc), w in zip(jobs, meta, want):
+        assert np.array_equal(api.to_host(res), w)
+        assert _result(res) == (msm.closed_form(sc, ks[off:off + n]), 0)
+    b.destroy()
+    srv = api.Server(1 << 28, streams=2)
+    for (xyu, st, res, n, c), w in zip(jobs, want):
+        res.fill_(-1)
+        srv.submit(xyu, st, res, n, c, schedule=sched)
+    srv.drain()
+    for (xyu, st, res, n, c), w in zip(jobs, want):
+        assert np.array_equal(api.to_host(res), w)
+    srv.destroy()
