@@ -52,9 +52,11 @@ import numpy as np  # noqa: E402
 
 N_POINTS = 1 << 20
 ENCODINGS = {"signed": 0, "unsigned": 1, "glv": 2}
-# window widths swept at n = 2^20, per encoding
+# window widths swept at n = 2^20, per encoding (requested widths; widths
+# that the library lowers to the same window layout run once)
 SWEEP = {"unsigned": list(range(10, 17)), "signed": list(range(10, 18)),
          "glv": list(range(10, 21))}
+DIGIT_BITS = {"signed": 254, "unsigned": 253, "glv": 128}
 MAD_PER_MUL = 276          # 144 a*b + 132 m*p 32x32-bit word products per Montgomery multiply
 MULS_MIXED = 7             # mixed PADD (Z2 = 1, U2 = k T2)
 MULS_COMPLETE = 9          # complete PADD with k T2 formed on the fly
@@ -79,15 +81,22 @@ def padd_count_formula(n, c):
 
 
 def num_windows(c, encoding):
-    bits = {"signed": 254, "unsigned": 253, "glv": 128}[encoding]
-    return -(-bits // c)
+    return -(-DIGIT_BITS[encoding] // c)
+
+
+def window_bits(c, encoding):
+    """The width the library runs for a requested c (msm_window_bits): the
+    window count of c, and the smallest width that covers the digit bits
+    with that many windows."""
+    return -(-DIGIT_BITS[encoding] // num_windows(c, encoding))
 
 
 def padd_count_executed(entries, c, encoding="signed", jobs=1):
-    """Additions and doublings the implementation executes for one MSM:
-    accumulation (one mixed addition per non-zero digit), the aggregation
-    tree (2^(bb+1) - bb - 2 per window), the window Horner steps and the
-    group Horner steps (c doublings and one addition per window but the top)."""
+    """Additions and doublings the implementation executes for one MSM at
+    the effective width c (window_bits): accumulation (one mixed addition
+    per non-zero digit), the aggregation tree (2^(bb+1) - bb - 2 per window),
+    the window Horner steps and the group Horner steps (c doublings and one
+    addition per window but the top)."""
     signed = encoding != "unsigned"
     W = num_windows(c, encoding)
     bb = c - 1 if signed else c
@@ -347,8 +356,8 @@ def glv_halves(sw_np):
 
 
 def nonzero_digit_entries(sw_np, c, encoding="signed"):
-    """Number of (point, window) pairs with a non-zero digit: the mixed PADDs
-    bucket accumulation performs."""
+    """Number of (point, window) pairs with a non-zero digit at the effective
+    width c (window_bits): the mixed PADDs bucket accumulation performs."""
     signed = encoding != "unsigned"
     W = num_windows(c, encoding)
     if encoding == "glv":
@@ -377,7 +386,11 @@ def sweep_leg(torch, api, wl, pts_for, s_dev, args):
     """Workload 3: every encoding at every width of SWEEP."""
     dev = s_dev.device
     out = {}
-    cands = [(args.encoding, args.c)] if args.c else [(e, c) for e in SWEEP for c in SWEEP[e]]
+    req = [(args.encoding, args.c)] if args.c else [(e, c) for e in SWEEP for c in SWEEP[e]]
+    cands = []
+    for enc, c in req:   # effective widths, each once
+        if (enc, window_bits(c, enc)) not in cands:
+            cands.append((enc, window_bits(c, enc)))
     for enc, c in cands:
         ws = api.workspace(N_POINTS, c, ENCODINGS[enc], device=dev)
         res = api.words(api.MSM_RESULT_WORDS, dev)
@@ -787,6 +800,9 @@ def main():
         pc = padd_count_executed(ent, c, enc)
         sweep_out["%s_c%d" % (enc, c)] = {
             "ms": ms, "padd_per_s": pc / (ms * 1e-3), "padds": pc,
+            "windows": num_windows(c, enc),
+            "requested_c": [r for r in SWEEP[enc] if window_bits(r, enc) == c] if not args.c
+            else [args.c],
             "ok": check(words, expected["c3"] if expected else None)}
 
     # the headline: timed steps at the best (encoding, width)

@@ -320,7 +320,10 @@ int msm_batch_destroy(msm_batch* batch);
  *   picks msm_default_window(n)).  Its workspace (msm_workspace_bytes) is its
  *   footprint: it is admitted -- launched on the stream with the fewest
  *   requests in flight -- as soon as that much of the arena is free and no
- *   earlier request is still waiting (FIFO).  Ordering: an event is recorded
+ *   earlier request is still waiting (FIFO).  While fewer than three
+ *   requests are in flight, an admitted request's bucket accumulation waits
+ *   for the previous request to finish (arrival order at light load); with
+ *   more in flight, requests overlap fully.  Ordering: an event is recorded
  *   on `stream` (the producer's stream; NULL = the null stream) at the call,
  *   and the request's kernels wait for it, so work the caller enqueued on
  *   that stream before submitting (writing the points or scalars, clearing

@@ -173,8 +173,10 @@ inline T* ws_at(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
 
-// every phase of a planned batch on one stream (msm_api.hip)
-int enqueue_msm(const Plan& pl, void* ws, hipStream_t st);
+// every phase of a planned batch on one stream (msm_api.hip); with an event
+// `accum_after`, the accumulation first waits for that event's last recording
+// (the digit sort does not)
+int enqueue_msm(const Plan& pl, void* ws, hipStream_t st, hipEvent_t accum_after = nullptr);
 
 inline JobView job_view(const Plan& pl, void* ws) {
   JobView v;

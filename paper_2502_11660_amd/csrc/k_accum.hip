@@ -42,8 +42,9 @@ __device__ __forceinline__ const uint32_t* entry_point(const uint32_t* __restric
 // One lane per chunk, on the carry-free 28-bit field form (curve28.hpp):
 // points are converted from their 12-word records as they are loaded, the
 // running sum stays in the 28-bit form and is converted back when it is
-// stored.  (Measured against the 12-word form: 2.16 vs 2.30 ms at n = 2^20;
-// with a register cap for four waves per SIMD it spills and takes 2.26 ms.)
+// stored.  (Measured against the 12-word form: 2.16 vs 2.30 ms at n = 2^20.
+// Four waves per SIMD, reachable without spills when the addition forms C
+// and D first, measured no faster than three with the index prefetch.)
 __global__ void __launch_bounds__(256) k_accum(const uint32_t* __restrict__ pts,
                                                  const int64_t* __restrict__ segoff, uint32_t bb,
                                                  const uint32_t* __restrict__ key,
@@ -63,8 +64,14 @@ __global__ void __launch_bounds__(256) k_accum(const uint32_t* __restrict__ pts,
   const bool open_left = (s > 0) && (key[s - 1] == cur);
   bool first_seg = true;
   xytz28 acc = pt28_identity();
+  // the next entry's key and index are loaded one iteration ahead, so the
+  // point gather does not wait behind the index load
+  uint32_t k_nx = key[s], i_nx = idx[s];
   for (uint32_t p = s; p < e; ++p) {
-    const uint32_t k = key[p];
+    const uint32_t k = k_nx, ie = i_nx;
+    const uint32_t pn = p + 1 < e ? p + 1 : p;
+    k_nx = key[pn];
+    i_nx = idx[pn];
     if (k != cur) {
       uint32_t* dst = (first_seg && open_left) ? head + (size_t)ch * XYTZ_WORDS
                                                : buckets + (size_t)cur * XYTZ_WORDS;
@@ -73,7 +80,6 @@ __global__ void __launch_bounds__(256) k_accum(const uint32_t* __restrict__ pts,
       cur = k;
       first_seg = false;
     }
-    const uint32_t ie = idx[p];
     const xyu28 P = pt28_from(ld_xyu(entry_point(pts, segoff, bb, k, ie)));
     acc = padd28_mixed_signed(acc, P, (ie >> 31) != 0u);
   }

@@ -8,6 +8,7 @@
 //    returning its sum once at the end (the shape of bucket accumulation),
 //    with the mixed addition.
 #include "common.hpp"
+#include "curve28.hpp"
 #include "quad.hpp"
 #include "wide_unit.hpp"
 
@@ -30,20 +31,20 @@ __global__ void __launch_bounds__(64) k_chain_quad(const uint32_t* __restrict__ 
   quad_st(out, acc);
 }
 
-// One lane: the same chain with the whole addition in one lane.
+// One lane: the same chain with the whole addition in one lane (the
+// throughput unit's carry-free 28-bit form).
 __global__ void __launch_bounds__(64) k_chain_lane(const uint32_t* __restrict__ pts,
                                                    uint32_t count, uint32_t* __restrict__ out) {
   if (threadIdx.x != 0) return;
-  const fe p2 = fe_const(kP2);
-  xytz acc = pt_identity();
+  xytz28 acc = pt28_identity();
   xytz nxt = ld_xytz(pts);
   for (uint32_t i = 0; i < count; ++i) {
-    const xytz cur = nxt;
+    const xytz28 cur = pt28_from(nxt);
     const uint32_t j = (i + 1 < count) ? i + 1 : i;
     nxt = ld_xytz(pts + (size_t)j * XYTZ_WORDS);
-    acc = padd_full(acc, cur, p2);
+    acc = padd28_full(acc, cur);
   }
-  st_xytz(out, acc);
+  st_xytz(out, pt28_to_words(acc));
 }
 
 // The wide unit: waves 0 and 1 run the additions (two phases of four
@@ -106,24 +107,19 @@ __global__ void __launch_bounds__(192) k_chain_wide(const uint32_t* __restrict__
 }
 
 // Accumulator a (one lane) sums the prepared points a, a + A, a + 2A, ...
-// (consecutive lanes read consecutive records).
+// (consecutive lanes read consecutive records), on the carry-free 28-bit
+// form like bucket accumulation.
 __global__ void __launch_bounds__(256) k_acc_stream(const uint32_t* __restrict__ xyu_pts,
                                                     uint32_t n, uint32_t A,
                                                     uint32_t* __restrict__ out) {
   const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= A) return;
-  const fe p2 = fe_const(kP2);
-  xytz acc = pt_identity();
-  if (a < n) {
-    xyu nxt = ld_xyu(xyu_pts + (size_t)a * XYU_WORDS);
-    for (uint32_t i = a; i < n; i += A) {
-      const xyu cur = nxt;
-      const uint32_t j = (i + A < n) ? i + A : i;
-      nxt = ld_xyu(xyu_pts + (size_t)j * XYU_WORDS);
-      acc = padd_mixed(acc, cur, p2);
-    }
-  }
-  st_xytz(out + (size_t)a * XYTZ_WORDS, acc);
+  xytz28 acc = pt28_identity();
+  // no prefetch of the next record: it would cost a wave per SIMD, and three
+  // resident waves cover the load latency
+  for (uint32_t i = a; i < n; i += A)
+    acc = padd28_mixed(acc, pt28_from(ld_xyu(xyu_pts + (size_t)i * XYU_WORDS)));
+  st_xytz(out + (size_t)a * XYTZ_WORDS, pt28_to_words(acc));
 }
 
 // Few accumulators: one wide unit per accumulator (block a) instead of one

@@ -224,7 +224,7 @@ bool make_plan(const size_t* ns, uint32_t J, int c_req, int encoding, Plan& pl,
   return true;
 }
 
-int enqueue_msm(const Plan& pl, void* ws, hipStream_t st) {
+int enqueue_msm(const Plan& pl, void* ws, hipStream_t st, hipEvent_t accum_after) {
   uint32_t* buckets = ws_at<uint32_t>(ws, pl.o_buckets);
   int rc;
   {
@@ -232,6 +232,7 @@ int enqueue_msm(const Plan& pl, void* ws, hipStream_t st) {
     rc = launch_sort(pl, buckets, ws, st);
   }
   if (rc != MSM_OK) return rc;
+  if (accum_after) HIPCHK(hipStreamWaitEvent(st, accum_after, 0));
   if ((rc = launch_accumulate(pl, buckets, ws, st)) != MSM_OK) return rc;
   if ((rc = launch_aggregate(pl, buckets, ws, st)) != MSM_OK) return rc;
   return launch_horner(pl, ws, st);

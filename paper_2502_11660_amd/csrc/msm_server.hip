@@ -11,6 +11,14 @@
 // request runs the full pipeline (sort, accumulation, aggregation, group
 // aggregation) on the stream with the fewest requests in flight, so requests
 // that arrive while others run overlap with them on the device.
+//
+// Overlap trades latency for throughput: a later request's accumulation,
+// which fills the device, delays an earlier request's latency-bound
+// aggregation chains (no stream priorities are used).  So when fewer than
+// OVERLAP_FROM requests are in flight, a new request's accumulation waits for
+// the previous request to finish (only its digit sort overlaps), which keeps
+// requests in arrival order at light load; with a backlog, requests overlap
+// fully, which raises the throughput.
 #include <algorithm>
 #include <deque>
 #include <map>
@@ -21,6 +29,9 @@
 using namespace msm;
 
 namespace {
+
+// in-flight requests from which a new request overlaps fully (see above)
+constexpr int OVERLAP_FROM = 3;
 
 struct Arena {
   size_t size = 0;
@@ -88,6 +99,8 @@ struct msm_server {
   std::vector<Request> running;
   std::deque<uint64_t> finished;
   std::vector<hipEvent_t> events;  // idle completion events
+  hipEvent_t gate = nullptr;  // recorded at the end of the last admitted request
+  bool gate_used = false;
   uint64_t next_ticket = 1;
 };
 
@@ -119,7 +132,11 @@ int admit(msm_server* s) {
     // the request's kernels wait for what the caller enqueued before submitting
     int rc = hipStreamWaitEvent(s->streams[k], r.ready, 0) == hipSuccess ? MSM_OK : MSM_EHIP;
     if (rc == MSM_OK) rc = take_event(s, r.done);
-    if (rc == MSM_OK) rc = enqueue_msm(r.plan, s->base + off, s->streams[k]);
+    const bool in_order = s->gate_used && (int)s->running.size() < OVERLAP_FROM;
+    if (rc == MSM_OK)
+      rc = enqueue_msm(r.plan, s->base + off, s->streams[k], in_order ? s->gate : nullptr);
+    if (rc == MSM_OK && hipEventRecord(s->gate, s->streams[k]) != hipSuccess) rc = MSM_EHIP;
+    if (rc == MSM_OK) s->gate_used = true;
     if (rc == MSM_OK && hipEventRecord(r.done, s->streams[k]) != hipSuccess) rc = MSM_EHIP;
     if (rc != MSM_OK) {
       s->arena.release(off, r.plan.bytes);
@@ -163,6 +180,7 @@ void destroy(msm_server* s) {
   for (Request& r : s->running) s->events.push_back(r.done);
   for (Request& r : s->queued) s->events.push_back(r.ready);
   for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
+  if (s->gate) (void)hipEventDestroy(s->gate);
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
   if (s->base) (void)hipFree(s->base);
   delete s;
@@ -171,6 +189,7 @@ void destroy(msm_server* s) {
 int create(size_t budget, int nstreams, int encoding, msm_server* s) {
   HIPCHK(hipGetDevice(&s->device));
   s->encoding = encoding;
+  HIPCHK(hipEventCreateWithFlags(&s->gate, hipEventDisableTiming));
   HIPCHK(hipMalloc((void**)&s->base, budget));
   s->arena.reset(budget);
   for (int i = 0; i < nstreams; ++i) {
