@@ -93,7 +93,7 @@ void prof_kernel_record(int tag, hipEvent_t a, hipEvent_t b);
 // SORT_PART_TARGET entries; pass 2 stages up to SORT_PART_CAP in LDS and
 // sorts larger partitions on many blocks, in items of SORT_BIG_ITEM entries.
 constexpr uint32_t SORT_PART_TARGET = 4096;
-constexpr uint32_t SORT_PART_CAP = 7168;
+constexpr uint32_t SORT_PART_CAP = 10240;
 constexpr uint32_t SORT_BIG_ITEM = 4096;
 
 // ---------------------------------------------------------------------------

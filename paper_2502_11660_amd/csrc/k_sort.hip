@@ -20,7 +20,8 @@
 //   pass 2  one block per partition (segment, high bits) counts the low
 //           <= 8 bits in LDS, writes the bucket offsets, and places the
 //           entries in bucket order.  Partitions up to PART_CAP entries are
-//           staged in LDS; larger ones (skewed inputs) are streamed twice.
+//           staged in LDS; larger ones (skewed inputs) are sorted by many
+//           blocks (k_big_*).
 // Segments of one job hold n entries each; jobs may differ in n, so a block
 // finds its job by binary search over the job table.
 #include <algorithm>
@@ -292,50 +293,33 @@ __device__ __forceinline__ uint32_t part_bucket0(const SortGeom& g, uint32_t p) 
   return (s << g.bb) + (hi << g.lo_bits);
 }
 
-// pass 2: one block per partition (segment s, high bits hi).  The partition
-// is ranked in LDS (a permutation into bucket order) and written out
-// linearly.  A partition of more than PART_CAP entries (skewed digits) is only
-// listed in big[] here; the k_big_* kernels sort it with many blocks.
-__global__ void __launch_bounds__(SORT_THREADS) k_part_sort(
-    SortGeom g, const uint32_t* __restrict__ scanned, const uint32_t* __restrict__ total_p,
-    size_t ncounts, const uint2* __restrict__ tmp, uint32_t* __restrict__ key,
-    uint32_t* __restrict__ idx, uint32_t* __restrict__ offsets, uint32_t* __restrict__ buckets,
-    uint32_t* __restrict__ big) {
-  __shared__ uint32_t ent_idx[PART_CAP];  // index words of the staged entries
-  __shared__ uint8_t ent_lo[PART_CAP];    // their low bucket bits
-  __shared__ uint16_t perm[PART_CAP];     // position in bucket order -> entry
-  __shared__ uint32_t hist[256], cur[256];
+// pass 2: one block per partition (segment s, high bits hi).  Each thread
+// keeps its share of the partition's entries in registers (ROWS rows of the
+// block); after the bucket histogram and its scan, every entry takes its place
+// in bucket order in LDS (index word and low bucket bits, 5 bytes an entry)
+// and the block writes the partition out linearly.
+template <uint32_t ROWS>
+__device__ __forceinline__ void part_sort_rows(const SortGeom& g, uint32_t p, uint32_t start,
+                                               uint32_t size, const uint2* __restrict__ tmp,
+                                               uint32_t* __restrict__ key,
+                                               uint32_t* __restrict__ idx,
+                                               uint32_t* __restrict__ offsets,
+                                               uint32_t* __restrict__ buckets, uint32_t* out_idx,
+                                               uint8_t* out_lo, uint32_t* hist, uint32_t* cur) {
   const uint32_t L = 1u << g.lo_bits;
-  const uint32_t p = blockIdx.x;
-  const uint32_t total = *total_p;
-  uint32_t start, size;
-  part_range(g, scanned, total, ncounts, p, start, size);
-  if (p == 0 && threadIdx.x == 0) offsets[g.S << g.bb] = total;
-  if (size > PART_CAP) {
-    if (threadIdx.x == 0) big[1 + atomicAdd(&big[0], 1u)] = p;
-    return;
-  }
   if (threadIdx.x < 256) hist[threadIdx.x] = 0;
   __syncthreads();
+  uint2 ev[ROWS];
   if (size > 0) {
     // all loads first (clamped, unconditional), so that they overlap
-    constexpr uint32_t PER = (PART_CAP + SORT_THREADS - 1) / SORT_THREADS;
-    uint2 ev[PER];
 #pragma unroll
-    for (uint32_t r = 0; r < PER; ++r) {
+    for (uint32_t r = 0; r < ROWS; ++r) {
       const uint32_t k = r * SORT_THREADS + threadIdx.x;
       ev[r] = tmp[start + (k < size ? k : size - 1)];
     }
 #pragma unroll
-    for (uint32_t r = 0; r < PER; ++r) {
-      const uint32_t k = r * SORT_THREADS + threadIdx.x;
-      if (k < size) {
-        const uint32_t lo = ev[r].y & (L - 1);
-        ent_idx[k] = ev[r].x;
-        ent_lo[k] = (uint8_t)lo;
-        atomicAdd(&hist[lo], 1u);
-      }
-    }
+    for (uint32_t r = 0; r < ROWS; ++r)
+      if (r * SORT_THREADS + threadIdx.x < size) atomicAdd(&hist[ev[r].y & (L - 1)], 1u);
   }
   __syncthreads();
   for (uint32_t lo = threadIdx.x; lo < L; lo += SORT_THREADS) cur[lo] = hist[lo];
@@ -349,14 +333,54 @@ __global__ void __launch_bounds__(SORT_THREADS) k_part_sort(
       st_xytz(buckets + (size_t)(bucket0 + lo) * XYTZ_WORDS, pt_identity());
   }
   __syncthreads();
-  for (uint32_t k = threadIdx.x; k < size; k += SORT_THREADS)
-    perm[atomicAdd(&cur[ent_lo[k]], 1u)] = (uint16_t)k;
+  if (size > 0) {
+#pragma unroll
+    for (uint32_t r = 0; r < ROWS; ++r) {
+      if (r * SORT_THREADS + threadIdx.x < size) {
+        const uint32_t lo = ev[r].y & (L - 1);
+        const uint32_t q = atomicAdd(&cur[lo], 1u);
+        out_idx[q] = ev[r].x;
+        out_lo[q] = (uint8_t)lo;
+      }
+    }
+  }
   __syncthreads();
   for (uint32_t q = threadIdx.x; q < size; q += SORT_THREADS) {
-    const uint32_t k = perm[q];
-    key[start + q] = bucket0 + ent_lo[k];
-    idx[start + q] = ent_idx[k];
+    key[start + q] = bucket0 + out_lo[q];
+    idx[start + q] = out_idx[q];
   }
+}
+
+// Partitions of up to SHORT_ROWS rows (evenly spread digits) take the short
+// form, larger ones up to PART_CAP entries the long one.  A partition of more
+// than PART_CAP entries (skewed digits) is only listed in big[] here; the
+// k_big_* kernels sort it with many blocks.
+constexpr uint32_t SHORT_ROWS = 20;
+
+__global__ void __launch_bounds__(SORT_THREADS) k_part_sort(
+    SortGeom g, const uint32_t* __restrict__ scanned, const uint32_t* __restrict__ total_p,
+    size_t ncounts, const uint2* __restrict__ tmp, uint32_t* __restrict__ key,
+    uint32_t* __restrict__ idx, uint32_t* __restrict__ offsets, uint32_t* __restrict__ buckets,
+    uint32_t* __restrict__ big) {
+  __shared__ uint32_t out_idx[PART_CAP];  // index words in bucket order
+  __shared__ uint8_t out_lo[PART_CAP];    // their low bucket bits
+  __shared__ uint32_t hist[256], cur[256];
+  constexpr uint32_t ROWS = (PART_CAP + SORT_THREADS - 1) / SORT_THREADS;
+  const uint32_t p = blockIdx.x;
+  const uint32_t total = *total_p;
+  uint32_t start, size;
+  part_range(g, scanned, total, ncounts, p, start, size);
+  if (p == 0 && threadIdx.x == 0) offsets[g.S << g.bb] = total;
+  if (size > PART_CAP) {
+    if (threadIdx.x == 0) big[1 + atomicAdd(&big[0], 1u)] = p;
+    return;
+  }
+  if (size <= SHORT_ROWS * SORT_THREADS)
+    part_sort_rows<SHORT_ROWS>(g, p, start, size, tmp, key, idx, offsets, buckets, out_idx, out_lo,
+                               hist, cur);
+  else
+    part_sort_rows<ROWS>(g, p, start, size, tmp, key, idx, offsets, buckets, out_idx, out_lo, hist,
+                         cur);
 }
 
 // Large partitions, sorted by many blocks.  big[0] = their count n, big[1..n]

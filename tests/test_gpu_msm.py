@@ -215,6 +215,20 @@ def test_msm_skewed_partition_larger_than_lds_stage(oracle_pool):
     assert got == msm.closed_form(sc, sel_k)
 
 
+def test_msm_partition_at_the_lds_stage_boundary(oracle_pool):
+    """Equal scalars put all n entries of a window into one bucket and one sort
+    partition: n = 10240 fills the pass-2 LDS stage exactly (the one-block
+    path), n = 10241 is one entry over it (the many-block path)."""
+    ks, pts = oracle_pool
+    s = 0x0123456789ABCDEF0123456789ABCDEF0123456789ABCDEF0123456789ABCDE % R_ORDER
+    for n in (10240, 10241):
+        sel_k = [ks[i % len(ks)] for i in range(n)]
+        xyu = _prepared([pts[i % len(pts)] for i in range(n)])
+        for c, enc in ((8, UNSIGNED), (9, SIGNED)):
+            got, flags = _run(xyu, [s] * n, c, enc)
+            assert flags == 0 and got == msm.closed_form([s] * n, sel_k), (n, c)
+
+
 @pytest.mark.parametrize("c", [10, 13])
 def test_msm_quarter_million_closed_form(c):
     """n = 2^18 GPU-generated points; c = 10 / 13 split digits into 6+4 / 6+7 bits."""
