@@ -266,7 +266,8 @@ int msm_run_noalloc(const uint32_t* xyu, const uint32_t* scalars, size_t n, int 
  * msm_default_window(n) choice), and the schedule (0 = the default for
  * each): chunk, the digit entries one lane sums in bucket accumulation
  * (default: enough entries that one resident round of lanes covers the
- * class; values below 4 are raised to 4); tree_quad, aggregation-tree levels
+ * class; every value is rounded up to a multiple of 4, at least 4);
+ * tree_quad, aggregation-tree levels
  * with fewer outputs than this run on the four-lane unit (default 65536);
  * tree_wide, levels with at most this many outputs run on the wide two-wave
  * unit (default 1024).  Jobs of a batch with the same width and schedule

@@ -183,6 +183,7 @@ bool make_plan(const size_t* ns, uint32_t J, int c_req, int encoding, Plan& pl,
   const size_t lanes = (size_t)device_cus() * 4 * 3 * 64;
   pl.K = sched.chunk ? (uint32_t)std::max(4, sched.chunk)
                      : (uint32_t)std::max<size_t>(16, (pl.NW + lanes - 1) / lanes);
+  pl.K = (pl.K + 3u) & ~3u;  // a multiple of 4: chunks start on 16-byte boundaries
   pl.chunks = (pl.NW + pl.K - 1) / pl.K;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -198,8 +199,8 @@ bool make_plan(const size_t* ns, uint32_t J, int c_req, int encoding, Plan& pl,
   pl.o_blocksums = take(4096 * 4);
   pl.o_digits = take(pl.NW * 4);
   pl.o_tmp = take(pl.NW * 8);
-  pl.o_key = take(pl.NW * 4);
-  pl.o_idx = take(pl.NW * 4);
+  pl.o_key = take(pl.NW * 4 + 32);  // + 16-byte groups read past the end
+  pl.o_idx = take(pl.NW * 4 + 32);
   pl.o_head = take(pl.chunks * rec);
   pl.o_tail = take(pl.chunks * rec);
   pl.o_longlist = take((pl.chunks + 1) * 4);
