@@ -743,7 +743,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X and has no "
+        print("bench.py measures one GPU: the library runs on a single MI355X and has no "
               "multi-GPU path (requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
