@@ -129,10 +129,20 @@ int admit(msm_server* s) {
     s->queued.pop_front();
     r.off = off;
     r.stream = k;
-    // the request's kernels wait for what the caller enqueued before submitting
-    int rc = hipStreamWaitEvent(s->streams[k], r.ready, 0) == hipSuccess ? MSM_OK : MSM_EHIP;
+    // the request's kernels wait for what the caller enqueued before
+    // submitting (no wait is enqueued when that work has already finished)
+    int rc = MSM_OK;
+    const hipError_t rq = hipEventQuery(r.ready);
+    if (rq == hipErrorNotReady)
+      rc = hipStreamWaitEvent(s->streams[k], r.ready, 0) == hipSuccess ? MSM_OK : MSM_EHIP;
+    else if (rq != hipSuccess)
+      rc = MSM_EHIP;
     if (rc == MSM_OK) rc = take_event(s, r.done);
-    const bool in_order = s->gate_used && (int)s->running.size() < OVERLAP_FROM;
+    // (nothing to wait for when nothing is in flight or the previous
+    // request has already finished)
+    const bool in_order = s->gate_used && !s->running.empty() &&
+                          (int)s->running.size() < OVERLAP_FROM &&
+                          hipEventQuery(s->gate) == hipErrorNotReady;
     if (rc == MSM_OK)
       rc = enqueue_msm(r.plan, s->base + off, s->streams[k], in_order ? s->gate : nullptr);
     if (rc == MSM_OK && hipEventRecord(s->gate, s->streams[k]) != hipSuccess) rc = MSM_EHIP;
