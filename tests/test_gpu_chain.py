@@ -51,7 +51,8 @@ def test_padd_chain_rejects_bad_unit(oracle_pool):
         api.padd_chain(_xytz_records(pts[:2], 1), 2, 7)
 
 
-@pytest.mark.parametrize("n,A", [(1000, 37), (1000, 10), (64, 100), (2048, 1024), (2048, 1500)])
+@pytest.mark.parametrize("n,A", [(1000, 37), (1000, 10), (64, 100), (2048, 1024), (2048, 1500),
+                                 (1100, 2000)])
 def test_accumulate_stream(oracle_pool, n, A):
     ks, pts = oracle_pool
     xy = H.soa(pts[:n], 2)
