@@ -932,6 +932,10 @@ def main():
     if cpu is not None and "baseline" in cpu:
         cpu_baseline = dict(cpu["baseline"])
         cpu_baseline["msm_ms_extrapolated"] = cpu_baseline["msm_n2p20_s_extrapolated"] * 1e3
+        ps = cpu["pair_sample_oracle"]
+        # the workload-2 sample's additions on one core (the oracle's affine
+        # additions computing the expected sums of the 4096 sampled pairs)
+        cpu_baseline["pair_sample_adds_per_s_one_core"] = ps["adds"] / ps["adds_s_one_core"]
 
     out = {
         "metric": "PADDs/s and MSM latency (ms) at n=2^20; batched/served MSMs/s + p99 vs plain",
