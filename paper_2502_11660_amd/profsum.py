@@ -18,6 +18,13 @@
       integer parts), SQ_ACTIVE_INST_VALU, GRBM_GUI_ACTIVE summed over the
       XCDs and the dispatch time, hence the mean engine clock and the share
       of SIMD cycles that issue VALU work (4 cycles per wave64 instruction).
+  python -m paper_2502_11660_amd.profsum clusters KERNEL_TRACE_CSV [--gap-ms G]
+      the kernel dispatches of a trace grouped into clusters separated by idle
+      gaps longer than G ms; per cluster the dispatch count, the wall time
+      from its first start to its last end, the union of the intervals in
+      which at least one kernel runs (busy), the sum of the kernel durations
+      and their ratio to busy (above 1 where kernels of several streams
+      overlap).
 """
 
 import argparse
@@ -132,6 +139,38 @@ def valu(args, xcds=8, simds=1024):
     return out
 
 
+def clusters(path, gap_ms):
+    rows = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short_name(r["Kernel_Name"]))
+            for r in csv.DictReader(open(path))]
+    rows.sort()
+    groups, cur, end = [], [], None
+    for s_ns, e_ns, name in rows:
+        if cur and s_ns - end > gap_ms * 1e6:
+            groups.append(cur)
+            cur = []
+        cur.append((s_ns, e_ns, name))
+        end = e_ns if end is None or not cur[:-1] else max(end, e_ns)
+    if cur:
+        groups.append(cur)
+    out = []
+    for g in groups:
+        busy, run_s, run_e = 0, None, None
+        for s_ns, e_ns, _ in g:
+            if run_e is None or s_ns > run_e:
+                if run_e is not None:
+                    busy += run_e - run_s
+                run_s, run_e = s_ns, e_ns
+            else:
+                run_e = max(run_e, e_ns)
+        busy += run_e - run_s
+        total = sum(e - s for s, e, _ in g)
+        wall = max(e for _, e, _ in g) - g[0][0]
+        out.append({"dispatches": len(g), "wall_ms": wall / 1e6, "busy_ms": busy / 1e6,
+                    "busy_share": busy / wall if wall else 1.0,
+                    "kernel_sum_ms": total / 1e6, "overlap": total / busy if busy else 1.0})
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="profsum")
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -150,9 +189,14 @@ def main(argv=None):
     v = sub.add_parser("valu")
     v.add_argument("csv")
     v.add_argument("--kernel", action="append", required=True)
+    c = sub.add_parser("clusters")
+    c.add_argument("csv")
+    c.add_argument("--gap-ms", type=float, default=5.0)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(stats_table(a.csv))
+    elif a.cmd == "clusters":
+        print(json.dumps(clusters(a.csv, a.gap_ms), indent=1))
     elif a.cmd == "valu":
         print(json.dumps(valu(a), indent=1))
     else:
