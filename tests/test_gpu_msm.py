@@ -217,11 +217,13 @@ def test_msm_skewed_partition_larger_than_lds_stage(oracle_pool):
 
 def test_msm_partition_at_the_lds_stage_boundary(oracle_pool):
     """Equal scalars put all n entries of a window into one bucket and one sort
-    partition: n = 10240 fills the pass-2 LDS stage exactly (the one-block
-    path), n = 10241 is one entry over it (the many-block path)."""
+    partition: n = 5120 is the largest partition of the short register form
+    of pass 2 and 5121 the smallest of the long one; n = 10240 fills the
+    pass-2 LDS stage exactly (the one-block path), n = 10241 is one entry over
+    it (the many-block path)."""
     ks, pts = oracle_pool
     s = 0x0123456789ABCDEF0123456789ABCDEF0123456789ABCDEF0123456789ABCDE % R_ORDER
-    for n in (10240, 10241):
+    for n in (5120, 5121, 10240, 10241):
         sel_k = [ks[i % len(ks)] for i in range(n)]
         xyu = _prepared([pts[i % len(pts)] for i in range(n)])
         for c, enc in ((8, UNSIGNED), (9, SIGNED)):
