@@ -432,3 +432,13 @@ def test_scalar_generator_range_and_determinism():
     assert max(vals) > R_ORDER // 2        # uses the full range
     e = inputs.base_field_elements(3, 200)
     assert all(0 < inputs.words_to_int(r) < P for r in e)
+
+
+def test_gen_points_equals_scalar_multiples():
+    """The generator of the workload points, with and without its process
+    pool, gives k G as double-and-add computes it."""
+    rng = random.Random(77)
+    ks = [0, 1, 2, R_ORDER - 1] + [rng.randrange(R_ORDER) for _ in range(68)]
+    want = [curve.smul(k, curve.G) for k in ks]
+    assert points.gen_points(ks) == want
+    assert points.gen_points(ks, processes=2) == want
