@@ -108,23 +108,27 @@ __device__ __forceinline__ fe f28_to_words(const fe28& x) {
 // compiler sums each column from zero and adds the carry afterwards, one
 // extra 64-bit add per column).  The carry-out of v_mad_u64_u32 goes to a
 // scratch SGPR pair (cc) that nothing reads.  CB is the second factor's
-// constraint ("v" for a VGPR, "s" for an SGPR such as a limb of p).
+// constraint ("v" for a VGPR, "s" for an SGPR such as a limb of p).  cc is
+// early-clobber ("=&s"): the block's first multiply-add writes it before the
+// later ones read their factors, so it must not share a register with an
+// SGPR factor (without the "&" the compiler may assign both to one register,
+// and a limb of p would be overwritten by a carry-out mid-block).
 #define MSM_MAD28_1(CB, acc, cc, a0, b0) \
   asm("v_mad_u64_u32 %0, %1, %2, %3, %0" \
-      : "+v"(acc), "=s"(cc) \
+      : "+v"(acc), "=&s"(cc) \
       : "v"(a0), CB(b0))
 
 #define MSM_MAD28_2(CB, acc, cc, a0, b0, a1, b1) \
   asm("v_mad_u64_u32 %0, %1, %2, %3, %0\n\t" \
       "v_mad_u64_u32 %0, %1, %4, %5, %0" \
-      : "+v"(acc), "=s"(cc) \
+      : "+v"(acc), "=&s"(cc) \
       : "v"(a0), CB(b0), "v"(a1), CB(b1))
 
 #define MSM_MAD28_3(CB, acc, cc, a0, b0, a1, b1, a2, b2) \
   asm("v_mad_u64_u32 %0, %1, %2, %3, %0\n\t" \
       "v_mad_u64_u32 %0, %1, %4, %5, %0\n\t" \
       "v_mad_u64_u32 %0, %1, %6, %7, %0" \
-      : "+v"(acc), "=s"(cc) \
+      : "+v"(acc), "=&s"(cc) \
       : "v"(a0), CB(b0), "v"(a1), CB(b1), "v"(a2), CB(b2))
 
 #define MSM_MAD28_4(CB, acc, cc, a0, b0, a1, b1, a2, b2, a3, b3) \
@@ -132,7 +136,7 @@ __device__ __forceinline__ fe f28_to_words(const fe28& x) {
       "v_mad_u64_u32 %0, %1, %4, %5, %0\n\t" \
       "v_mad_u64_u32 %0, %1, %6, %7, %0\n\t" \
       "v_mad_u64_u32 %0, %1, %8, %9, %0" \
-      : "+v"(acc), "=s"(cc) \
+      : "+v"(acc), "=&s"(cc) \
       : "v"(a0), CB(b0), "v"(a1), CB(b1), "v"(a2), CB(b2), "v"(a3), CB(b3))
 
 #define MSM_MAD28_5(CB, acc, cc, a0, b0, a1, b1, a2, b2, a3, b3, a4, b4) \
@@ -141,7 +145,7 @@ __device__ __forceinline__ fe f28_to_words(const fe28& x) {
       "v_mad_u64_u32 %0, %1, %6, %7, %0\n\t" \
       "v_mad_u64_u32 %0, %1, %8, %9, %0\n\t" \
       "v_mad_u64_u32 %0, %1, %10, %11, %0" \
-      : "+v"(acc), "=s"(cc) \
+      : "+v"(acc), "=&s"(cc) \
       : "v"(a0), CB(b0), "v"(a1), CB(b1), "v"(a2), CB(b2), "v"(a3), CB(b3), "v"(a4), CB(b4))
 
 #define MSM_MAD28_6(CB, acc, cc, a0, b0, a1, b1, a2, b2, a3, b3, a4, b4, a5, b5) \
@@ -151,7 +155,7 @@ __device__ __forceinline__ fe f28_to_words(const fe28& x) {
       "v_mad_u64_u32 %0, %1, %8, %9, %0\n\t" \
       "v_mad_u64_u32 %0, %1, %10, %11, %0\n\t" \
       "v_mad_u64_u32 %0, %1, %12, %13, %0" \
-      : "+v"(acc), "=s"(cc) \
+      : "+v"(acc), "=&s"(cc) \
       : "v"(a0), CB(b0), "v"(a1), CB(b1), "v"(a2), CB(b2), "v"(a3), CB(b3), "v"(a4), CB(b4), "v"(a5), CB(b5))
 
 #define MSM_MAD28_7(CB, acc, cc, a0, b0, a1, b1, a2, b2, a3, b3, a4, b4, a5, b5, a6, b6) \
@@ -162,7 +166,7 @@ __device__ __forceinline__ fe f28_to_words(const fe28& x) {
       "v_mad_u64_u32 %0, %1, %10, %11, %0\n\t" \
       "v_mad_u64_u32 %0, %1, %12, %13, %0\n\t" \
       "v_mad_u64_u32 %0, %1, %14, %15, %0" \
-      : "+v"(acc), "=s"(cc) \
+      : "+v"(acc), "=&s"(cc) \
       : "v"(a0), CB(b0), "v"(a1), CB(b1), "v"(a2), CB(b2), "v"(a3), CB(b3), "v"(a4), CB(b4), "v"(a5), CB(b5), "v"(a6), CB(b6))
 
 #define MSM_MAD28_8(CB, acc, cc, a0, b0, a1, b1, a2, b2, a3, b3, a4, b4, a5, b5, a6, b6, a7, b7) \
@@ -174,7 +178,7 @@ __device__ __forceinline__ fe f28_to_words(const fe28& x) {
       "v_mad_u64_u32 %0, %1, %12, %13, %0\n\t" \
       "v_mad_u64_u32 %0, %1, %14, %15, %0\n\t" \
       "v_mad_u64_u32 %0, %1, %16, %17, %0" \
-      : "+v"(acc), "=s"(cc) \
+      : "+v"(acc), "=&s"(cc) \
       : "v"(a0), CB(b0), "v"(a1), CB(b1), "v"(a2), CB(b2), "v"(a3), CB(b3), "v"(a4), CB(b4), "v"(a5), CB(b5), "v"(a6), CB(b6), "v"(a7), CB(b7))
 
 template <int N, bool SGPR_Y>
