@@ -141,7 +141,8 @@ struct Plan {
   uint64_t tree_quad = 65536;  // tree levels with fewer outputs run on quads
   uint64_t tree_wide = 1024;   // levels with at most this many outputs on wide units
   uint32_t lo_bits = 0, hi_bits = 0;  // split of the bb bucket bits in the sort
-  size_t ncounts = 0, nb = 0;         // sort count matrix size, its scan blocks
+  size_t ncounts = 0, nb = 0, nb2 = 0;  // sort count matrix size, its scan blocks (two levels
+                                        // and, for nb > 4096, a third)
   JobDesc one{};  // the job when J = 1; otherwise one.xyu is the base of segment offsets
   // byte offsets into the workspace
   size_t o_flags = 0, o_total = 0, o_offsets = 0, o_counts = 0, o_blocksums = 0, o_digits = 0,

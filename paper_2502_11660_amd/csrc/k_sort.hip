@@ -644,16 +644,27 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_add(uint32_t* __restrict_
 // distributed digits of the largest job holds about max_n / 2^hi <=
 // SORT_PART_TARGET entries, at most 8 low bits (pass-2 histogram) and at most 12
 // high bits (pass-1 histogram).  Also the tile count and count-matrix size.
+// The count matrix (tiles x 2^hi) grows with the square of the input while
+// the partitions are small; for large inputs the split takes fewer high bits
+// (down to bb - 8), so that the matrix stays within one two-level scan
+// (SCAN_ITEMS^2 counts) and the partitions, now larger than the LDS stage,
+// are sorted by the many-block path.  Where even bb - 8 high bits leave more
+// counts (widths of 18 and up at large n), the scan takes a third level
+// (nb2 blocks over the nb block sums).
 void sort_geometry(Plan& pl) {
   const uint32_t bb = (uint32_t)pl.bb;
   uint32_t want = 0;
   while (want < 12 && (pl.max_n >> want) > SORT_PART_TARGET) ++want;
-  uint32_t hi = std::max<uint32_t>(want, bb > 8 ? bb - 8 : 0);
+  const uint32_t hi_min = bb > 8 ? bb - 8 : 0;
+  uint32_t hi = std::max<uint32_t>(want, hi_min);
   hi = std::min<uint32_t>(hi, std::min<uint32_t>(bb, 12));
+  const size_t two_level = (size_t)SCAN_ITEMS * SCAN_ITEMS;
+  while (hi > hi_min && (pl.tiles << hi) > two_level) --hi;
   pl.hi_bits = hi;
   pl.lo_bits = bb - hi;
   pl.ncounts = pl.tiles << hi;
   pl.nb = (pl.ncounts + SCAN_ITEMS - 1) / SCAN_ITEMS;
+  pl.nb2 = pl.nb > (size_t)SCAN_ITEMS ? (pl.nb + SCAN_ITEMS - 1) / SCAN_ITEMS : 0;
 }
 
 int launch_sort(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t st) {
@@ -666,7 +677,7 @@ int launch_sort(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t st) {
   uint2* tmp = ws_at<uint2>(ws, pl.o_tmp);
   uint32_t* key = ws_at<uint32_t>(ws, pl.o_key);
   uint32_t* idx = ws_at<uint32_t>(ws, pl.o_idx);
-  if (pl.lo_bits > 8 || pl.hi_bits > 12 || pl.nb > (size_t)SCAN_ITEMS) return MSM_EINVAL;
+  if (pl.lo_bits > 8 || pl.hi_bits > 12 || pl.nb2 > (size_t)SCAN_ITEMS) return MSM_EINVAL;
 
   SortGeom g;
   g.jv = job_view(pl, ws);
@@ -684,7 +695,16 @@ int launch_sort(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t st) {
                                                         pl.encoding, digits, flags);
   k_part_count<<<(unsigned)pl.tiles, SORT_THREADS, 0, st>>>(g, off, digits, counts);
   k_scan_block<<<(unsigned)pl.nb, SCAN_THREADS, 0, st>>>(counts, pl.ncounts, blocksums);
-  k_scan_top<<<1, SCAN_THREADS, 0, st>>>(blocksums, (uint32_t)pl.nb, total);
+  if (pl.nb2 == 0) {
+    k_scan_top<<<1, SCAN_THREADS, 0, st>>>(blocksums, (uint32_t)pl.nb, total);
+  } else {
+    // three levels: the nb block sums are scanned in blocks, and their nb2
+    // sums by one block (the second-level sums follow the first's)
+    uint32_t* sums2 = blocksums + pl.nb;
+    k_scan_block<<<(unsigned)pl.nb2, SCAN_THREADS, 0, st>>>(blocksums, pl.nb, sums2);
+    k_scan_top<<<1, SCAN_THREADS, 0, st>>>(sums2, (uint32_t)pl.nb2, total);
+    k_scan_add<<<(unsigned)pl.nb2, SCAN_THREADS, 0, st>>>(blocksums, pl.nb, sums2);
+  }
   k_scan_add<<<(unsigned)pl.nb, SCAN_THREADS, 0, st>>>(counts, pl.ncounts, blocksums);
   const size_t scatter_lds = TILE * sizeof(uint2) + 2 * ((size_t)4 << pl.hi_bits);
   uint32_t* big = ws_at<uint32_t>(ws, pl.o_big);

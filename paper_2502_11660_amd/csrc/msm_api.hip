@@ -171,7 +171,7 @@ bool make_plan(const size_t* ns, uint32_t J, int c_req, int encoding, Plan& pl,
       pl.tiles >= ((size_t)1 << 31))
     return false;
   sort_geometry(pl);
-  if (pl.lo_bits > 8 || pl.nb > 4096) return false;
+  if (pl.lo_bits > 8 || pl.nb2 > 4096) return false;
   if (J == 1) {
     pl.one.n = (uint32_t)(mult * ns[0]);
     pl.one.tps = (uint32_t)((mult * ns[0] + SORT_TILE - 1) / SORT_TILE);
@@ -196,7 +196,7 @@ bool make_plan(const size_t* ns, uint32_t J, int c_req, int encoding, Plan& pl,
   pl.o_total = take(4);
   pl.o_offsets = take((pl.M + 1) * 4);
   pl.o_counts = take(pl.ncounts * 4);
-  pl.o_blocksums = take(4096 * 4);
+  pl.o_blocksums = take(std::max<size_t>(pl.nb + pl.nb2, 4096) * 4);
   pl.o_digits = take(pl.NW * 4);
   pl.o_tmp = take(pl.NW * 8);
   pl.o_key = take(pl.NW * 4 + 32);  // + 16-byte groups read past the end

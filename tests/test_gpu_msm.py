@@ -195,6 +195,44 @@ def test_msm_full_size_closed_form(c):
         assert rows[i] == points.fixed_base_mul(ks[i])
 
 
+@pytest.mark.parametrize("n,c,enc", [
+    ((1 << 23), 20, SIGNED),
+    ((1 << 26) - 1, 16, api.MSM_DIGITS_GLV),
+])
+def test_msm_large_jobs(n, c, enc):
+    """Jobs beyond the sizes whose sort partitions fit the LDS stage.
+    n = 2^23 with signed digits at c = 20: the count matrix (13 windows x 1024
+    tiles x 2^11 partitions) exceeds one two-level scan, so the scan takes a
+    third level.  n = 2^26 - 1, the largest job the interface takes, with
+    the endomorphism split at c' = 16: 2^30 - 16 digit slots (entry
+    positions, keys and indices are 32-bit words), a 2^7 x 2^8 split of the
+    bucket bits that keeps the count matrix within two scan levels, every
+    one of the 1024 sort partitions on the many-block path, and 5464-entry
+    accumulation chunks (device memory: about 50 GB).  k_i and s_i are drawn
+    uniformly below 2^252 with numpy (no rejection step, which would take a
+    minute at this size); the result is checked against the closed form,
+    summed exactly with float64 digit products (oracle.msm.dot_mod_r)."""
+    rng = np.random.default_rng(inputs.config_seed(3) + n % 1000 + c)
+    kw = rng.integers(0, 1 << 32, size=(n, 8), dtype=np.uint32)
+    kw[:, 7] &= 0x0FFFFFFF
+    kw[:, 0] |= 1
+    sw = rng.integers(0, 1 << 32, size=(n, 8), dtype=np.uint32)
+    sw[:, 7] &= 0x0FFFFFFF
+    k_dev = _dev(kw)
+    xy, inf = api.gen_points(k_dev, n)
+    del k_dev
+    xyu, status = api.points_prepare(xy, n, inf=inf, endo=enc == api.MSM_DIGITS_GLV)
+    del xy, inf
+    s_dev = _dev(sw)
+    res = api.msm_run(xyu, s_dev, n, c, enc)
+    got, flags = api.decode_result(api.to_host(res))
+    ok_status = int(api.to_host(status)[0]) == 0
+    del xyu, s_dev
+    torch.cuda.empty_cache()
+    assert flags == 0 and ok_status
+    assert got == msm.closed_form_words(sw, kw)
+
+
 def test_msm_skewed_partition_larger_than_lds_stage(oracle_pool):
     """All scalars equal at n = 20000: one bucket per window holds every entry,
     so the sort's partition exceeds its LDS stage and the accumulation's
