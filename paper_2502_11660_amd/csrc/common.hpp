@@ -110,8 +110,8 @@ struct JobDesc {
   uint32_t* result;         // MSM_RESULT_WORDS words
   uint32_t n;               // points of the job
   uint32_t pt_off;          // points of the jobs before it
-  uint32_t tile_off;        // tiles per window of the jobs before it
-  uint32_t tps;             // sort tiles per window, ceil(n / SORT_TILE)
+  uint32_t tile_off;        // tile groups per window of the jobs before it
+  uint32_t tps;             // sort tile groups per window, ceil(n / tile_digits)
 };
 
 // Kernel-argument view of a batch's jobs: a device table, or (J = 1) the one
@@ -141,8 +141,9 @@ struct Plan {
   uint64_t tree_quad = 65536;  // tree levels with fewer outputs run on quads
   uint64_t tree_wide = 1024;   // levels with at most this many outputs on wide units
   uint32_t lo_bits = 0, hi_bits = 0;  // split of the bb bucket bits in the sort
-  size_t ncounts = 0, nb = 0, nb2 = 0;  // sort count matrix size, its scan blocks (two levels
-                                        // and, for nb > 4096, a third)
+  uint32_t tpb = 1;                   // pass-1 tiles per block (one histogram per group)
+  uint32_t tile_digits = SORT_TILE;   // digits per group, SORT_TILE tpb
+  size_t ncounts = 0, nb = 0;         // sort count matrix size, its scan blocks
   JobDesc one{};  // the job when J = 1; otherwise one.xyu is the base of segment offsets
   // byte offsets into the workspace
   size_t o_flags = 0, o_total = 0, o_offsets = 0, o_counts = 0, o_blocksums = 0, o_digits = 0,
@@ -192,7 +193,9 @@ inline JobView job_view(const Plan& pl, void* ws) {
 // ---------------------------------------------------------------------------
 // k_sort.hip: digits -> CSR offsets, sorted (key, idx | sign << 31); empty
 // buckets set to the identity
-void sort_geometry(Plan& pl);  // fills lo_bits, hi_bits, tiles, ncounts, nb
+// fills lo_bits, hi_bits, tpb, tile_digits, tiles (groups over all segments),
+// ncounts, nb for jobs of mult * ns[j] points
+void sort_geometry(Plan& pl, const size_t* ns, uint32_t J, size_t mult);
 int launch_sort(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t st);
 // k_accum.hip: bucket accumulation and split-bucket merge
 int launch_accumulate(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t st);

@@ -41,6 +41,7 @@ constexpr unsigned BIG_GRID = 512;    // blocks of the large-partition kernels
 struct SortGeom {
   JobView jv;
   uint32_t W, S, bb, lo_bits, hi_bits;
+  uint32_t tpb;  // pass-1 tiles per block: a block's group of tpb tiles shares one histogram
 };
 
 // largest j with key(j) <= x, for a key non-decreasing in j (J >= 1)
@@ -57,7 +58,8 @@ __device__ __forceinline__ uint32_t find_job(uint32_t J, uint32_t x, F key) {
   return lo;
 }
 
-// the segment, tile and job of pass-1 block b
+// the segment, tile group and job of pass-1 block b (tile = the group's
+// index in its segment; a group is tpb consecutive tiles of TILE digits)
 struct TileRef {
   JobDesc d;
   uint32_t j, w, tile;
@@ -73,7 +75,7 @@ __device__ __forceinline__ TileRef tile_ref(const SortGeom& g, uint32_t b) {
   return r;
 }
 
-// count-matrix index of (segment of job d window w, high bits hi, tile)
+// count-matrix index of (segment of job d window w, high bits hi, tile group)
 __device__ __forceinline__ size_t count_index(const SortGeom& g, const JobDesc& d, uint32_t w,
                                               uint32_t hi, uint32_t tile) {
   const size_t seg_tile0 = (size_t)g.W * d.tile_off + (size_t)w * d.tps;
@@ -140,7 +142,8 @@ __device__ __forceinline__ uint32_t bucket_of(uint32_t q, uint32_t off) {
   return (q & 0x7fffffffu) - off;
 }
 
-// pass 1a: per-tile histogram of the high bits
+// pass 1a: per-group histogram of the high bits (the group's tiles one
+// after another into one LDS histogram)
 __global__ void __launch_bounds__(SORT_THREADS) k_part_count(SortGeom g, uint32_t off,
                                                              const uint32_t* __restrict__ digits,
                                                              uint32_t* __restrict__ counts) {
@@ -149,18 +152,21 @@ __global__ void __launch_bounds__(SORT_THREADS) k_part_count(SortGeom g, uint32_
   const uint32_t H = 1u << g.hi_bits;
   for (uint32_t b = threadIdx.x; b < H; b += SORT_THREADS) hist[b] = 0;
   __syncthreads();
-  const uint32_t e0 = t.tile * TILE, e1 = min(e0 + TILE, t.d.n);
+  const uint32_t g0 = t.tile * TILE * g.tpb, g1 = min(g0 + TILE * g.tpb, t.d.n);
   const uint32_t* dg = digits + (size_t)g.W * t.d.pt_off + (size_t)t.w * t.d.n;
-  uint32_t dq[PER_THREAD];
+  for (uint32_t e0 = g0; e0 < g1; e0 += TILE) {
+    const uint32_t e1 = min(e0 + TILE, g1);
+    uint32_t dq[PER_THREAD];
 #pragma unroll
-  for (uint32_t r = 0; r < PER_THREAD; ++r) {  // loads first, clamped (e1 > e0)
-    const uint32_t e = e0 + r * SORT_THREADS + threadIdx.x;
-    dq[r] = dg[e < e1 ? e : e1 - 1];
-  }
+    for (uint32_t r = 0; r < PER_THREAD; ++r) {  // loads first, clamped (e1 > e0)
+      const uint32_t e = e0 + r * SORT_THREADS + threadIdx.x;
+      dq[r] = dg[e < e1 ? e : e1 - 1];
+    }
 #pragma unroll
-  for (uint32_t r = 0; r < PER_THREAD; ++r) {
-    const uint32_t q = e0 + r * SORT_THREADS + threadIdx.x < e1 ? dq[r] : 0u;
-    if (q) atomicAdd(&hist[bucket_of(q, off) >> g.lo_bits], 1u);
+    for (uint32_t r = 0; r < PER_THREAD; ++r) {
+      const uint32_t q = e0 + r * SORT_THREADS + threadIdx.x < e1 ? dq[r] : 0u;
+      if (q) atomicAdd(&hist[bucket_of(q, off) >> g.lo_bits], 1u);
+    }
   }
   __syncthreads();
   for (uint32_t b = threadIdx.x; b < H; b += SORT_THREADS)
@@ -208,9 +214,11 @@ __device__ uint32_t lds_exclusive_scan(uint32_t* v, uint32_t n) {
   return total;
 }
 
-// pass 1b: scatter into (partition, tile) ranges; tmp entry = {idx | sign, key}.
-// The tile is first ordered by partition in LDS, so that consecutive threads
-// write consecutive entries of each partition's range.
+// pass 1b: scatter into (partition, tile group) ranges; tmp entry =
+// {idx | sign, key}.  Each tile of the group is first ordered by partition in
+// LDS, so that consecutive threads write consecutive entries of each
+// partition's range; a partition's cursor (gstart) then moves past the
+// tile's entries for the next tile of the group.
 __global__ void __launch_bounds__(SORT_THREADS) k_part_scatter(SortGeom g, uint32_t off,
                                                                const uint32_t* __restrict__ digits,
                                                                const uint32_t* __restrict__ scanned,
@@ -236,41 +244,51 @@ __global__ void __launch_bounds__(SORT_THREADS) k_part_scatter(SortGeom g, uint3
     lstart[b] = 0;
   }
   __syncthreads();
-  const uint32_t e0 = t.tile * TILE, e1 = min(e0 + TILE, t.d.n);
+  const uint32_t g0 = t.tile * TILE * g.tpb, g1 = min(g0 + TILE * g.tpb, t.d.n);
   const uint32_t* dg = digits + (size_t)g.W * t.d.pt_off + (size_t)t.w * t.d.n;
   const uint32_t keybase = (t.j * g.W + t.w) << g.bb;
-  uint32_t part[PER_THREAD], rank[PER_THREAD], dq[PER_THREAD];
-  uint2 ent[PER_THREAD];
-  // all loads first (clamped, unconditional), so that they overlap
+  for (uint32_t e0 = g0; e0 < g1; e0 += TILE) {
+    const uint32_t e1 = min(e0 + TILE, g1);
+    uint32_t part[PER_THREAD], rank[PER_THREAD], dq[PER_THREAD];
+    uint2 ent[PER_THREAD];
+    // all loads first (clamped, unconditional), so that they overlap
 #pragma unroll
-  for (uint32_t r = 0; r < PER_THREAD; ++r) {
-    const uint32_t e = e0 + r * SORT_THREADS + threadIdx.x;
-    dq[r] = dg[e < e1 ? e : e1 - 1];
-  }
-#pragma unroll
-  for (uint32_t r = 0; r < PER_THREAD; ++r) {
-    const uint32_t e = e0 + r * SORT_THREADS + threadIdx.x;
-    const uint32_t q = e < e1 ? dq[r] : 0u;
-    part[r] = H;  // no entry
-    rank[r] = 0;
-    ent[r] = make_uint2(0u, 0u);
-    if (q) {
-      const uint32_t m = bucket_of(q, off);
-      part[r] = m >> g.lo_bits;
-      rank[r] = atomicAdd(&lstart[part[r]], 1u);
-      ent[r] = make_uint2(e | (q & 0x80000000u), keybase + m);
+    for (uint32_t r = 0; r < PER_THREAD; ++r) {
+      const uint32_t e = e0 + r * SORT_THREADS + threadIdx.x;
+      dq[r] = dg[e < e1 ? e : e1 - 1];
     }
-  }
-  __syncthreads();
-  const uint32_t count = lds_exclusive_scan(lstart, H);
 #pragma unroll
-  for (uint32_t r = 0; r < PER_THREAD; ++r)
-    if (part[r] < H) stage[lstart[part[r]] + rank[r]] = ent[r];
-  __syncthreads();
-  for (uint32_t k = threadIdx.x; k < count; k += SORT_THREADS) {
-    const uint2 en = stage[k];
-    const uint32_t pr = (en.y - keybase) >> g.lo_bits;
-    tmp[gstart[pr] + (k - lstart[pr])] = en;
+    for (uint32_t r = 0; r < PER_THREAD; ++r) {
+      const uint32_t e = e0 + r * SORT_THREADS + threadIdx.x;
+      const uint32_t q = e < e1 ? dq[r] : 0u;
+      part[r] = H;  // no entry
+      rank[r] = 0;
+      ent[r] = make_uint2(0u, 0u);
+      if (q) {
+        const uint32_t m = bucket_of(q, off);
+        part[r] = m >> g.lo_bits;
+        rank[r] = atomicAdd(&lstart[part[r]], 1u);
+        ent[r] = make_uint2(e | (q & 0x80000000u), keybase + m);
+      }
+    }
+    __syncthreads();
+    const uint32_t count = lds_exclusive_scan(lstart, H);
+#pragma unroll
+    for (uint32_t r = 0; r < PER_THREAD; ++r)
+      if (part[r] < H) stage[lstart[part[r]] + rank[r]] = ent[r];
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < count; k += SORT_THREADS) {
+      const uint2 en = stage[k];
+      const uint32_t pr = (en.y - keybase) >> g.lo_bits;
+      tmp[gstart[pr] + (k - lstart[pr])] = en;
+    }
+    if (g.tpb == 1) break;  // (a single tile needs no cursor update)
+    __syncthreads();  // the stage and the local starts are read
+    for (uint32_t b = threadIdx.x; b < H; b += SORT_THREADS)
+      gstart[b] += (b + 1 < H ? lstart[b + 1] : count) - lstart[b];
+    __syncthreads();  // every local start is read before the reset
+    for (uint32_t b = threadIdx.x; b < H; b += SORT_THREADS) lstart[b] = 0;
+    __syncthreads();
   }
 }
 
@@ -643,28 +661,41 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_add(uint32_t* __restrict_
 // Split of the bb bucket bits: enough high bits that a partition of uniformly
 // distributed digits of the largest job holds about max_n / 2^hi <=
 // SORT_PART_TARGET entries, at most 8 low bits (pass-2 histogram) and at most 12
-// high bits (pass-1 histogram).  Also the tile count and count-matrix size.
-// The count matrix (tiles x 2^hi) grows with the square of the input while
-// the partitions are small; for large inputs the split takes fewer high bits
-// (down to bb - 8), so that the matrix stays within one two-level scan
-// (SCAN_ITEMS^2 counts) and the partitions, now larger than the LDS stage,
-// are sorted by the many-block path.  Where even bb - 8 high bits leave more
-// counts (widths of 18 and up at large n), the scan takes a third level
-// (nb2 blocks over the nb block sums).
-void sort_geometry(Plan& pl) {
+// high bits (pass-1 histogram).  Also the tile grouping and the count-matrix
+// size.  A pass-1 block takes a group of tpb tiles with one histogram: tpb =
+// 2^hi / 512 keeps about 16 entries per (group, partition) for uniform digits,
+// so that the scatter writes runs of 128 bytes and the count matrix (groups
+// x 2^hi, which with single tiles grows with the square of the input) stays
+// small.  If the matrix still exceeds the two-level scan (SCAN_ITEMS^2
+// counts), groups grow to 64 tiles, then the split takes fewer high bits
+// (down to bb - 8), whose partitions, larger than the LDS stage, go to the
+// many-block path.  Every single job the interface takes then fits (at
+// n < 2^26 the matrix stays within 2^24 counts); plans that still do not
+// (batches of thousands of jobs at widths of 18 and up, whose buckets alone
+// would need hundreds of GB) are refused.
+void sort_geometry(Plan& pl, const size_t* ns, uint32_t J, size_t mult) {
   const uint32_t bb = (uint32_t)pl.bb;
   uint32_t want = 0;
   while (want < 12 && (pl.max_n >> want) > SORT_PART_TARGET) ++want;
   const uint32_t hi_min = bb > 8 ? bb - 8 : 0;
   uint32_t hi = std::max<uint32_t>(want, hi_min);
   hi = std::min<uint32_t>(hi, std::min<uint32_t>(bb, 12));
+  auto groups = [&](uint32_t tpb) {
+    size_t gs = 0;
+    for (uint32_t j = 0; j < J; ++j) gs += (mult * ns[j] + (size_t)SORT_TILE * tpb - 1) / ((size_t)SORT_TILE * tpb);
+    return gs * (size_t)pl.W;
+  };
   const size_t two_level = (size_t)SCAN_ITEMS * SCAN_ITEMS;
-  while (hi > hi_min && (pl.tiles << hi) > two_level) --hi;
+  uint32_t tpb = std::max<uint32_t>(1u, (1u << hi) / 512u);
+  while (tpb < 64 && (groups(tpb) << hi) > two_level) tpb <<= 1;
+  while (hi > hi_min && (groups(tpb) << hi) > two_level) --hi;
   pl.hi_bits = hi;
   pl.lo_bits = bb - hi;
+  pl.tpb = tpb;
+  pl.tile_digits = SORT_TILE * tpb;
+  pl.tiles = groups(tpb);
   pl.ncounts = pl.tiles << hi;
   pl.nb = (pl.ncounts + SCAN_ITEMS - 1) / SCAN_ITEMS;
-  pl.nb2 = pl.nb > (size_t)SCAN_ITEMS ? (pl.nb + SCAN_ITEMS - 1) / SCAN_ITEMS : 0;
 }
 
 int launch_sort(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t st) {
@@ -677,7 +708,7 @@ int launch_sort(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t st) {
   uint2* tmp = ws_at<uint2>(ws, pl.o_tmp);
   uint32_t* key = ws_at<uint32_t>(ws, pl.o_key);
   uint32_t* idx = ws_at<uint32_t>(ws, pl.o_idx);
-  if (pl.lo_bits > 8 || pl.hi_bits > 12 || pl.nb2 > (size_t)SCAN_ITEMS) return MSM_EINVAL;
+  if (pl.lo_bits > 8 || pl.hi_bits > 12 || pl.nb > (size_t)SCAN_ITEMS) return MSM_EINVAL;
 
   SortGeom g;
   g.jv = job_view(pl, ws);
@@ -686,6 +717,7 @@ int launch_sort(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t st) {
   g.bb = (uint32_t)pl.bb;
   g.lo_bits = pl.lo_bits;
   g.hi_bits = pl.hi_bits;
+  g.tpb = pl.tpb;
   const uint32_t off = pl.encoding == MSM_DIGITS_UNSIGNED ? 0u : 1u;
 
   int rc;
@@ -695,16 +727,7 @@ int launch_sort(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t st) {
                                                         pl.encoding, digits, flags);
   k_part_count<<<(unsigned)pl.tiles, SORT_THREADS, 0, st>>>(g, off, digits, counts);
   k_scan_block<<<(unsigned)pl.nb, SCAN_THREADS, 0, st>>>(counts, pl.ncounts, blocksums);
-  if (pl.nb2 == 0) {
-    k_scan_top<<<1, SCAN_THREADS, 0, st>>>(blocksums, (uint32_t)pl.nb, total);
-  } else {
-    // three levels: the nb block sums are scanned in blocks, and their nb2
-    // sums by one block (the second-level sums follow the first's)
-    uint32_t* sums2 = blocksums + pl.nb;
-    k_scan_block<<<(unsigned)pl.nb2, SCAN_THREADS, 0, st>>>(blocksums, pl.nb, sums2);
-    k_scan_top<<<1, SCAN_THREADS, 0, st>>>(sums2, (uint32_t)pl.nb2, total);
-    k_scan_add<<<(unsigned)pl.nb2, SCAN_THREADS, 0, st>>>(blocksums, pl.nb, sums2);
-  }
+  k_scan_top<<<1, SCAN_THREADS, 0, st>>>(blocksums, (uint32_t)pl.nb, total);
   k_scan_add<<<(unsigned)pl.nb, SCAN_THREADS, 0, st>>>(counts, pl.ncounts, blocksums);
   const size_t scatter_lds = TILE * sizeof(uint2) + 2 * ((size_t)4 << pl.hi_bits);
   uint32_t* big = ws_at<uint32_t>(ws, pl.o_big);

@@ -154,27 +154,23 @@ bool make_plan(const size_t* ns, uint32_t J, int c_req, int encoding, Plan& pl,
   pl.J = J;
   // with the endomorphism split every input point contributes two points
   const size_t mult = encoding == MSM_DIGITS_GLV ? 2 : 1;
-  size_t tps_sum = 0;
   for (uint32_t j = 0; j < J; ++j) {
     if (ns[j] == 0 || ns[j] >= ((size_t)1 << 26)) return false;
     const size_t nv = mult * ns[j];
     pl.N += nv;
     pl.max_n = std::max(pl.max_n, nv);
-    tps_sum += (nv + SORT_TILE - 1) / SORT_TILE;
   }
   pl.S = (size_t)J * W;
   pl.M = pl.S << pl.bb;
   pl.NW = pl.N * (size_t)W;
-  pl.tiles = tps_sum * (size_t)W;
   // entry positions, keys (s 2^bb + m) and point indices are 32-bit words
-  if (pl.N >= ((size_t)1 << 31) || pl.NW >= ((size_t)1 << 31) || pl.M >= ((size_t)1 << 31) ||
-      pl.tiles >= ((size_t)1 << 31))
+  if (pl.N >= ((size_t)1 << 31) || pl.NW >= ((size_t)1 << 31) || pl.M >= ((size_t)1 << 31))
     return false;
-  sort_geometry(pl);
-  if (pl.lo_bits > 8 || pl.nb2 > 4096) return false;
+  sort_geometry(pl, ns, J, mult);
+  if (pl.lo_bits > 8 || pl.nb > 4096 || pl.tiles >= ((size_t)1 << 31)) return false;
   if (J == 1) {
     pl.one.n = (uint32_t)(mult * ns[0]);
-    pl.one.tps = (uint32_t)((mult * ns[0] + SORT_TILE - 1) / SORT_TILE);
+    pl.one.tps = (uint32_t)((mult * ns[0] + pl.tile_digits - 1) / pl.tile_digits);
   }
   // accumulation chunk: as many lanes as k_accum keeps resident in one
   // round (CUs x 4 SIMDs x 3 waves x 64 lanes; its register use allows 3
@@ -196,7 +192,7 @@ bool make_plan(const size_t* ns, uint32_t J, int c_req, int encoding, Plan& pl,
   pl.o_total = take(4);
   pl.o_offsets = take((pl.M + 1) * 4);
   pl.o_counts = take(pl.ncounts * 4);
-  pl.o_blocksums = take(std::max<size_t>(pl.nb + pl.nb2, 4096) * 4);
+  pl.o_blocksums = take(4096 * 4);
   pl.o_digits = take(pl.NW * 4);
   pl.o_tmp = take(pl.NW * 8);
   pl.o_key = take(pl.NW * 4 + 32);  // + 16-byte groups read past the end

@@ -132,7 +132,7 @@ int create(const msm_job* jobs, size_t njobs, int encoding, void* ws, size_t ws_
       d.n = (uint32_t)(encoding == MSM_DIGITS_GLV ? 2 * jb.n : jb.n);
       d.pt_off = pt_off;
       d.tile_off = tile_off;
-      d.tps = (uint32_t)((d.n + SORT_TILE - 1) / SORT_TILE);
+      d.tps = (uint32_t)((d.n + pl.tile_digits - 1) / pl.tile_digits);
       pt_off += d.n;
       tile_off += d.tps;
       const int64_t off = (int64_t)(jb.xyu - base_pts);

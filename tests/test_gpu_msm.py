@@ -196,19 +196,20 @@ def test_msm_full_size_closed_form(c):
 
 
 @pytest.mark.parametrize("n,c,enc", [
+    ((1 << 22), 16, api.MSM_DIGITS_GLV),
     ((1 << 23), 20, SIGNED),
     ((1 << 26) - 1, 16, api.MSM_DIGITS_GLV),
 ])
 def test_msm_large_jobs(n, c, enc):
-    """Jobs beyond the sizes whose sort partitions fit the LDS stage.
-    n = 2^23 with signed digits at c = 20: the count matrix (13 windows x 1024
-    tiles x 2^11 partitions) exceeds one two-level scan, so the scan takes a
-    third level.  n = 2^26 - 1, the largest job the interface takes, with
-    the endomorphism split at c' = 16: 2^30 - 16 digit slots (entry
-    positions, keys and indices are 32-bit words), a 2^7 x 2^8 split of the
-    bucket bits that keeps the count matrix within two scan levels, every
-    one of the 1024 sort partitions on the many-block path, and 5464-entry
-    accumulation chunks (device memory: about 50 GB).  k_i and s_i are drawn
+    """Jobs whose sort takes groups of tiles (one pass-1 histogram per group).
+    On a 256-CU device: n = 2^22 with the endomorphism split at c' = 16,
+    groups of 4 tiles and 2^11 partitions of ~4096 entries (LDS path);
+    n = 2^23 with signed digits at c = 20, groups of 4 tiles over 13 windows;
+    n = 2^26 - 1, the largest job the interface takes, with the split at
+    c' = 16: 2^30 - 16 digit slots (entry positions, keys and indices are
+    32-bit words), groups of 32 tiles, 2^12 partitions of ~32 K entries per
+    window, all on the many-block sort, and 5464-entry accumulation chunks
+    (device memory: about 50 GB).  k_i and s_i are drawn
     uniformly below 2^252 with numpy (no rejection step, which would take a
     minute at this size); the result is checked against the closed form,
     summed exactly with float64 digit products (oracle.msm.dot_mod_r)."""
