@@ -207,7 +207,11 @@ int msm_window_bits(int c, int encoding);
  * encoding.  Returns 0 for invalid arguments. */
 size_t msm_workspace_bytes(size_t n, int c, int encoding);
 
-/* Window width msm_run picks for n points when called with c = 0. */
+/* Window width msm_run picks for n points when called with c = 0 and signed
+ * or unsigned digits (a cost model: n W entries plus the aggregation of W
+ * windows of buckets, widths 4..20).  With the endomorphism split, c = 0
+ * picks from a model of its own (2n W entries of W = ceil(127 / c') windows):
+ * c' = 16 up to n ~ 2^21 and 19 (seven windows) above. */
 int msm_default_window(size_t n);
 
 /* Bucket accumulation (Sec. II-C), digits of c' = msm_window_bits(c,
@@ -228,7 +232,8 @@ int msm_bucket_accumulate(const uint32_t* xyu, const uint32_t* scalars, size_t n
                           void* stream);
 
 /* Full MSM: result = sum_i s_i P_i (Sec. II-C), Pippenger with window width
- * c (c = 0 picks msm_default_window(n)) and the given digit encoding.
+ * c (c = 0 picks msm_default_window(n), or the split digits' own choice)
+ * and the given digit encoding.
  * result: MSM_RESULT_WORDS device words: x[12], y[12] (Weierstrass affine,
  * ordinary form, canonical), inf (1 if the sum is the point at infinity, then
  * x = y = 0), flags (MSM_FLAG_RANGE).  Other arguments as for
@@ -263,7 +268,7 @@ int msm_run_noalloc(const uint32_t* xyu, const uint32_t* scalars, size_t n, int 
  *
  * msm_job: device pointers owned by the caller (prepared points, scalars,
  * MSM_RESULT_WORDS result words), n >= 1 points, window width c (0 = the
- * msm_default_window(n) choice), and the schedule (0 = the default for
+ * choice of msm_run with c = 0), and the schedule (0 = the default for
  * each): chunk, the digit entries one lane sums in bucket accumulation
  * (default: enough entries that one resident round of lanes covers the
  * class; every value is rounded up to a multiple of 4, at least 4);
@@ -318,7 +323,7 @@ int msm_batch_destroy(msm_batch* batch);
  *   priority; every request uses the given digit encoding.  *out receives the
  *   handle (host memory owned by the library).
  * msm_server_submit: queues one MSM (job as for msm_batch_create; c = 0
- *   picks msm_default_window(n)).  Its workspace (msm_workspace_bytes) is its
+ *   picks as msm_run does).  Its workspace (msm_workspace_bytes) is its
  *   footprint: it is admitted -- launched on the stream with the fewest
  *   requests in flight -- as soon as that much of the arena is free and no
  *   earlier request is still waiting (FIFO).  While fewer than three

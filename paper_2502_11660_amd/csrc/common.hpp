@@ -153,7 +153,8 @@ struct Plan {
 
 int num_windows(int c, int encoding);
 int window_bits(int c, int encoding);
-int default_window(size_t n);
+int default_window(size_t n);                     // signed-digit model (msm_default_window)
+int default_window_for(size_t n, int encoding);   // the width c = 0 picks for an encoding
 // schedule of a plan (0 = default for each; msm_job's chunk, tree_quad,
 // tree_wide)
 struct Schedule {

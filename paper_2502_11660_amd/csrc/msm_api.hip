@@ -111,12 +111,35 @@ int window_bits(int c, int encoding) {
 
 int default_window(size_t n) {
   // additions ~ n W (accumulation) + ~1.3 * 2^c W (signed-digit aggregation
-  // of 2^(c-1) buckets per window, merges included)
+  // of 2^(c-1) buckets per window, merges included); widths above 18 win
+  // from n ~ 2^23 on (n = 2^24: c = 20 measured 5% faster than 17)
   int best = 8;
   double best_cost = 1e300;
-  for (int c = 4; c <= 18; ++c) {
+  for (int c = 4; c <= 20; ++c) {
     double W = num_windows(c, MSM_DIGITS_SIGNED);
     double cost = (double)n * W + 1.3 * std::ldexp(1.0, c) * W;
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = c;
+    }
+  }
+  return best;
+}
+
+int default_window_for(size_t n, int encoding) {
+  if (encoding != MSM_DIGITS_GLV) return default_window(n);
+  // split digits: 2n W entries of W = ceil(127 / c') windows, and 2^(c'-1)
+  // buckets per window, each costing about as much as 3.9 entries (tree,
+  // merges and the sort's identity fill: fitted to the n = 2^20 width sweep).
+  // Measured picks: c' = 16 up to n ~ 2^21 (2^18: 18% faster than the
+  // signed model's 15), c' = 19 above (2^22: 3%, 2^24: 10% faster than 16).
+  int best = 16;
+  double best_cost = 1e300;
+  for (int c = 4; c <= 20; ++c) {
+    const double W = num_windows(c, MSM_DIGITS_GLV);
+    if (W == 0) continue;
+    const int cw = window_bits(c, MSM_DIGITS_GLV);
+    const double cost = 2.0 * (double)n * W + 3.9 * std::ldexp(1.0, cw - 1) * W;
     if (cost < best_cost) {
       best_cost = cost;
       best = c;
@@ -286,7 +309,7 @@ int msm_default_window(size_t n) { return default_window(n); }
 int msm_window_bits(int c, int encoding) { return window_bits(c, encoding); }
 
 size_t msm_workspace_bytes(size_t n, int c, int encoding) {
-  if (c == 0) c = default_window(n);
+  if (c == 0) c = default_window_for(n, encoding);
   Plan pl;
   if (!make_plan(&n, 1, c, encoding, pl)) return 0;
   return pl.bytes;
@@ -344,7 +367,7 @@ int msm_bucket_accumulate(const uint32_t* xyu, const uint32_t* scalars, size_t n
 int msm_run(const uint32_t* xyu, const uint32_t* scalars, size_t n, int c, int encoding,
             uint32_t* result, void* ws, size_t ws_bytes, void* stream) {
   if (!xyu || !scalars || !result || !ws) return MSM_EINVAL;
-  if (c == 0) c = default_window(n);
+  if (c == 0) c = default_window_for(n, encoding);
   Plan pl;
   if (!make_plan(&n, 1, c, encoding, pl)) return MSM_EINVAL;
   if (ws_bytes < pl.bytes) return MSM_ENOSPC;
@@ -357,7 +380,7 @@ int msm_run(const uint32_t* xyu, const uint32_t* scalars, size_t n, int c, int e
 int msm_run_noalloc(const uint32_t* xyu, const uint32_t* scalars, size_t n, int c, int encoding,
                     uint32_t* result, void* stream) {
   if (!xyu || !scalars || !result) return MSM_EINVAL;
-  if (c == 0) c = default_window(n);
+  if (c == 0) c = default_window_for(n, encoding);
   Plan pl;
   if (!make_plan(&n, 1, c, encoding, pl)) return MSM_EINVAL;
   if (pl.bytes > kScratchBytes) return MSM_ENOSPC;  // the MSM needs more than the scratch

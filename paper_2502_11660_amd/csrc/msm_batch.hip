@@ -54,7 +54,7 @@ bool classify(const msm_job* jobs, size_t njobs, int encoding, Classes& cls) {
     const msm_job& jb = jobs[i];
     if (!jb.xyu || !jb.scalars || !jb.result || jb.n == 0) return false;
     if (jb.chunk < 0 || jb.tree_quad < 0 || jb.tree_wide < 0) return false;
-    const int c = jb.c == 0 ? default_window(jb.n) : jb.c;
+    const int c = jb.c == 0 ? default_window_for(jb.n, encoding) : jb.c;
     if (num_windows(c, encoding) == 0) return false;
     cls[ClassKey(c, schedule_of(jb))].push_back(i);
   }

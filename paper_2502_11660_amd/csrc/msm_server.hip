@@ -236,7 +236,7 @@ int msm_server_submit(msm_server* s, const msm_job* job, void* stream, uint64_t*
   if (!s || !job || !ticket || !job->xyu || !job->scalars || !job->result) return MSM_EINVAL;
   Request r;
   r.job = *job;
-  const int c = job->c == 0 ? default_window(job->n) : job->c;
+  const int c = job->c == 0 ? default_window_for(job->n, s->encoding) : job->c;
   size_t n = job->n;
   Schedule sched;
   sched.chunk = job->chunk;
