@@ -145,6 +145,40 @@ def test_batch_64_jobs_log_uniform_sizes():
         off += n
 
 
+def test_batch_class_with_grouped_sort_tiles():
+    """One class (split digits, c = 16) holding a 2^22-point job, whose size
+    makes the sort's pass 1 take groups of 4 tiles, beside jobs of 3, 8193 and
+    100000 points (one group each, or a few): every job's group offset in the
+    job table follows the class's group size.  k_i and s_i uniform below
+    2^252; every result against the closed form."""
+    sizes = [1 << 22, 3, 8193, 100000]
+    ntot = sum(sizes)
+    rng = np.random.default_rng(inputs.config_seed(4) + 22)
+    kw = rng.integers(0, 1 << 32, size=(ntot, 8), dtype=np.uint32)
+    kw[:, 7] &= 0x0FFFFFFF
+    kw[:, 0] |= 1
+    sw = rng.integers(0, 1 << 32, size=(ntot, 8), dtype=np.uint32)
+    sw[:, 7] &= 0x0FFFFFFF
+    xy, inf = api.gen_points(_dev(kw), ntot)
+    xyu, status = api.points_prepare(xy, ntot, inf=inf, endo=True)
+    del xy, inf
+    s_dev = _dev(sw)
+    jobs, off = [], 0
+    for n in sizes:  # two records per point with the split
+        jobs.append((xyu[2 * off * 36:2 * (off + n) * 36], s_dev[off * 8:(off + n) * 8],
+                     api.words(api.MSM_RESULT_WORDS), n, 16))
+        off += n
+    b = api.Batch(jobs, encoding=api.MSM_DIGITS_GLV)
+    b.run()
+    torch.cuda.synchronize()
+    assert int(api.to_host(status)[0]) == 0
+    off = 0
+    for (x, s, res, n, c) in jobs:
+        assert _result(res) == (msm.closed_form_words(sw[off:off + n], kw[off:off + n]), 0), n
+        off += n
+    b.destroy()
+
+
 @pytest.mark.parametrize("sched", [{"chunk": 5}, {"chunk": 300}, {"tree_quad": 2048},
                                    {"tree_quad": 1 << 20, "tree_wide": 1},
                                    {"chunk": 7, "tree_quad": 16, "tree_wide": 4096}])
