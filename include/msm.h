@@ -225,7 +225,9 @@ int msm_default_window(size_t n);
  * multiple is the same point).  ws: device workspace of
  * ws_bytes >= msm_workspace_bytes(n, c, encoding); word 0 of ws receives the
  * status flags (MSM_FLAG_RANGE).
- * Errors: MSM_EINVAL (null, n = 0, n >= 2^26, c not in [1, 20] -- [2, 20]
+ * Errors: MSM_EINVAL (null, n = 0, n >= 2^26, 2^31 or more digit slots --
+ * n times the window count, twice that with the endomorphism split; e.g.
+ * widths below 8 at n near 2^26 -- c not in [1, 20] -- [2, 20]
  * for signed digits -- or an unknown encoding), MSM_ENOSPC, MSM_EHIP. */
 int msm_bucket_accumulate(const uint32_t* xyu, const uint32_t* scalars, size_t n, int c,
                           int encoding, uint32_t* buckets, void* ws, size_t ws_bytes,

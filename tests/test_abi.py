@@ -156,3 +156,31 @@ def test_window_helpers(lib):
     Job = _lib.MsmJob
     one = (Job * 1)(Job(16, 16, 16, 5000, 11))
     assert lib.msm_batch_workspace_bytes(one, 1, S) == lib.msm_workspace_bytes(5000, 11, S)
+
+
+def test_size_limits_plan_at_every_width(lib):
+    """Single MSMs plan up to the interface's n = 2^26 - 1 points at every
+    width and encoding whose digit slots (points x windows, twice the points
+    with the split) stay below 2^31 (entry positions are 32-bit words): the
+    sort groups tiles and splits the bucket bits so that its count matrix
+    fits the two-level scan.  n = 2^26 is refused.  The split digits' c = 0
+    choice is c' = 16 at n = 2^20 and c' = 19 from ~2^22 on; the signed
+    model's reaches c = 20 at 2^24."""
+    S, U, G = _lib.MSM_DIGITS_SIGNED, _lib.MSM_DIGITS_UNSIGNED, _lib.MSM_DIGITS_GLV
+    top = (1 << 26) - 1
+    planned = 0
+    for enc in (S, U, G):
+        for c in range(2, 21):
+            slots = (2 if enc == G else 1) * top * lib.msm_num_windows(c, enc)
+            b = lib.msm_workspace_bytes(top, c, enc)
+            if slots < (1 << 31):
+                assert 0 < b < (48 << 30), (enc, c)  # well inside one GPU's memory
+                planned += 1
+            else:
+                assert b == 0, (enc, c)
+            assert lib.msm_workspace_bytes(1 << 26, c, enc) == 0, (enc, c)
+    assert planned >= 3 * 12  # c = 8 .. 20 at least, in every encoding
+    assert lib.msm_default_window(1 << 24) == 20
+    assert lib.msm_workspace_bytes(1 << 20, 0, G) == lib.msm_workspace_bytes(1 << 20, 16, G)
+    assert lib.msm_workspace_bytes(1 << 24, 0, G) == lib.msm_workspace_bytes(1 << 24, 19, G)
+    assert lib.msm_workspace_bytes(1 << 24, 0, G) != lib.msm_workspace_bytes(1 << 24, 16, G)
