@@ -700,15 +700,17 @@ def host_to_device_leg(torch, xyu, xyu_endo, s_dev):
     return out
 
 
-def bucket_scatter_figure(phases_ms, entries, n):
+def bucket_scatter_figure(phases_ms, entries, n, records):
     """Algorithmic HBM bytes of the digit slicing and bucket sort at n points
     with `entries` digit slots (non-zero and zero digits alike are slotted),
     per the layout: 32 B of scalar read per point; per slot a 4-byte digit
-    written and read, an 8-byte (index, key) staging pair written and read,
+    written and read, a staging entry written and read (one 4-byte word for
+    jobs of at most 2^23 point records, else an 8-byte index and key pair),
     and the sorted key and index written (8 B); and the bytes the committed
     rocprofv3 counter summary measured for the sort phase's kernels, per
     slot, times these slots (null when the sort sources changed since)."""
-    nbytes = 32 * n + entries * (4 + 4 + 8 + 8 + 8)
+    staged = 4 if records <= (1 << 23) else 8
+    nbytes = 32 * n + entries * (4 + 4 + staged + staged + 8)
     ms = phases_ms.get("sort")
     out = {"algorithmic_bytes": nbytes, "phase_ms": ms,
            "GBps": nbytes / (ms * 1e-3) / 1e9 if ms else None,
@@ -986,7 +988,8 @@ def main():
         "config1": config1,
         "sweep": sweep_out,
         "phase_ms": phases,
-        "bucket_scatter": bucket_scatter_figure(phases, slots, n),
+        "bucket_scatter": bucket_scatter_figure(phases, slots, n,
+                                                (2 if best_enc == "glv" else 1) * n),
         "roofline": {
             "kernel": "k_accum (bucket accumulation, mixed PADD)",
             "bound": "alu",

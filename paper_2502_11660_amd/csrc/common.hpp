@@ -143,6 +143,7 @@ struct Plan {
   uint32_t lo_bits = 0, hi_bits = 0;  // split of the bb bucket bits in the sort
   uint32_t tpb = 1;                   // pass-1 tiles per block (one histogram per group)
   uint32_t tile_digits = SORT_TILE;   // digits per group, SORT_TILE tpb
+  bool tmp_packed = false;            // staged sort entries in one word (jobs <= 2^23 points)
   size_t ncounts = 0, nb = 0;         // sort count matrix size, its scan blocks
   JobDesc one{};  // the job when J = 1; otherwise one.xyu is the base of segment offsets
   // byte offsets into the workspace

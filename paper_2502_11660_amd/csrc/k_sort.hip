@@ -44,6 +44,32 @@ struct SortGeom {
   uint32_t tpb;  // pass-1 tiles per block: a block's group of tpb tiles shares one histogram
 };
 
+// Staged entries between the passes (tmp): the index word (point index |
+// sign << 31) and the bucket key, 8 bytes; or, for jobs of at most 2^23
+// points (PK), one word: index bits 0..22, the key's low (<= 8) bucket bits
+// at 23..30, the sign at 31.  Pass 2 and the many-block sort need only the
+// index word and the low bits (a partition's keys are its first bucket plus
+// the low bits), so the packed form loses nothing and halves the staging
+// traffic.
+template <bool PK>
+struct TmpEnt;
+template <>
+struct TmpEnt<false> {
+  using T = uint2;
+  __device__ static T make(uint32_t idxw, uint32_t key, uint32_t) { return make_uint2(idxw, key); }
+  __device__ static uint32_t lo(const T& e, uint32_t L) { return e.y & (L - 1); }
+  __device__ static uint32_t idx(const T& e) { return e.x; }
+};
+template <>
+struct TmpEnt<true> {
+  using T = uint32_t;
+  __device__ static T make(uint32_t idxw, uint32_t, uint32_t lo) {
+    return (idxw & 0x807fffffu) | (lo << 23);
+  }
+  __device__ static uint32_t lo(const T& e, uint32_t) { return (e >> 23) & 0xffu; }
+  __device__ static uint32_t idx(const T& e) { return e & 0x807fffffu; }
+};
+
 // largest j with key(j) <= x, for a key non-decreasing in j (J >= 1)
 template <typename F>
 __device__ __forceinline__ uint32_t find_job(uint32_t J, uint32_t x, F key) {
@@ -219,10 +245,11 @@ __device__ uint32_t lds_exclusive_scan(uint32_t* v, uint32_t n) {
 // LDS, so that consecutive threads write consecutive entries of each
 // partition's range; a partition's cursor (gstart) then moves past the
 // tile's entries for the next tile of the group.
+template <bool PK>
 __global__ void __launch_bounds__(SORT_THREADS) k_part_scatter(SortGeom g, uint32_t off,
                                                                const uint32_t* __restrict__ digits,
                                                                const uint32_t* __restrict__ scanned,
-                                                               uint2* __restrict__ tmp,
+                                                               typename TmpEnt<PK>::T* __restrict__ tmp,
                                                                uint32_t* __restrict__ clear0,
                                                                uint32_t* __restrict__ clear1) {
   // two list counters of later passes start at zero (the large-partition
@@ -280,7 +307,8 @@ __global__ void __launch_bounds__(SORT_THREADS) k_part_scatter(SortGeom g, uint3
     for (uint32_t k = threadIdx.x; k < count; k += SORT_THREADS) {
       const uint2 en = stage[k];
       const uint32_t pr = (en.y - keybase) >> g.lo_bits;
-      tmp[gstart[pr] + (k - lstart[pr])] = en;
+      tmp[gstart[pr] + (k - lstart[pr])] =
+          TmpEnt<PK>::make(en.x, en.y, (en.y - keybase) & ((1u << g.lo_bits) - 1));
     }
     if (g.tpb == 1) break;  // (a single tile needs no cursor update)
     __syncthreads();  // the stage and the local starts are read
@@ -316,9 +344,10 @@ __device__ __forceinline__ uint32_t part_bucket0(const SortGeom& g, uint32_t p) 
 // block); after the bucket histogram and its scan, every entry takes its place
 // in bucket order in LDS (index word and low bucket bits, 5 bytes an entry)
 // and the block writes the partition out linearly.
-template <uint32_t ROWS>
+template <uint32_t ROWS, bool PK>
 __device__ __forceinline__ void part_sort_rows(const SortGeom& g, uint32_t p, uint32_t start,
-                                               uint32_t size, const uint2* __restrict__ tmp,
+                                               uint32_t size,
+                                               const typename TmpEnt<PK>::T* __restrict__ tmp,
                                                uint32_t* __restrict__ key,
                                                uint32_t* __restrict__ idx,
                                                uint32_t* __restrict__ offsets,
@@ -327,7 +356,7 @@ __device__ __forceinline__ void part_sort_rows(const SortGeom& g, uint32_t p, ui
   const uint32_t L = 1u << g.lo_bits;
   if (threadIdx.x < 256) hist[threadIdx.x] = 0;
   __syncthreads();
-  uint2 ev[ROWS];
+  typename TmpEnt<PK>::T ev[ROWS];
   if (size > 0) {
     // all loads first (clamped, unconditional), so that they overlap
 #pragma unroll
@@ -337,7 +366,7 @@ __device__ __forceinline__ void part_sort_rows(const SortGeom& g, uint32_t p, ui
     }
 #pragma unroll
     for (uint32_t r = 0; r < ROWS; ++r)
-      if (r * SORT_THREADS + threadIdx.x < size) atomicAdd(&hist[ev[r].y & (L - 1)], 1u);
+      if (r * SORT_THREADS + threadIdx.x < size) atomicAdd(&hist[TmpEnt<PK>::lo(ev[r], L)], 1u);
   }
   __syncthreads();
   for (uint32_t lo = threadIdx.x; lo < L; lo += SORT_THREADS) cur[lo] = hist[lo];
@@ -355,9 +384,9 @@ __device__ __forceinline__ void part_sort_rows(const SortGeom& g, uint32_t p, ui
 #pragma unroll
     for (uint32_t r = 0; r < ROWS; ++r) {
       if (r * SORT_THREADS + threadIdx.x < size) {
-        const uint32_t lo = ev[r].y & (L - 1);
+        const uint32_t lo = TmpEnt<PK>::lo(ev[r], L);
         const uint32_t q = atomicAdd(&cur[lo], 1u);
-        out_idx[q] = ev[r].x;
+        out_idx[q] = TmpEnt<PK>::idx(ev[r]);
         out_lo[q] = (uint8_t)lo;
       }
     }
@@ -375,9 +404,10 @@ __device__ __forceinline__ void part_sort_rows(const SortGeom& g, uint32_t p, ui
 // k_big_* kernels sort it with many blocks.
 constexpr uint32_t SHORT_ROWS = 20;
 
+template <bool PK>
 __global__ void __launch_bounds__(SORT_THREADS) k_part_sort(
     SortGeom g, const uint32_t* __restrict__ scanned, const uint32_t* __restrict__ total_p,
-    size_t ncounts, const uint2* __restrict__ tmp, uint32_t* __restrict__ key,
+    size_t ncounts, const typename TmpEnt<PK>::T* __restrict__ tmp, uint32_t* __restrict__ key,
     uint32_t* __restrict__ idx, uint32_t* __restrict__ offsets, uint32_t* __restrict__ buckets,
     uint32_t* __restrict__ big) {
   __shared__ uint32_t out_idx[PART_CAP];  // index words in bucket order
@@ -394,11 +424,11 @@ __global__ void __launch_bounds__(SORT_THREADS) k_part_sort(
     return;
   }
   if (size <= SHORT_ROWS * SORT_THREADS)
-    part_sort_rows<SHORT_ROWS>(g, p, start, size, tmp, key, idx, offsets, buckets, out_idx, out_lo,
-                               hist, cur);
+    part_sort_rows<SHORT_ROWS, PK>(g, p, start, size, tmp, key, idx, offsets, buckets, out_idx,
+                                   out_lo, hist, cur);
   else
-    part_sort_rows<ROWS>(g, p, start, size, tmp, key, idx, offsets, buckets, out_idx, out_lo, hist,
-                         cur);
+    part_sort_rows<ROWS, PK>(g, p, start, size, tmp, key, idx, offsets, buckets, out_idx, out_lo,
+                             hist, cur);
 }
 
 // Large partitions, sorted by many blocks.  big[0] = their count n, big[1..n]
@@ -444,11 +474,12 @@ __global__ void __launch_bounds__(SORT_THREADS) k_big_plan(
 }
 
 // per item: histogram of the low bucket bits
+template <bool PK>
 __global__ void __launch_bounds__(SORT_THREADS) k_big_count(SortGeom g,
                                                             const uint32_t* __restrict__ big,
                                                             const uint32_t* __restrict__ desc,
                                                             const uint32_t* __restrict__ item_of,
-                                                            const uint2* __restrict__ tmp,
+                                                            const typename TmpEnt<PK>::T* __restrict__ tmp,
                                                             uint32_t* __restrict__ cnt) {
   __shared__ uint32_t hist[256];
   const uint32_t nbig = big[0];
@@ -465,11 +496,11 @@ __global__ void __launch_bounds__(SORT_THREADS) k_big_count(SortGeom g,
 #pragma unroll
     for (uint32_t r = 0; r < PER; ++r) {  // loads first, clamped (e1 > e0)
       const uint32_t k = e0 + r * SORT_THREADS + threadIdx.x;
-      kv[r] = tmp[start + (k < e1 ? k : e1 - 1)].y;
+      kv[r] = TmpEnt<PK>::lo(tmp[start + (k < e1 ? k : e1 - 1)], L);
     }
 #pragma unroll
     for (uint32_t r = 0; r < PER; ++r)
-      if (e0 + r * SORT_THREADS + threadIdx.x < e1) atomicAdd(&hist[kv[r] & (L - 1)], 1u);
+      if (e0 + r * SORT_THREADS + threadIdx.x < e1) atomicAdd(&hist[kv[r]], 1u);
     __syncthreads();
     for (uint32_t lo = threadIdx.x; lo < L; lo += SORT_THREADS)
       cnt[(size_t)item * 256 + lo] = hist[lo];
@@ -513,12 +544,13 @@ __global__ void __launch_bounds__(SORT_THREADS) k_big_scan(SortGeom g,
 }
 
 // per item: place its entries at the cursors
+template <bool PK>
 __global__ void __launch_bounds__(SORT_THREADS) k_big_scatter(SortGeom g,
                                                               const uint32_t* __restrict__ big,
                                                               const uint32_t* __restrict__ desc,
                                                               const uint32_t* __restrict__ item_of,
                                                               const uint32_t* __restrict__ cnt,
-                                                              const uint2* __restrict__ tmp,
+                                                              const typename TmpEnt<PK>::T* __restrict__ tmp,
                                                               uint32_t* __restrict__ key,
                                                               uint32_t* __restrict__ idx) {
   __shared__ uint32_t cur[256];
@@ -532,7 +564,7 @@ __global__ void __launch_bounds__(SORT_THREADS) k_big_scatter(SortGeom g,
     const uint32_t bucket0 = part_bucket0(g, p);
     for (uint32_t lo = threadIdx.x; lo < L; lo += SORT_THREADS) cur[lo] = cnt[(size_t)item * 256 + lo];
     constexpr uint32_t PER = BIG_CH / SORT_THREADS;
-    uint2 ev[PER];
+    typename TmpEnt<PK>::T ev[PER];
 #pragma unroll
     for (uint32_t r = 0; r < PER; ++r) {  // loads first, clamped (e1 > e0)
       const uint32_t k = e0 + r * SORT_THREADS + threadIdx.x;
@@ -542,10 +574,10 @@ __global__ void __launch_bounds__(SORT_THREADS) k_big_scatter(SortGeom g,
 #pragma unroll
     for (uint32_t r = 0; r < PER; ++r) {
       if (e0 + r * SORT_THREADS + threadIdx.x < e1) {
-        const uint32_t lo = ev[r].y & (L - 1);
+        const uint32_t lo = TmpEnt<PK>::lo(ev[r], L);
         const uint32_t pos = start + atomicAdd(&cur[lo], 1u);
         key[pos] = bucket0 + lo;
-        idx[pos] = ev[r].x;
+        idx[pos] = TmpEnt<PK>::idx(ev[r]);
       }
     }
     __syncthreads();
@@ -696,7 +728,36 @@ void sort_geometry(Plan& pl, const size_t* ns, uint32_t J, size_t mult) {
   pl.tiles = groups(tpb);
   pl.ncounts = pl.tiles << hi;
   pl.nb = (pl.ncounts + SCAN_ITEMS - 1) / SCAN_ITEMS;
+  // one-word staged entries: 23 index bits and 8 low bucket bits
+  pl.tmp_packed = pl.max_n <= ((size_t)1 << 23) && pl.lo_bits <= 8;
 }
+
+namespace {
+struct SortBufs {
+  uint32_t *digits, *counts, *total, *offsets, *key, *idx, *buckets;
+  uint32_t *big, *bigdesc, *bigcnt, *bigitem, *longlist;
+};
+
+// pass-1 scatter, pass 2 and the many-block sort, on staged entries of
+// either form
+template <bool PK>
+void sort_passes(const Plan& pl, const SortGeom& g, uint32_t off, const SortBufs& b,
+                 typename TmpEnt<PK>::T* tmp, size_t scatter_lds, hipStream_t st) {
+  k_part_scatter<PK><<<(unsigned)pl.tiles, SORT_THREADS, scatter_lds, st>>>(
+      g, off, b.digits, b.counts, tmp, b.big, b.longlist);
+  k_part_sort<PK><<<(unsigned)(pl.S << pl.hi_bits), SORT_THREADS, 0, st>>>(
+      g, b.counts, b.total, pl.ncounts, tmp, b.key, b.idx, b.offsets, b.buckets, b.big);
+  // large partitions (none for evenly spread digits: these return at once)
+  k_big_plan<<<1, SORT_THREADS, 0, st>>>(g, b.counts, b.total, pl.ncounts, b.big, b.bigdesc,
+                                         b.bigitem);
+  k_big_count<PK><<<BIG_GRID, SORT_THREADS, 0, st>>>(g, b.big, b.bigdesc, b.bigitem, tmp,
+                                                     b.bigcnt);
+  k_big_scan<<<BIG_GRID, SORT_THREADS, 0, st>>>(g, b.big, b.bigdesc, b.bigcnt, b.offsets,
+                                                b.buckets);
+  k_big_scatter<PK><<<BIG_GRID, SORT_THREADS, 0, st>>>(g, b.big, b.bigdesc, b.bigitem, b.bigcnt,
+                                                       tmp, b.key, b.idx);
+}
+}  // namespace
 
 int launch_sort(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t st) {
   uint32_t* flags = ws_at<uint32_t>(ws, pl.o_flags);
@@ -705,7 +766,6 @@ int launch_sort(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t st) {
   uint32_t* counts = ws_at<uint32_t>(ws, pl.o_counts);
   uint32_t* blocksums = ws_at<uint32_t>(ws, pl.o_blocksums);
   uint32_t* digits = ws_at<uint32_t>(ws, pl.o_digits);
-  uint2* tmp = ws_at<uint2>(ws, pl.o_tmp);
   uint32_t* key = ws_at<uint32_t>(ws, pl.o_key);
   uint32_t* idx = ws_at<uint32_t>(ws, pl.o_idx);
   if (pl.lo_bits > 8 || pl.hi_bits > 12 || pl.nb > (size_t)SCAN_ITEMS) return MSM_EINVAL;
@@ -730,20 +790,14 @@ int launch_sort(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t st) {
   k_scan_top<<<1, SCAN_THREADS, 0, st>>>(blocksums, (uint32_t)pl.nb, total);
   k_scan_add<<<(unsigned)pl.nb, SCAN_THREADS, 0, st>>>(counts, pl.ncounts, blocksums);
   const size_t scatter_lds = TILE * sizeof(uint2) + 2 * ((size_t)4 << pl.hi_bits);
-  uint32_t* big = ws_at<uint32_t>(ws, pl.o_big);
-  uint32_t* bigdesc = ws_at<uint32_t>(ws, pl.o_bigdesc);
-  uint32_t* bigcnt = ws_at<uint32_t>(ws, pl.o_bigcnt);
-  uint32_t* bigitem = ws_at<uint32_t>(ws, pl.o_bigitem);
-  k_part_scatter<<<(unsigned)pl.tiles, SORT_THREADS, scatter_lds, st>>>(
-      g, off, digits, counts, tmp, big, ws_at<uint32_t>(ws, pl.o_longlist));
-  k_part_sort<<<(unsigned)(pl.S << pl.hi_bits), SORT_THREADS, 0, st>>>(
-      g, counts, total, pl.ncounts, tmp, key, idx, offsets, buckets, big);
-  // large partitions (none for evenly spread digits: these return at once)
-  k_big_plan<<<1, SORT_THREADS, 0, st>>>(g, counts, total, pl.ncounts, big, bigdesc, bigitem);
-  k_big_count<<<BIG_GRID, SORT_THREADS, 0, st>>>(g, big, bigdesc, bigitem, tmp, bigcnt);
-  k_big_scan<<<BIG_GRID, SORT_THREADS, 0, st>>>(g, big, bigdesc, bigcnt, offsets, buckets);
-  k_big_scatter<<<BIG_GRID, SORT_THREADS, 0, st>>>(g, big, bigdesc, bigitem, bigcnt, tmp, key,
-                                                   idx);
+  SortBufs sb{digits, counts, total, offsets, key, idx, buckets,
+              ws_at<uint32_t>(ws, pl.o_big), ws_at<uint32_t>(ws, pl.o_bigdesc),
+              ws_at<uint32_t>(ws, pl.o_bigcnt), ws_at<uint32_t>(ws, pl.o_bigitem),
+              ws_at<uint32_t>(ws, pl.o_longlist)};
+  if (pl.tmp_packed)
+    sort_passes<true>(pl, g, off, sb, ws_at<uint32_t>(ws, pl.o_tmp), scatter_lds, st);
+  else
+    sort_passes<false>(pl, g, off, sb, ws_at<uint2>(ws, pl.o_tmp), scatter_lds, st);
   HIPCHK(hipGetLastError());
   return MSM_OK;
 }
