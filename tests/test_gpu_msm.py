@@ -195,6 +195,34 @@ def test_msm_full_size_closed_form(c):
         assert rows[i] == points.fixed_base_mul(ks[i])
 
 
+def test_msm_run_on_two_streams_at_once(oracle_pool):
+    """msm_run is reentrant given distinct workspaces: two MSMs of different
+    sizes and encodings, each on its own stream with its own workspace,
+    enqueued back to back with no synchronisation between them, both equal
+    to the closed form (and to the same calls made one at a time)."""
+    ks, pts = oracle_pool
+    npool = len(pts)
+    xs = _prepared(pts)
+    jobs = []
+    for t, (n, c, enc) in enumerate(((1 << 16, 13, SIGNED), (3 << 14, 11, UNSIGNED))):
+        sc = [inputs.words_to_int(r) for r in inputs.scalars_mod_r(8800 + t, n)]
+        jobs.append((n, c, enc, sc, xs.repeat(n // npool), _dev(H.scalar_words(sc)),
+                     api.workspace(n, c, enc), api.words(api.MSM_RESULT_WORDS)))
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for _ in range(3):
+        for st, (n, c, enc, sc, x, sd, ws, res) in zip(streams, jobs):
+            with torch.cuda.stream(st):
+                api.msm_run(x, sd, n, c, enc, result=res, ws=ws)
+    torch.cuda.synchronize()
+    for (n, c, enc, sc, x, sd, ws, res) in jobs:
+        sel_k = [ks[i % npool] for i in range(n)]
+        got, flags = api.decode_result(api.to_host(res))
+        assert flags == 0 and got == msm.closed_form(sc, sel_k), (n, c, enc)
+        alone = api.msm_run(x, sd, n, c, enc)
+        assert np.array_equal(api.to_host(alone), api.to_host(res)), (n, c, enc)
+
+
 @pytest.mark.parametrize("n,c,enc", [
     ((1 << 22), 16, api.MSM_DIGITS_GLV),
     ((1 << 23), 20, SIGNED),
