@@ -50,3 +50,40 @@ def test_noalloc_refuses_more_than_the_scratch(oracle_pool):
     sd = api.to_device(inputs.scalars_mod_r(9600, n))
     with pytest.raises(api.MSMError):
         api.msm_run_noalloc(xyu, sd, n, 16)
+
+
+def test_noalloc_under_graph_capture(oracle_pool):
+    """The callers the entry point is for include code under HIP graph
+    capture: msm_run_noalloc recorded once in a graph (torch.cuda.graph) and
+    replayed three times, new scalars copied into the captured scalar buffer
+    before each replay and the program's own work and synchronisation between
+    replays; every replay's result equals the closed form of its scalars and
+    msm_run's result for them."""
+    import torch
+    ks, pts = oracle_pool
+    npool = len(pts)
+    n, c, enc = 1 << 14, 0, api.MSM_DIGITS_SIGNED
+    xyu = _prepared(pts, False).repeat(n // npool)
+    sd = api.to_device(inputs.scalars_mod_r(9700, n))
+    res = api.words(api.MSM_RESULT_WORDS)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # first call on this GPU outside the capture
+        api.msm_run_noalloc(xyu, sd, n, c, enc, result=res)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        api.msm_run_noalloc(xyu, sd, n, c, enc, result=res)
+    kk = [ks[i % npool] for i in range(n)]
+    for rep in range(3):
+        sw = inputs.scalars_mod_r(9710 + rep, n)
+        sd.copy_(api.to_device(sw))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        ss = [inputs.words_to_int(r) for r in sw]
+        assert api.decode_result(api.to_host(res)) == (msm.closed_form(ss, kk), 0), rep
+        want = api.msm_run(xyu, sd, n, c, enc)
+        torch.cuda.synchronize()
+        assert np.array_equal(api.to_host(want), api.to_host(res)), rep
