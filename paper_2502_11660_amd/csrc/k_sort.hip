@@ -695,8 +695,9 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_add(uint32_t* __restrict_
 // SORT_PART_TARGET entries, at most 8 low bits (pass-2 histogram) and at most 12
 // high bits (pass-1 histogram).  Also the tile grouping and the count-matrix
 // size.  A pass-1 block takes a group of tpb tiles with one histogram: tpb =
-// 2^hi / 512 keeps about 16 entries per (group, partition) for uniform digits,
-// so that the scatter writes runs of 128 bytes and the count matrix (groups
+// 2^hi / (32 x staged entry bytes) keeps about 256 bytes of staged entries
+// per (group, partition) for uniform digits (64 one-word or 32 two-word
+// entries), so that the scatter writes long runs and the count matrix (groups
 // x 2^hi, which with single tiles grows with the square of the input) stays
 // small.  If the matrix still exceeds the two-level scan (SCAN_ITEMS^2
 // counts), groups grow to 64 tiles, then the split takes fewer high bits
@@ -718,7 +719,9 @@ void sort_geometry(Plan& pl, const size_t* ns, uint32_t J, size_t mult) {
     return gs * (size_t)pl.W;
   };
   const size_t two_level = (size_t)SCAN_ITEMS * SCAN_ITEMS;
-  uint32_t tpb = std::max<uint32_t>(1u, (1u << hi) / 512u);
+  // staged entry bytes: one word for jobs of at most 2^23 point records
+  const uint32_t sb = pl.max_n <= ((size_t)1 << 23) ? 4u : 8u;
+  uint32_t tpb = std::max<uint32_t>(1u, (1u << hi) / (32u * sb));
   while (tpb < 64 && (groups(tpb) << hi) > two_level) tpb <<= 1;
   while (hi > hi_min && (groups(tpb) << hi) > two_level) --hi;
   pl.hi_bits = hi;
