@@ -224,15 +224,18 @@ def test_msm_run_on_two_streams_at_once(oracle_pool):
 
 
 @pytest.mark.parametrize("n,c,enc", [
+    ((1 << 21) + 777, 16, api.MSM_DIGITS_GLV),
     ((1 << 22), 16, api.MSM_DIGITS_GLV),
     ((1 << 23), 20, SIGNED),
     ((1 << 26) - 1, 16, api.MSM_DIGITS_GLV),
 ])
 def test_msm_large_jobs(n, c, enc):
     """Jobs whose sort takes groups of tiles (one pass-1 histogram per group).
-    On a 256-CU device: n = 2^22 with the endomorphism split at c' = 16,
-    groups of 4 tiles and 2^11 partitions of ~4096 entries (LDS path);
-    n = 2^23 with signed digits at c = 20, groups of 4 tiles over 13 windows;
+    On a 256-CU device: n = 2^21 + 777 with the endomorphism split at c' = 16,
+    2^11 partitions a window and groups of 16 tiles, the last group of each
+    window holding only 1554 entries; n = 2^22 with the split at c' = 16,
+    groups of 16 tiles and 2^11 partitions of ~4096 entries (LDS path);
+    n = 2^23 with signed digits at c = 20, groups of 16 tiles over 13 windows;
     n = 2^26 - 1, the largest job the interface takes, with the split at
     c' = 16: 2^30 - 16 digit slots (entry positions, keys and indices are
     32-bit words), groups of 32 tiles, 2^12 partitions of ~32 K entries per
