@@ -147,7 +147,7 @@ def test_batch_64_jobs_log_uniform_sizes():
 
 def test_batch_class_with_grouped_sort_tiles():
     """One class (split digits, c = 16) holding a 2^22-point job, whose size
-    makes the sort's pass 1 take groups of 4 tiles, beside jobs of 3, 8193 and
+    makes the sort's pass 1 take groups of 16 tiles, beside jobs of 3, 8193 and
     100000 points (one group each, or a few): every job's group offset in the
     job table follows the class's group size.  k_i and s_i uniform below
     2^252; every result against the closed form."""
