@@ -137,7 +137,8 @@ struct Plan {
   size_t NW = 0;      // digits N W
   size_t tiles = 0;   // pass-1 sort tiles over all segments
   size_t chunks = 0;  // accumulation chunks
-  uint32_t K = 32;    // entries per accumulation chunk
+  uint32_t K = 32;    // entries per accumulation chunk (the first Kx chunks: K + 4)
+  uint32_t Kx = 0;    // accumulation chunks of K + 4 entries, before those of K
   uint64_t tree_quad = 65536;  // tree levels with fewer outputs run on quads
   uint64_t tree_wide = 1024;   // levels with at most this many outputs on wide units
   uint32_t lo_bits = 0, hi_bits = 0;  // split of the bb bucket bits in the sort

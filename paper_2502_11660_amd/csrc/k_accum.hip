@@ -39,6 +39,18 @@ __device__ __forceinline__ const uint32_t* entry_point(const uint32_t* __restric
   return pts + off + (int64_t)(e & 0x7fffffffu) * XYU_WORDS;
 }
 
+// Chunk ch of the sorted entries: the first X chunks hold K + 4 entries, the
+// rest K (both multiples of 4).
+__device__ __forceinline__ uint64_t chunk_start(uint32_t ch, uint32_t K, uint32_t X) {
+  return (uint64_t)ch * K + 4ull * (ch < X ? ch : X);
+}
+
+// the chunk holding entry e
+__device__ __forceinline__ uint32_t chunk_of(uint32_t e, uint32_t K, uint32_t X) {
+  const uint64_t longer = (uint64_t)X * (K + 4);
+  return e < longer ? (uint32_t)(e / (K + 4)) : X + (uint32_t)((e - longer) / K);
+}
+
 // One lane per chunk, on the carry-free 28-bit field form (curve28.hpp):
 // points are converted from their 12-word records as they are loaded, the
 // running sum stays in the 28-bit form and is converted back when it is
@@ -51,22 +63,24 @@ __global__ void __launch_bounds__(256) k_accum(const uint32_t* __restrict__ pts,
                                                  const uint32_t* __restrict__ key,
                                                  const uint32_t* __restrict__ idx,
                                                  const uint32_t* __restrict__ offsets, uint32_t M,
-                                                 uint32_t K, uint32_t* __restrict__ buckets,
+                                                 uint32_t K, uint32_t X,
+                                                 uint32_t* __restrict__ buckets,
                                                  uint32_t* __restrict__ head,
                                                  uint32_t* __restrict__ tail) {
   const uint32_t E1 = offsets[M];
   const uint32_t ch = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t s64 = (uint64_t)ch * K;
+  const uint64_t s64 = chunk_start(ch, K, X);
   if (s64 >= E1) return;
   const uint32_t s = (uint32_t)s64;
-  const uint32_t e = (uint32_t)(s64 + K < E1 ? s64 + K : E1);
+  const uint64_t e64 = s64 + K + (ch < X ? 4u : 0u);
+  const uint32_t e = (uint32_t)(e64 < E1 ? e64 : E1);
 
   uint32_t cur = key[s];
   const bool open_left = (s > 0) && (key[s - 1] == cur);
   bool first_seg = true;
   xytz28 acc = pt28_identity();
-  // Keys and indices are read four at a time with 16-byte loads (K is a
-  // multiple of 4, so a chunk starts on a 16-byte boundary; the arrays carry
+  // Keys and indices are read four at a time with 16-byte loads (chunk
+  // lengths are multiples of 4, so a chunk starts on a 16-byte boundary; the arrays carry
   // 32 bytes of padding for a last group that ends past E1).  A lane's
   // 128-byte line of keys would otherwise be fetched again for every entry:
   // the point gathers of all resident waves evict it between iterations.
@@ -121,17 +135,19 @@ __global__ void __launch_bounds__(256) k_accum(const uint32_t* __restrict__ pts,
 // chunk ch holds a tail partial: returns true, the bucket and its last chunk
 __device__ __forceinline__ bool tail_of(const uint32_t* __restrict__ key,
                                         const uint32_t* __restrict__ offsets, uint32_t E1,
-                                        uint32_t K, uint32_t ch, uint32_t& b, uint32_t& c1) {
-  const uint64_t s64 = (uint64_t)ch * K;
+                                        uint32_t K, uint32_t X, uint32_t ch, uint32_t& b,
+                                        uint32_t& c1) {
+  const uint64_t s64 = chunk_start(ch, K, X);
   if (s64 >= E1) return false;
   const uint32_t s = (uint32_t)s64;
-  const uint32_t e = (uint32_t)(s64 + K < E1 ? s64 + K : E1);
+  const uint64_t e64 = s64 + K + (ch < X ? 4u : 0u);
+  const uint32_t e = (uint32_t)(e64 < E1 ? e64 : E1);
   const uint32_t last = key[e - 1];
   if (!(e < E1 && key[e] == last)) return false;          // last piece ends here
   if (s > 0 && key[s - 1] == key[s] && key[s] == last)     // whole chunk is a middle piece
     return false;
   b = last;
-  c1 = (offsets[b + 1] - 1) / K;
+  c1 = chunk_of(offsets[b + 1] - 1, K, X);
   return true;
 }
 
@@ -142,7 +158,7 @@ __device__ __forceinline__ bool tail_of(const uint32_t* __restrict__ key,
 // wholly idle waves leave at once.
 __global__ void __launch_bounds__(256) k_merge_small(const uint32_t* __restrict__ key,
                                                      const uint32_t* __restrict__ offsets,
-                                                     uint32_t M, uint32_t K,
+                                                     uint32_t M, uint32_t K, uint32_t X,
                                                      const uint32_t* __restrict__ head,
                                                      const uint32_t* __restrict__ tail,
                                                      uint32_t* __restrict__ buckets,
@@ -155,7 +171,7 @@ __global__ void __launch_bounds__(256) k_merge_small(const uint32_t* __restrict_
   const uint32_t E1 = offsets[M];
   const uint32_t ch = blockIdx.x * blockDim.x + tid;
   uint32_t b = 0, c1 = 0;
-  const bool has = tail_of(key, offsets, E1, K, ch, b, c1);
+  const bool has = tail_of(key, offsets, E1, K, X, ch, b, c1);
   const uint32_t span = has ? c1 - ch : 0u;
   if (has && span > SMALL_SPAN) {
     const uint32_t slot = atomicAdd(&longlist[0], 1u);
@@ -169,8 +185,9 @@ __global__ void __launch_bounds__(256) k_merge_small(const uint32_t* __restrict_
   const uint32_t n1 = cnt[0], n2 = cnt[1];
   if (!(tid < n1 || tid >= 256 - n2)) return;
   const uint32_t c = task[tid];
-  const uint32_t bk = key[(c + 1) * K - 1];  // the tail's bucket ends after chunk c
-  const uint32_t sp = (offsets[bk + 1] - 1) / K - c;
+  // the tail's bucket ends after chunk c
+  const uint32_t bk = key[(uint32_t)chunk_start(c + 1, K, X) - 1];
+  const uint32_t sp = chunk_of(offsets[bk + 1] - 1, K, X) - c;
   xytz28 acc = pt28_from(ld_xytz(tail + (size_t)c * XYTZ_WORDS));
   for (uint32_t j = 1; j <= sp; ++j)
     acc = padd28_full(acc, pt28_from(ld_xytz(head + (size_t)(c + j) * XYTZ_WORDS)));
@@ -187,7 +204,7 @@ __global__ void __launch_bounds__(256) k_merge_small(const uint32_t* __restrict_
 constexpr int LONG_THREADS = 128;
 __global__ void __launch_bounds__(LONG_THREADS) k_merge_long(const uint32_t* __restrict__ key,
                                                              const uint32_t* __restrict__ offsets,
-                                                             uint32_t K,
+                                                             uint32_t K, uint32_t X,
                                                              const uint32_t* __restrict__ head,
                                                              const uint32_t* __restrict__ tail,
                                                              uint32_t* __restrict__ buckets,
@@ -196,9 +213,10 @@ __global__ void __launch_bounds__(LONG_THREADS) k_merge_long(const uint32_t* __r
   const uint32_t count = longlist[0];
   for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
     const uint32_t ch = longlist[1 + item];
-    const uint32_t e_last = (ch + 1) * K - 1;  // the tail's bucket ends after this chunk
+    // the tail's bucket ends after this chunk
+    const uint32_t e_last = (uint32_t)chunk_start(ch + 1, K, X) - 1;
     const uint32_t b = key[e_last];
-    const uint32_t c1 = (offsets[b + 1] - 1) / K;
+    const uint32_t c1 = chunk_of(offsets[b + 1] - 1, K, X);
     const uint32_t span = c1 - ch;
     const uint32_t nact = span < (uint32_t)LONG_THREADS ? span : (uint32_t)LONG_THREADS;
     if (threadIdx.x < nact) {
@@ -238,27 +256,28 @@ int launch_accumulate(const Plan& pl, uint32_t* buckets, void* ws, hipStream_t s
   uint32_t* tail = ws_at<uint32_t>(ws, pl.o_tail);
   uint32_t* longlist = ws_at<uint32_t>(ws, pl.o_longlist);
   const int64_t* segoff = pl.J == 1 ? nullptr : ws_at<const int64_t>(ws, pl.o_segoff);
-  const uint32_t K = pl.K, M = (uint32_t)pl.M;
+  const uint32_t K = pl.K, X = pl.Kx, M = (uint32_t)pl.M;
   const unsigned grid = grid_for(pl.chunks, 256);
   // longlist[0] was cleared by the digit sort's scatter pass
   hipEvent_t ea = nullptr, eb = nullptr;
   if (prof_kernel_events(PT_ACCUM, st, &ea, &eb)) {
     // timed by events attached to the dispatch itself
     hipExtLaunchKernelGGL(k_accum, dim3(grid), dim3(256), 0, st, ea, eb, 0, pl.one.xyu, segoff,
-                          (uint32_t)pl.bb, key, idx, offsets, M, K, buckets, head, tail);
+                          (uint32_t)pl.bb, key, idx, offsets, M, K, X, buckets, head, tail);
     prof_kernel_record(PT_ACCUM, ea, eb);
   } else {
     ProfScope prof(PT_ACCUM, st);
     k_accum<<<grid, 256, 0, st>>>(pl.one.xyu, segoff, (uint32_t)pl.bb, key, idx, offsets, M, K,
-                                  buckets, head, tail);
+                                  X, buckets, head, tail);
   }
   ProfScope prof(PT_MERGE, st);
-  k_merge_small<<<grid, 256, 0, st>>>(key, offsets, M, K, head, tail, buckets, longlist);
+  k_merge_small<<<grid, 256, 0, st>>>(key, offsets, M, K, X, head, tail, buckets, longlist);
   // a block per possible entry (at most chunks / SMALL_SPAN), capped: the
   // common empty list then costs one short wave per block
   const unsigned long_grid =
       (unsigned)std::min<size_t>(2048, std::max<size_t>(1, pl.chunks / SMALL_SPAN));
-  k_merge_long<<<long_grid, LONG_THREADS, 0, st>>>(key, offsets, K, head, tail, buckets, longlist);
+  k_merge_long<<<long_grid, LONG_THREADS, 0, st>>>(key, offsets, K, X, head, tail, buckets,
+                                                    longlist);
   HIPCHK(hipGetLastError());
   return MSM_OK;
 }

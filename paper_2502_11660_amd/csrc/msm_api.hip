@@ -195,15 +195,28 @@ bool make_plan(const size_t* ns, uint32_t J, int c_req, int encoding, Plan& pl,
     pl.one.n = (uint32_t)(mult * ns[0]);
     pl.one.tps = (uint32_t)((mult * ns[0] + pl.tile_digits - 1) / pl.tile_digits);
   }
-  // accumulation chunk: as many lanes as k_accum keeps resident in one
-  // round (CUs x 4 SIMDs x 3 waves x 64 lanes; its register use allows 3
-  // waves per SIMD), so that every lane runs exactly once and no second,
-  // mostly idle round follows; at least 16 entries per chunk
+  // accumulation chunks: one per lane k_accum keeps resident in one round
+  // (CUs x 4 SIMDs x 3 waves x 64 lanes; its register use allows 3 waves per
+  // SIMD), so that every lane runs exactly once and no second, mostly idle
+  // round follows; at least 16 entries per chunk.  Chunk lengths are
+  // multiples of 4 (every chunk starts on a 16-byte boundary): Kx chunks of
+  // K + 4 entries, then chunks of K, with K the multiple of 4 below the
+  // average, so that the lanes' work differs by at most 4 entries instead of
+  // all lanes taking the average rounded up to a multiple of 4 and some lanes
+  // none.  A schedule's chunk gives every chunk the same length.
   const size_t lanes = (size_t)device_cus() * 4 * 3 * 64;
-  pl.K = sched.chunk ? (uint32_t)std::max(4, sched.chunk)
-                     : (uint32_t)std::max<size_t>(16, (pl.NW + lanes - 1) / lanes);
-  pl.K = (pl.K + 3u) & ~3u;  // a multiple of 4: chunks start on 16-byte boundaries
-  pl.chunks = (pl.NW + pl.K - 1) / pl.K;
+  if (sched.chunk) {
+    pl.K = ((uint32_t)std::max(4, sched.chunk) + 3u) & ~3u;
+    pl.Kx = 0;
+  } else {
+    const size_t k0 = std::max<size_t>(16, (pl.NW / lanes) & ~(size_t)3);
+    pl.K = (uint32_t)k0;
+    pl.Kx = pl.NW > k0 * lanes ? (uint32_t)((pl.NW - k0 * lanes + 3) / 4) : 0u;
+  }
+  {
+    const size_t longer = (size_t)pl.Kx * (pl.K + 4);
+    pl.chunks = pl.Kx + (pl.NW > longer ? (pl.NW - longer + pl.K - 1) / pl.K : 0);
+  }
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
