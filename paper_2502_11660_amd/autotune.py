@@ -52,8 +52,10 @@ def n_bucket(n):
 
 
 def default_chunk(total_entries, cus=256):
-    """The library's default accumulation chunk for a class with this many
-    digit entries (one resident round of 256 CUs x 4 SIMDs x 3 waves x 64)."""
+    """The average length of the library's default accumulation chunks for a
+    class with this many digit entries: one chunk per lane of a resident
+    round (256 CUs x 4 SIMDs x 3 waves x 64), at least 16 entries; the
+    library splits that into lengths K and K + 4 (multiples of 4)."""
     lanes = cus * 4 * 3 * 64
     return max(16, -(-int(total_entries) // lanes))
 
